@@ -1,0 +1,276 @@
+/*
+ * ORACLE - test infrastructure only.
+ *
+ * A plain, slow, FP64 CPU implementation of wire-scan depth reconstruction,
+ * used by the tests, the smoke check and the benchmark's CPU baseline to
+ * check the GPU library.  It shares no code, header, table or helper with the
+ * GPU path, and the product never calls it.
+ *
+ * What it computes (paper Sec. I and Sec. III-C: the per-pixel reconstruction
+ * takes the intensity difference at each pixel between consecutive wire
+ * positions and adds the differences into depth arrays; the paper defers the
+ * geometry to the differential-aperture method it cites, so the geometry below
+ * is the reading written down with the tests):
+ *
+ *   frame      um, beam along +z through x = y = 0, depth = z; the wire axis is
+ *              x, so only (y, z) projections matter.
+ *   pixel      P = (origin + i*u) + j*v for column i and row j, or an explicit
+ *              per-pixel table.
+ *   depth      for pixel P, wire centre C_k and radius r, the ray from P that is
+ *              tangent to the wire on side s (+1: the +z side) meets the beam at
+ *                d = Cz - (Cy*tz + s*r*L2) / ty
+ *              with a = C - P, L2 = |a|^2, kk = sqrt(L2 - r^2),
+ *              tz = az*kk - ay*s*r, ty = ay*kk + az*s*r.
+ *   edge       s_p = +1 when that +z-side depth moves toward +z over the scan
+ *              (last step vs first step), else -1; the leading edge uses s_p.
+ *   binning    u_k = (d_k - e0) * (1/width), e0 = first_center - width/2.
+ *              For k = 0..N-2 the difference dI_k = I_k - I_{k+1} is spread
+ *              over [lo, hi] = [min, max](u_k, u_{k+1}): bin b gets
+ *              dI_k * ov/len with ov = min(hi, b+1) - max(lo, b) > 0 and
+ *              len = hi - lo; parts outside [0, n_bins) are dropped; a
+ *              zero-length interval puts dI_k into bin floor(lo).
+ *   totals     tot[b] = sum over pixels of out[b][p].
+ *
+ * Every operation is one IEEE binary64 operation in the order written; build
+ * with -ffp-contract=off.  Pins (tests/test_oracle_*.py): the tangent depth
+ * against a similar-triangles closed form, the zero-radius line intersection,
+ * bisection on an independent occlusion predicate and mirror symmetry; the
+ * binning against hand-computed profiles and intensity conservation; the
+ * whole chain against brute-force sub-sampled ray integration and against
+ * depths planted by the forward model.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORACLE_OK 0
+#define ORACLE_EINVAL (-1)
+
+/* Depth at which the ray from (py, pz), tangent to the wire disc centred at
+ * (cy, cz) on side s, meets the beam.  Returns NAN when the pixel is inside
+ * the disc. */
+double oracle_tangent_depth(double py, double pz, double cy, double cz, double r, int s)
+{
+    double sr = (double)s * r;
+    double ay = cy - py;
+    double az = cz - pz;
+    double L2 = az * az + ay * ay;
+    double q = L2 - r * r;
+    if (!(q > 0.0)) return NAN;
+    double kk = sqrt(q);
+    double tz = az * kk - ay * sr;
+    double ty = ay * kk + az * sr;
+    return cz - (cy * tz + sr * L2) / ty;
+}
+
+/* Leading-edge side for one pixel: +1 when the +z tangent depth grows from the
+ * first to the last wire position, else -1. */
+int oracle_edge_sign(double py, double pz, int n_steps, const double* centers, double r)
+{
+    double d0 = oracle_tangent_depth(py, pz, centers[1], centers[2], r, +1);
+    double d1 = oracle_tangent_depth(py, pz, centers[3 * (n_steps - 1) + 1],
+                                     centers[3 * (n_steps - 1) + 2], r, +1);
+    return (d1 > d0) ? +1 : -1;
+}
+
+static void pixel_center(int nx, const double* origin, const double* u, const double* v,
+                         const double* pixel_xyz, int64_t p, double* py, double* pz)
+{
+    if (pixel_xyz) {
+        *py = pixel_xyz[3 * p + 1];
+        *pz = pixel_xyz[3 * p + 2];
+        return;
+    }
+    double i = (double)(p % nx);
+    double j = (double)(p / nx);
+    *py = (origin[1] + i * u[1]) + j * v[1];
+    *pz = (origin[2] + i * u[2]) + j * v[2];
+}
+
+static int32_t floor_to_i32(double x)
+{
+    double f = floor(x);
+    if (f < -2147483648.0) return INT32_MIN;
+    if (f > 2147483647.0) return INT32_MAX;
+    return (int32_t)f;
+}
+
+/* Positions u_k of the leading edge in bin units for one pixel.  Returns
+ * ORACLE_EINVAL if the pixel is inside the wire or a value is not finite. */
+static int pixel_positions(double py, double pz, int n_steps, const double* centers, double r,
+                           double e0, double invw, double* u)
+{
+    int s = oracle_edge_sign(py, pz, n_steps, centers, r);
+    for (int k = 0; k < n_steps; ++k) {
+        double d = oracle_tangent_depth(py, pz, centers[3 * k + 1], centers[3 * k + 2], r, s);
+        u[k] = (d - e0) * invw;
+        if (!isfinite(u[k])) return ORACLE_EINVAL;
+    }
+    return ORACLE_OK;
+}
+
+/* Spread the intensity differences of one pixel over the depth bins.
+ *   u      [n_steps] leading-edge positions in bin units
+ *   I      [n_steps] intensities (counts), read as doubles
+ *   out    [n_bins] accumulated in place (caller zeroes it)
+ *   stride distance between consecutive bins of out */
+void oracle_bin_profile(const double* u, const double* I, int n_steps, int n_bins,
+                        double* out, int64_t stride)
+{
+    for (int k = 0; k + 1 < n_steps; ++k) {
+        double dI = I[k] - I[k + 1];
+        double lo = u[k] < u[k + 1] ? u[k] : u[k + 1];
+        double hi = u[k] < u[k + 1] ? u[k + 1] : u[k];
+        double len = hi - lo;
+        if (len > 0.0) {
+            double first = floor(lo), last = floor(hi);
+            if (first < 0.0) first = 0.0;
+            if (last > (double)(n_bins - 1)) last = (double)(n_bins - 1);
+            for (double bd = first; bd <= last; bd += 1.0) {
+                double top = hi < bd + 1.0 ? hi : bd + 1.0;
+                double bot = lo > bd ? lo : bd;
+                double ov = top - bot;
+                if (ov > 0.0) out[(int64_t)bd * stride] += dI * (ov / len);
+            }
+        } else {
+            double bd = floor(lo);
+            if (bd >= 0.0 && bd < (double)n_bins) out[(int64_t)bd * stride] += dI;
+        }
+    }
+}
+
+/*
+ * Full reconstruction of detector rows [row0, row0 + nrows).
+ *   images  [n_steps][ny][nx] uint16, step slowest
+ *   out     [n_bins][nrows][nx] FP64, overwritten
+ *   totals  [n_bins] FP64 sums over the processed pixels, or NULL
+ *   bins    [nrows*nx][n_steps] int32 floor(u_k), or NULL
+ * Returns ORACLE_OK or ORACLE_EINVAL.
+ */
+int oracle_reconstruct(int nx, int ny, const double* origin, const double* u, const double* v,
+                       const double* pixel_xyz, double radius, int n_steps, const double* centers,
+                       int n_bins, double first_center, double width, const uint16_t* images,
+                       int row0, int nrows, double* out, double* totals, int32_t* bins,
+                       int nthreads)
+{
+    if (nx <= 0 || ny <= 0 || n_steps < 2 || n_bins <= 0 || !(width > 0.0) || !(radius > 0.0))
+        return ORACLE_EINVAL;
+    if (row0 < 0 || nrows < 0 || row0 + nrows > ny) return ORACLE_EINVAL;
+    const double e0 = first_center - width / 2.0;
+    const double invw = 1.0 / width;
+    const int64_t plane_in = (int64_t)nx * ny;
+    const int64_t plane_out = (int64_t)nx * nrows;
+    memset(out, 0, sizeof(double) * (size_t)plane_out * (size_t)n_bins);
+    int status = ORACLE_OK;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+
+#pragma omp parallel
+    {
+        double* uk = (double*)malloc(sizeof(double) * (size_t)n_steps);
+        double* Ik = (double*)malloc(sizeof(double) * (size_t)n_steps);
+#pragma omp for schedule(dynamic, 1)
+        for (int jr = 0; jr < nrows; ++jr) {
+            for (int i = 0; i < nx; ++i) {
+                int64_t p = (int64_t)(row0 + jr) * nx + i;
+                int64_t q = (int64_t)jr * nx + i;
+                double py, pz;
+                pixel_center(nx, origin, u, v, pixel_xyz, p, &py, &pz);
+                if (pixel_positions(py, pz, n_steps, centers, radius, e0, invw, uk) != ORACLE_OK) {
+#pragma omp atomic write
+                    status = ORACLE_EINVAL;
+                    continue;
+                }
+                if (bins)
+                    for (int k = 0; k < n_steps; ++k) bins[q * n_steps + k] = floor_to_i32(uk[k]);
+                for (int k = 0; k < n_steps; ++k) Ik[k] = (double)images[(int64_t)k * plane_in + p];
+                oracle_bin_profile(uk, Ik, n_steps, n_bins, out + q, plane_out);
+            }
+        }
+        free(uk);
+        free(Ik);
+    }
+    if (status != ORACLE_OK) return status;
+    if (totals) {
+        for (int b = 0; b < n_bins; ++b) {
+            double t = 0.0;
+            for (int64_t q = 0; q < plane_out; ++q) t += out[(int64_t)b * plane_out + q];
+            totals[b] = t;
+        }
+    }
+    return ORACLE_OK;
+}
+
+/*
+ * Reconstruction of an explicit list of pixels (flat indices j*nx + i), for
+ * sampled checks of large scans.  Intensities come from `images`
+ * ([n_steps][ny][nx]) or, when `series` is not NULL, from series[n][n_steps]
+ * (the time series of the n-th listed pixel).
+ *   out   [npix][n_bins] FP64 profile of each listed pixel
+ *   bins  [npix][n_steps] int32 floor(u_k), or NULL
+ *   upos  [npix][n_steps] FP64 u_k, or NULL
+ */
+int oracle_reconstruct_pixels(int nx, int ny, const double* origin, const double* u,
+                              const double* v, const double* pixel_xyz, double radius,
+                              int n_steps, const double* centers, int n_bins,
+                              double first_center, double width, const uint16_t* images,
+                              const uint16_t* series, const int64_t* pixels, int64_t npix,
+                              double* out, int32_t* bins,
+                              double* upos, int nthreads)
+{
+    if (nx <= 0 || ny <= 0 || n_steps < 2 || n_bins <= 0 || !(width > 0.0) || !(radius > 0.0))
+        return ORACLE_EINVAL;
+    const double e0 = first_center - width / 2.0;
+    const double invw = 1.0 / width;
+    const int64_t plane_in = (int64_t)nx * ny;
+    int status = ORACLE_OK;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel
+    {
+        double* uk = (double*)malloc(sizeof(double) * (size_t)n_steps);
+        double* Ik = (double*)malloc(sizeof(double) * (size_t)n_steps);
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t n = 0; n < npix; ++n) {
+            int64_t p = pixels[n];
+            double* o = out + n * n_bins;
+            for (int b = 0; b < n_bins; ++b) o[b] = 0.0;
+            if (p < 0 || p >= plane_in) {
+#pragma omp atomic write
+                status = ORACLE_EINVAL;
+                continue;
+            }
+            double py, pz;
+            pixel_center(nx, origin, u, v, pixel_xyz, p, &py, &pz);
+            if (pixel_positions(py, pz, n_steps, centers, radius, e0, invw, uk) != ORACLE_OK) {
+#pragma omp atomic write
+                status = ORACLE_EINVAL;
+                continue;
+            }
+            if (bins)
+                for (int k = 0; k < n_steps; ++k) bins[n * n_steps + k] = floor_to_i32(uk[k]);
+            if (upos)
+                for (int k = 0; k < n_steps; ++k) upos[n * n_steps + k] = uk[k];
+            if (series) {
+                for (int k = 0; k < n_steps; ++k) Ik[k] = (double)series[n * n_steps + k];
+                oracle_bin_profile(uk, Ik, n_steps, n_bins, o, 1);
+            } else if (images) {
+                for (int k = 0; k < n_steps; ++k) Ik[k] = (double)images[(int64_t)k * plane_in + p];
+                oracle_bin_profile(uk, Ik, n_steps, n_bins, o, 1);
+            }
+        }
+        free(uk);
+        free(Ik);
+    }
+    return status;
+}

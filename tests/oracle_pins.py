@@ -1,0 +1,299 @@
+"""Pins of the FP64 oracle to facts other than itself.
+
+Each function takes an oracle library handle (so the mutation test can run the
+same checks against a copy of the oracle with a planted mistake) and raises
+AssertionError when the pin does not hold.
+
+Independent facts used:
+* similar triangles when the pixel is level with the wire centre;
+* the zero-radius limit: the ray through the wire centre, a textbook
+  line-line intersection;
+* bisection on an occlusion predicate (distance from the wire centre to the
+  source-pixel segment), written here and never using the tangent formula;
+* mirror symmetry about the horizontal line through the wire centre;
+* hand-computed bin profiles;
+* intensity conservation (sum over bins equals first minus last count);
+* brute-force sub-sampled ray integration;
+* depths planted by the forward model.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+import oracle
+import synth
+
+# ------------------------------------------------------------------ helpers
+
+
+def seg_dist(cy, cz, zs, py, pz):
+    """Distance (y, z projection) from (cy, cz) to the segment (0, zs)-(py, pz)."""
+    dy, dz = py, pz - zs
+    wy, wz = cy, cz - zs
+    t = (wy * dy + wz * dz) / (dy * dy + dz * dz)
+    t = min(1.0, max(0.0, t))
+    return math.hypot(wy - t * dy, wz - t * dz)
+
+
+def seg_dist_vec(cy, cz, zs: np.ndarray, py, pz) -> np.ndarray:
+    dy = py
+    dz = pz - zs
+    wy = cy
+    wz = cz - zs
+    t = np.clip((wy * dy + wz * dz) / (dy * dy + dz * dz), 0.0, 1.0)
+    return np.hypot(wy - t * dy, wz - t * dz)
+
+
+def random_geometries(n, seed):
+    """Random pixel/wire placements spanning the workloads' ranges (um)."""
+    rng = np.random.default_rng(seed)
+    py = rng.uniform(2.0e5, 8.0e5, n)
+    pz = rng.uniform(-3.0e5, 3.0e5, n)
+    cy = rng.uniform(50.0, 2000.0, n)
+    cz = rng.uniform(-500.0, 500.0, n)
+    r = rng.uniform(5.0, 100.0, n)
+    return py, pz, cy, cz, r
+
+
+# -------------------------------------------------------- tangent depth pins
+
+
+def pin_closed_form_level(lib):
+    """Pixel level with the wire centre (Pz = Cz): similar triangles give
+    d = Cz + s r Py / sqrt((Py - Cy)^2 - r^2)."""
+    py, _, cy, cz, r = random_geometries(500, 11)
+    for s in (+1, -1):
+        for a, b, c, rr in zip(py, cy, cz, r):
+            d = oracle.tangent_depth(a, c, b, c, rr, s, lib=lib)
+            ref = c + s * rr * a / math.sqrt((a - b) ** 2 - rr * rr)
+            assert abs(d - ref) <= 1e-9 * (1.0 + abs(ref)), (d, ref)
+    # numbers of the 510 mm geometry: +-26.0153 um about the wire centre
+    d = oracle.tangent_depth(510000.0, -26.0, 300.0, -26.0, 26.0, +1, lib=lib)
+    assert abs((d + 26.0) - 26.0153) < 1e-4, d
+
+
+def pin_zero_radius(lib):
+    """r -> 0: the ray through the wire centre, d = Cz - Cy (Cz - Pz)/(Cy - Py)."""
+    py, pz, cy, cz, _ = random_geometries(500, 12)
+    for s in (+1, -1):
+        for a, z, b, c in zip(py, pz, cy, cz):
+            d = oracle.tangent_depth(a, z, b, c, 1e-300, s, lib=lib)
+            ref = c - b * (c - z) / (b - a)
+            assert abs(d - ref) <= 1e-9 * (1.0 + abs(ref)), (d, ref)
+
+
+def pin_bisection(lib):
+    """Tangent depth equals the beam point where the source-pixel segment just
+    touches the wire disc, found by bisection on the distance alone."""
+    py, pz, cy, cz, r = random_geometries(300, 13)
+    for a, z, b, c, rr in zip(py, pz, cy, cz, r):
+        zc = c - b * (c - z) / (b - a)  # segment through the wire centre
+        for s in (+1, -1):
+            # on side s the distance grows from 0 (at zc) past r; bracket it
+            lo, hi = zc, zc + s * 1e4
+            assert seg_dist(b, c, hi, a, z) > rr
+            for _ in range(200):
+                mid = 0.5 * (lo + hi)
+                if seg_dist(b, c, mid, a, z) < rr:
+                    lo = mid
+                else:
+                    hi = mid
+            d = oracle.tangent_depth(a, z, b, c, rr, s, lib=lib)
+            assert abs(d - 0.5 * (lo + hi)) < 2e-8, (d, lo, hi, s)
+
+
+def pin_mirror(lib):
+    """Reflecting z about the wire centre swaps the two edges:
+    d_s(Pz) = 2 Cz - d_{-s}(2 Cz - Pz)."""
+    py, pz, cy, cz, r = random_geometries(500, 14)
+    for a, z, b, c, rr in zip(py, pz, cy, cz, r):
+        for s in (+1, -1):
+            d1 = oracle.tangent_depth(a, z, b, c, rr, s, lib=lib)
+            d2 = oracle.tangent_depth(a, 2 * c - z, b, c, rr, -s, lib=lib)
+            assert abs(d1 - (2 * c - d2)) <= 1e-9 * (1.0 + abs(d1)), (d1, d2)
+
+
+def pin_edge_sign(lib):
+    """The leading edge is the +z edge when the wire moves downstream (+z) and
+    the -z edge when the same scan runs backwards."""
+    w = synth.wire_scan(41, 1.0)
+    assert oracle.edge_sign(510000.0, 0.0, w.centers, 26.0, lib=lib) == +1
+    assert oracle.edge_sign(510000.0, 0.0, w.centers[::-1].copy(), 26.0, lib=lib) == -1
+
+
+# ---------------------------------------------------------------- binning pins
+
+HAND_PROFILES = [
+    # (u, I, n_bins, expected out) -- computed by hand
+    ([0.5, 1.5], [10, 0], 3, [5.0, 5.0, 0.0]),            # split evenly over two bins
+    ([1.25, 1.75], [8, 2], 3, [0.0, 6.0, 0.0]),           # inside one bin: fraction 1
+    ([-0.5, 0.5], [10, 0], 3, [5.0, 0.0, 0.0]),           # part below the grid dropped
+    ([2.5, 3.5], [10, 0], 3, [0.0, 0.0, 5.0]),            # part above the grid dropped
+    ([1.0, 2.0], [4, 0], 4, [0.0, 4.0, 0.0, 0.0]),        # exact bin edges: one bin
+    ([1.3, 1.3], [4, 1], 3, [0.0, 3.0, 0.0]),             # zero length: point mass
+    ([2.5, 0.5], [10, 0], 3, [2.5, 5.0, 2.5]),            # decreasing positions
+    ([0.0, 4.0], [0, 8], 4, [-2.0, -2.0, -2.0, -2.0]),    # negative difference kept
+    ([0.5, 1.5, 3.0], [10, 4, 1], 4, [3.0, 3.0 + 1.0, 2.0, 0.0]),
+    ([-5.0, -4.0], [9, 0], 3, [0.0, 0.0, 0.0]),           # entirely outside
+    ([3.0, 5.0], [9, 0], 3, [0.0, 0.0, 0.0]),             # starts at the top edge
+    ([0.0, 0.0], [6, 1], 2, [5.0, 0.0]),                  # zero length at bin edge 0
+    ([-1.0, 0.0], [6, 1], 2, [0.0, 0.0]),                 # ends exactly at the grid start
+]
+
+
+def pin_hand_profiles(lib):
+    for u, I, B, want in HAND_PROFILES:
+        got = oracle.bin_profile(u, I, B, lib=lib)
+        assert np.allclose(got, want, rtol=0, atol=1e-12), (u, I, got, want)
+
+
+def pin_conservation_random(lib):
+    """Positions inside the grid: the profile sums to I_0 - I_{N-1}."""
+    rng = np.random.default_rng(15)
+    for _ in range(50):
+        N = int(rng.integers(2, 60))
+        B = 50
+        u = np.sort(rng.uniform(0.0, B, N))
+        if rng.random() < 0.5:
+            u = u[::-1].copy()
+        I = rng.integers(0, 65536, N).astype(np.float64)
+        got = oracle.bin_profile(u, I, B, lib=lib)
+        assert abs(got.sum() - (I[0] - I[-1])) <= 1e-8 * (1 + np.abs(np.diff(I)).sum())
+
+
+# --------------------------------------------------------- whole-chain pins
+
+
+def pin_conservation_scan(lib):
+    """Config-1 scan: every pixel's sweep lies inside the grid, so each pixel
+    conserves intensity and the totals sum to the total first-minus-last."""
+    s = synth.config1()
+    out, tot, _ = oracle.reconstruct(s, lib=lib)
+    I = s.images.astype(np.float64)
+    scale = np.abs(np.diff(I, axis=0)).sum(0) + 1.0
+    assert np.all(np.abs(out.sum(0) - (I[0] - I[-1])) <= 1e-9 * scale)
+    assert abs(tot.sum() - (I[0] - I[-1]).sum()) <= 1e-9 * scale.sum()
+
+
+def brute_force_pixel(py, pz, centers, r, grid, I, samples_per_bin=4000):
+    """Depth profile of one pixel by sub-sampling the beam: the intensity lost
+    between steps k and k+1 is spread uniformly over the beam points that are
+    clear at step k and blocked at step k+1 (the slice the leading edge sweeps).
+    Returns (profile, per-bin error bound)."""
+    B, w, c0 = grid.n_bins, grid.width, grid.first_center
+    e0 = c0 - 0.5 * w
+    h = w / samples_per_bin
+    # sample far beyond the grid so that slices crossing its ends are measured whole
+    zlo, zhi = e0 - 30.0 * w, e0 + (B + 30) * w
+    z = zlo + h * (np.arange(int((zhi - zlo) / h)) + 0.5)
+    occ = np.stack([seg_dist_vec(c[1], c[2], z, py, pz) < r for c in centers])
+    binidx = np.floor((z - e0) / w).astype(np.int64)
+    inside = (binidx >= 0) & (binidx < B)
+    prof = np.zeros(B)
+    err = np.zeros(B)
+    for k in range(len(centers) - 1):
+        newly = occ[k + 1] & ~occ[k]
+        n = int(newly.sum())
+        dI = float(I[k]) - float(I[k + 1])
+        if n == 0:
+            continue
+        sel = newly & inside
+        cnt = np.bincount(binidx[sel], minlength=B)
+        prof += dI * cnt / n
+        touched = cnt > 0
+        err[touched] += abs(dI) * 4.0 / n
+    return prof, err
+
+
+def pin_brute_force(lib):
+    """Tiny scans (4x4 px, 9 steps, 15 bins) against brute-force integration."""
+    for seed, step, width in ((21, 1.0, 1.0), (22, 0.5, 0.5), (23, 2.0, 1.0)):
+        s = synth.tiny(4, 4, 9, 15, seed=seed, pitch=3000.0, step=step, width=width,
+                       n_src=6, dark=50.0, sigma=1.0)
+        out, _, _ = oracle.reconstruct(s, lib=lib)
+        py, pz = s.detector.pixel_yz()
+        for j in range(4):
+            for i in range(4):
+                prof, err = brute_force_pixel(py[j, i], pz[j, i], s.wire.centers,
+                                              s.wire.radius, s.grid, s.images[:, j, i])
+                got = out[:, j, i]
+                assert np.all(np.abs(got - prof) <= err + 1e-9), (seed, j, i, got, prof, err)
+
+
+def pin_planted_sources(lib):
+    """Noise-free single-pixel sources with integer amplitude: the source depth
+    lies inside the interval of the step at which it goes dark, and the bins of
+    that interval receive exactly its amplitude."""
+    s = synth.tiny(48, 48, 61, 121, seed=31, step=1.0, width=1.0, n_src=30, dark=0.0,
+                   noise=False, sigma=0.0, integer_amp=True)
+    out, _, bins = oracle.reconstruct(s, want_bins=True, lib=lib)
+    src = s.sources
+    ii = np.rint(src.ci).astype(int)
+    jj = np.rint(src.cj).astype(int)
+    flat = jj * s.detector.nx + ii
+    uniq, cnt = np.unique(flat, return_counts=True)
+    single = set(uniq[cnt == 1].tolist())
+    _, _, upos = oracle.reconstruct_pixels(s, flat, want_u=True, lib=lib)
+    e0 = s.grid.first_center - 0.5 * s.grid.width
+    checked = 0
+    for n in range(len(flat)):
+        if flat[n] not in single:
+            continue
+        I = s.images[:, jj[n], ii[n]].astype(np.int64)
+        drops = np.nonzero(I[:-1] > I[1:])[0]
+        if len(drops) == 0:
+            continue  # never occluded during the scan
+        k = int(drops[0])
+        assert I[k] - I[k + 1] == int(src.amp[n])
+        u0, u1 = upos[n, k], upos[n, k + 1]
+        zu = (src.zs[n] - e0) / s.grid.width
+        assert min(u0, u1) - 1e-9 <= zu <= max(u0, u1) + 1e-9, (zu, u0, u1)
+        b0 = max(0, int(math.floor(min(u0, u1))))
+        b1 = min(s.grid.n_bins - 1, int(math.floor(max(u0, u1))))
+        got = out[b0:b1 + 1, jj[n], ii[n]].sum()
+        assert abs(got - src.amp[n]) < 1e-8 * src.amp[n], (got, src.amp[n])
+        checked += 1
+    assert checked >= 10, checked
+
+
+def pin_poisson_recovery(lib):
+    """Poisson data: the +-1-bin smoothed profile of the brightest pixel of
+    each clearly recoverable source peaks within one bin of its depth."""
+    s = synth.tiny(160, 160, 81, 121, seed=41, step=1.0, width=1.0, n_src=120, dark=100.0,
+                   noise=True, sigma=1.5)
+    out, _, _ = oracle.reconstruct(s, lib=lib)
+    src = s.sources
+    e0 = s.grid.first_center - 0.5 * s.grid.width
+    ii = np.rint(src.ci).astype(int)
+    jj = np.rint(src.cj).astype(int)
+    ok = tot = 0
+    for n in range(len(src.zs)):
+        # skip sources whose spots overlap another source's
+        d = np.hypot(src.ci - src.ci[n], src.cj - src.cj[n])
+        d[n] = np.inf
+        if d.min() < 9.0:
+            continue
+        g = math.exp(-((ii[n] - src.ci[n]) ** 2 + (jj[n] - src.cj[n]) ** 2) / (2 * 1.5 ** 2))
+        peak = src.amp[n] * g
+        if peak < 20.0 * math.sqrt(peak + 100.0):
+            continue
+        prof = out[:, jj[n], ii[n]]
+        sm = prof.copy()
+        sm[1:] += prof[:-1]
+        sm[:-1] += prof[1:]
+        want = math.floor((src.zs[n] - e0) / s.grid.width)
+        I = s.images[:, jj[n], ii[n]].astype(float)
+        if I[:5].mean() - I.min() < 0.5 * peak:
+            continue  # not occluded during the scan: not recoverable
+        tot += 1
+        ok += abs(int(np.argmax(sm)) - want) <= 1
+    assert tot >= 30 and ok >= math.ceil(0.99 * tot), (ok, tot)
+
+
+ALL_PINS = [
+    pin_closed_form_level, pin_zero_radius, pin_bisection, pin_mirror, pin_edge_sign,
+    pin_hand_profiles, pin_conservation_random, pin_conservation_scan, pin_brute_force,
+    pin_planted_sources, pin_poisson_recovery,
+]

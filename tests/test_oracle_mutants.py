@@ -1,0 +1,68 @@
+"""Planted mistakes in the oracle must fail at least one pin.
+
+Each mutant is a copy of oracle.c with one plausible slip (a dropped term, a
+flipped sign, a wrong or transposed index) compiled into a temporary library;
+the pins of tests/oracle_pins.py are run against it, fastest first, and at
+least one must fail.  Mutants are built on the CPU only.
+"""
+import os
+
+import pytest
+
+import oracle
+import oracle_pins
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
+
+MUTANTS = [
+    ("tz_sign", "double tz = az * kk - ay * sr;", "double tz = az * kk + ay * sr;"),
+    ("ty_sign", "double ty = ay * kk + az * sr;", "double ty = ay * kk - az * sr;"),
+    ("drop_L2_term", "return cz - (cy * tz + sr * L2) / ty;", "return cz - (cy * tz) / ty;"),
+    ("L2_index", "double L2 = az * az + ay * ay;", "double L2 = az * az + ay * az;"),
+    ("kk_sign", "double q = L2 - r * r;", "double q = L2 + r * r;"),
+    ("edge_flip", "return (d1 > d0) ? +1 : -1;", "return (d1 > d0) ? -1 : +1;"),
+    ("u_offset_sign", "u[k] = (d - e0) * invw;", "u[k] = (d + e0) * invw;"),
+    ("e0_half_bin", "const double e0 = first_center - width / 2.0;",
+     "const double e0 = first_center;"),
+    ("dI_sign", "double dI = I[k] - I[k + 1];", "double dI = I[k + 1] - I[k];"),
+    ("dI_index", "double dI = I[k] - I[k + 1];", "double dI = I[k] - I[n_steps - 1];"),
+    ("top_swap", "double top = hi < bd + 1.0 ? hi : bd + 1.0;",
+     "double top = hi < bd + 1.0 ? bd + 1.0 : hi;"),
+    ("no_normalise", "out[(int64_t)bd * stride] += dI * (ov / len);",
+     "out[(int64_t)bd * stride] += dI * ov;"),
+    ("ceil_first", "double first = floor(lo), last = floor(hi);",
+     "double first = ceil(lo), last = floor(hi);"),
+    ("pixel_transposed", "*pz = (origin[2] + i * u[2]) + j * v[2];",
+     "*pz = (origin[2] + j * u[2]) + i * v[2];"),
+    ("step_reversed", "Ik[k] = (double)images[(int64_t)k * plane_in + p];",
+     "Ik[k] = (double)images[(int64_t)(n_steps - 1 - k) * plane_in + p];"),
+    ("point_mass_sign", "if (bd >= 0.0 && bd < (double)n_bins) out[(int64_t)bd * stride] += dI;",
+     "if (bd >= 0.0 && bd < (double)n_bins) out[(int64_t)bd * stride] -= dI;"),
+    ("lo_hi_swap", "double lo = u[k] < u[k + 1] ? u[k] : u[k + 1];",
+     "double lo = u[k];"),
+]
+
+
+def _ordered_pins():
+    pins = list(oracle_pins.ALL_PINS)
+    slow = [oracle_pins.pin_brute_force]
+    return [p for p in pins if p not in slow] + slow
+
+
+@pytest.mark.parametrize("name,orig,repl", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_mutant_is_caught(tmp_path, name, orig, repl):
+    text = open(SRC).read()
+    assert orig in text, f"mutation site for {name} not found"
+    mutated = text.replace(orig, repl)
+    src = tmp_path / f"oracle_{name}.c"
+    src.write_text(mutated)
+    lib_path = oracle.build(force=True, src=str(src), out=str(tmp_path / f"liboracle_{name}.so"))
+    lib = oracle.load(lib_path)
+    failures = []
+    for pin in _ordered_pins():
+        try:
+            pin(lib)
+        except (AssertionError, oracle.OracleError) as e:  # the pin caught it
+            failures.append(pin.__name__)
+            break
+    assert failures, f"mutant {name} survived every pin"
