@@ -1,0 +1,198 @@
+"""Benchmark: wire-scan depth reconstruction on one MI355X.
+
+A step is one pass of the whole path over the full-frame scan (2048 x 2048
+pixels, 1001 wire steps, 1001 depth bins, uint16 images resident in HBM):
+the reconstruction kernel (tangent-depth plan, differences, fractional
+binning, every output bin stored once) and the per-depth totals.  Prints one
+JSON line with the throughput in pixel-wire-steps per second, the dominant
+kernel's achieved HBM bandwidth against the 8 TB/s peak, the oracle's CPU
+throughput on a bounded sample, and the slab-streamed end-to-end rate
+(host images over PCIe), which is never the headline value.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "pixel·wire-steps/s + HBM GB/s vs roofline; serving p50/p99 latency"
+UNIT = "pixel·wire-steps/s"
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_source_digest() -> str:
+    with open(os.path.join(ROOT, "paper_2201_13309_amd", "csrc", "dr_kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def algorithmic_bytes(nx, ny, n_steps, n_bins):
+    """Bytes the method must move per pass: every uint16 image element read
+    once, every FP32 output bin written once, each row's bin plan read once
+    (bin index, count and three fractions: 20 B per row and interval) and the
+    totals written."""
+    P = nx * ny
+    return 2 * P * n_steps + 4 * P * n_bins + 20 * ny * (n_steps - 1) + 4 * n_bins
+
+
+def measured_traffic(digest: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, when
+    it was taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", "traffic_rows_f32_config3.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("kernel_source_sha256_16") != digest:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(scan, target_s: float):
+    """The oracle as it stands, on a bounded sample of rows of the same scan."""
+    import oracle
+    cores = min(16, os.cpu_count() or 1)
+    det, N = scan.detector, scan.wire.n_steps
+    r0 = det.ny // 2
+    t0 = time.perf_counter()
+    oracle.reconstruct(scan, row0=r0, nrows=1, nthreads=cores)
+    one = max(time.perf_counter() - t0, 1e-3)
+    rows = int(max(1, min(det.ny - r0, target_s / one)))
+    t0 = time.perf_counter()
+    oracle.reconstruct(scan, row0=r0, nrows=rows, nthreads=cores)
+    dt = time.perf_counter() - t0
+    work = rows * det.nx * N
+    return {"value": work / dt, "unit": UNIT, "cores": cores, "kind": "oracle",
+            "sample": f"rows {r0}..{r0 + rows - 1} of the {det.nx}x{det.ny}x{N}-step scan "
+                      f"({work:.3e} pixel-wire-steps, FP64, {dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-e2e", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--workload", default="config3", choices=["config2", "config3"])
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_2201_13309_amd import dr
+
+    dr.load()
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    gen = synth.config3 if args.workload == "config3" else synth.config2
+    s = gen(render_now=False)
+    det, grid, N = s.detector, s.grid, s.wire.n_steps
+    nx, ny, B = det.nx, det.ny, grid.n_bins
+    log(f"rendering {args.workload}: {nx}x{ny} px, {N} steps, {B} bins")
+    t0 = time.perf_counter()
+    host = torch.empty((N, ny, nx), dtype=torch.int16, pin_memory=True)
+    synth.render(s, out=host.numpy().view(np.uint16))
+    log(f"rendered {host.numel() * 2 / 1e9:.2f} GB in {time.perf_counter() - t0:.1f} s")
+    dev = host.to("cuda", non_blocking=False)
+    out = torch.empty((B, ny, nx), dtype=torch.float32, device="cuda")
+    tot = torch.empty((B,), dtype=torch.float32, device="cuda")
+    ctx = dr.dr_ctx_create(0, 0)
+    g = dr.dr_geometry_init(ctx, det, s.wire, grid)
+    stream = torch.cuda.current_stream()
+    tile = None
+    if not args.no_autotune:
+        tile = dr.dr_autotune(g, dev, out)
+        log(f"autotuned launch shape (pixels/lane, waves, prefetch): {tile[:3]}")
+    for _ in range(args.warmup):
+        dr.dr_reconstruct(g, dev, True, out, tot, stream)
+    torch.cuda.synchronize()
+    log("warm-up done")
+
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        dr.dr_reconstruct(g, dev, True, out, tot, stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_step = ev0.elapsed_time(ev1) / args.steps
+    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step")
+
+    # dominant kernel alone: HIP events the library records around its launch
+    dr.dr_enable_timing(g, True)
+    kms, tms = [], []
+    for _ in range(args.steps):
+        dr.dr_reconstruct(g, dev, True, out, tot, stream)
+        a, b = dr.dr_last_timing(g)
+        kms.append(a)
+        tms.append(b)
+    dr.dr_enable_timing(g, False)
+    k_avg = float(np.mean(kms))
+    alg = algorithmic_bytes(nx, ny, N, B)
+    achieved = alg / (k_avg * 1e-3) / 1e9
+    digest = kernel_source_digest()
+    traffic = measured_traffic(digest)
+    work = nx * ny * N
+    result = {
+        "metric": METRIC,
+        "value": work / (ms_step * 1e-3),
+        "unit": UNIT,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u16 in, f32 accumulate, f64 geometry",
+        "data": "synthetic (seeded forward model: point sources, wire occlusion, Poisson counts)",
+        "config": {"workload": f"{args.workload}: {nx}x{ny} px uint16, {N} wire steps x 0.5 um, "
+                               f"{B} depth bins x {grid.width} um, images resident in HBM",
+                   "pixel_wire_steps": work,
+                   "launch_shape": None if tile is None else list(tile[:3])},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "rows_f32_kernel", "kernel_ms": k_avg,
+                     "totals_ms": float(np.mean(tms)), "algorithmic_bytes": alg,
+                     "kernel_source_sha256_16": digest},
+    }
+    if not args.no_e2e:
+        # host images over PCIe, row slabs double-buffered against the kernel
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dr.dr_reconstruct(g, host, False, out, tot, stream)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        result["end_to_end"] = {"value": work / dt, "unit": UNIT, "ms": dt * 1e3,
+                                "h2d_GBps": host.numel() * 2 / dt / 1e9,
+                                "note": "pinned host images streamed in row slabs; PCIe-bound"}
+        log(f"end-to-end (PCIe) {dt * 1e3:.1f} ms")
+    dr.dr_geometry_free(g)
+    del dev, out
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        log("timing the oracle on a CPU sample")
+        s.images = host.numpy().view(np.uint16)
+        result["cpu_baseline"] = cpu_baseline(s, args.cpu_seconds)
+    dr.dr_ctx_destroy(ctx)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

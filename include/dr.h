@@ -1,0 +1,262 @@
+/*
+ * dr.h - C ABI of the MI355X (gfx950) wire-scan depth-reconstruction library.
+ *
+ * The library reconstructs depth-resolved intensity from a stack of detector
+ * images taken at successive wire positions: p images of m rows x n columns
+ * (paper Sec. III-B), each pixel's intensity differences between consecutive
+ * images being added into depth arrays (paper Sec. III-C).  For every pixel
+ * and wire step it computes, in FP64, the depth at which the ray from the
+ * pixel that grazes the wire's leading edge meets the incident beam, and it
+ * spreads I_k - I_{k+1} over the depth interval [d_k, d_{k+1}] into fixed
+ * bins in proportion to the overlap.  Geometry conventions:
+ *
+ *   - lengths in micrometres; the beam is the line x = y = 0 travelling +z;
+ *     depth is the z coordinate of a point on the beam;
+ *   - the wire is a cylinder of radius `radius` whose axis is the lab x axis;
+ *   - pixel (row j, column i) has centre (origin + i*u) + j*v unless an
+ *     explicit per-pixel table is given;
+ *   - bin b of the depth grid is centred at first_center + b*width and covers
+ *     [first_center + (b - 1/2) width, first_center + (b + 1/2) width);
+ *   - the leading edge is the wire side whose shadow on the beam advances with
+ *     the scan: the +z side when the +z tangent depth of the last step exceeds
+ *     that of the first, otherwise the -z side; the intensity difference
+ *     I_k - I_{k+1} is spread over [u_k, u_{k+1}] (bin units), parts outside
+ *     the grid are dropped, and a zero-length interval adds into floor(u_k).
+ *
+ * Data layout (all row-major, flat one-dimensional buffers as in the paper's
+ * Sec. III-B choice of a 1D array over a pointer-based 3D array):
+ *   images  uint16 [n_steps][ny][nx]   (step slowest)
+ *   out     float  [n_bins][ny][nx]    (depth slowest; every element written)
+ *   totals  float  [n_bins]            (sum of out over all pixels)
+ *
+ * Precision: tangent depths, bin positions and overlap fractions in FP64;
+ * intensity differences and bin accumulation in FP32 (dr_reconstruct) or
+ * FP64 (dr_reconstruct_f64).  Bin indices floor(u_k) are exact FP64 results
+ * (IEEE operations in a fixed order, no contraction).
+ *
+ * Errors: every entry point returns a dr_status; negative values are errors
+ * and dr_last_error() returns a message for the calling thread.  Nothing is
+ * thrown across the ABI.  Arguments are checked before any device work.
+ *
+ * Threads: a dr_ctx may be used from several host threads; calls that enqueue
+ * work on one dr_geom must not overlap in time on different streams, because
+ * each geometry owns one scratch area (per-wave partial sums of the totals).
+ */
+#ifndef DR_H
+#define DR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dr_status;
+#define DR_OK 0
+#define DR_PENDING 1
+#define DR_E_INVAL (-1)
+#define DR_E_NOMEM (-2)
+#define DR_E_UNSUPPORTED (-3)
+#define DR_E_DEVICE (-4)
+#define DR_E_BUSY (-5)
+#define DR_E_NOTFOUND (-6)
+
+#define DR_EDGE_LEADING 0
+
+typedef struct dr_ctx_s* dr_ctx;     /* one GPU: streams, slab buffers, scheduler */
+typedef struct dr_geom_s* dr_geom;   /* device-resident tables of one geometry */
+typedef struct dr_batch_s* dr_batch; /* a captured, tuned launch over many scans */
+
+/* Detector: pixel (j, i) centre = (origin + i*u) + j*v (um).  pixel_xyz, when
+ * not NULL, is a host array [ny][nx][3] of explicit centres that overrides the
+ * affine map.  Only the y and z coordinates enter the reconstruction. */
+typedef struct {
+    int32_t nx, ny;
+    double origin[3], u[3], v[3];
+    const double* pixel_xyz;
+} dr_detector;
+
+/* Wire: a cylinder of `radius` um with axis `axis` (must be (1,0,0));
+ * centers is a host array [n_steps][3] of the axis position at each step (the
+ * x coordinate is ignored).  edge must be DR_EDGE_LEADING. */
+typedef struct {
+    double radius;
+    double axis[3];
+    int32_t n_steps;
+    const double* centers;
+    int32_t edge;
+} dr_wire;
+
+/* Depth grid: n_bins bins of `width` um, bin b centred at first_center + b*width. */
+typedef struct {
+    int32_t n_bins;
+    double first_center, width;
+} dr_depth_grid;
+
+/* Launch shape of the reconstruction kernel.  pixels_per_lane in {1,2,4,8},
+ * waves_per_group in {2,4}, prefetch (wire steps in flight per lane) in
+ * {4,8}; groups_per_cu only matters for persistent (batched) launches.
+ * A zero field means "choose". */
+typedef struct {
+    int32_t pixels_per_lane, waves_per_group, prefetch, groups_per_cu;
+} dr_tile_config;
+
+/* ------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes bounds the device
+ * memory the serving scheduler may hold for admitted requests (0 = 90% of the
+ * free memory at creation).  Errors: DR_E_INVAL (bad device or NULL out),
+ * DR_E_DEVICE (HIP failure). */
+dr_status dr_ctx_create(int device, size_t hbm_budget_bytes, dr_ctx* out);
+
+/* Stop the scheduler, wait for outstanding work and free the context.  Every
+ * geometry and batch created on it must have been freed first
+ * (DR_E_BUSY otherwise). */
+dr_status dr_ctx_destroy(dr_ctx ctx);
+
+/* ------------------------------------------------------------ geometry */
+
+/* Build the device tables of one (detector, wire, depth grid) - the
+ * per-pixel geometry the paper's kernel reads for each pixel (Sec. III-C) -
+ * and check it on the device.  Copies every input, so the caller may free its
+ * arrays on return; the library owns *out until dr_geometry_free.
+ * Errors: DR_E_INVAL for NULL pointers, nx/ny/n_bins < 1, n_steps < 2,
+ * radius <= 0, width <= 0, an axis other than (1,0,0) or an edge other than
+ * DR_EDGE_LEADING (DR_E_UNSUPPORTED for those two), a pixel inside the wire,
+ * a wire position not strictly between beam and detector in y, or any
+ * non-finite depth; DR_E_NOMEM / DR_E_DEVICE for allocation or HIP failures.
+ * Synchronous. */
+dr_status dr_geometry_init(dr_ctx ctx, const dr_detector* det, const dr_wire* wire,
+                           const dr_depth_grid* grid, dr_geom* out);
+
+/* Free a geometry.  Waits for the device work already enqueued on it.
+ * DR_E_BUSY while serving requests that use it are in flight. */
+dr_status dr_geometry_free(dr_geom geom);
+
+/* Force a launch shape for this geometry (tile-invariance tests, manual
+ * tuning); NULL restores the automatic choice.  DR_E_INVAL for values outside
+ * the sets listed at dr_tile_config or a shape that does not fit nx or the
+ * buffer alignment at launch time. */
+dr_status dr_set_tile(dr_geom geom, const dr_tile_config* tile);
+
+/* Time the available launch shapes on this geometry with the caller's device
+ * buffers and keep the fastest for later calls (autotuner; results are cached
+ * per device architecture and size class, and in the JSON file named by the
+ * environment variable DR_TUNE_CACHE when set).  `out` is overwritten.
+ * Synchronous.  *chosen (if not NULL) receives the winner. */
+dr_status dr_autotune(dr_geom geom, const uint16_t* images_dev, float* out_dev,
+                      dr_tile_config* chosen);
+
+/* -------------------------------------------------------- reconstruction */
+
+/* Reconstruct one scan (paper Sec. III-C) into out[n_bins][ny][nx] (device,
+ * FP32) and, when totals is not NULL, totals[n_bins] (device, FP32).
+ *   images_on_device != 0: images is a device pointer [n_steps][ny][nx].
+ *   images_on_device == 0: images is host memory (pinned for full speed);
+ *     it is streamed to the device in row slabs, each slab's copy on the
+ *     context's copy stream overlapping the kernel of the previous slab - the
+ *     paper's pass-per-row-slab scheme (Sec. III-B) with double buffering.
+ * stream is a hipStream_t (NULL = the context's compute stream).  The call
+ * returns after enqueueing; buffers must stay valid and unchanged until the
+ * stream reaches the end of the enqueued work.  Errors: DR_E_INVAL for NULL
+ * or misaligned pointers, DR_E_DEVICE for HIP failures. */
+dr_status dr_reconstruct(dr_geom geom, const uint16_t* images, int images_on_device,
+                         float* out, float* totals, void* stream);
+
+/* Same operation with FP64 intensity differences and FP64 accumulation into
+ * out[n_bins][ny][nx] and totals[n_bins] (both device, double).  Validation
+ * instance of the same kernel: it performs the oracle's operations in the
+ * oracle's order.  images must be on the device. */
+dr_status dr_reconstruct_f64(dr_geom geom, const uint16_t* images_dev, double* out,
+                             double* totals, void* stream);
+
+/* Positions of the leading edge, computed by the device code the kernels use,
+ * for a host list of pixels (flat indices j*nx + i): bins_out[n][n_steps]
+ * receives floor(u_k) as int32 (saturated) and u_out[n][n_steps] the FP64
+ * u_k = (d_k - e0)/width-scaled positions; either output may be NULL.  Host
+ * buffers; synchronous.  DR_E_INVAL for an out-of-range pixel. */
+dr_status dr_debug_plan(dr_geom geom, const int64_t* pixels, int32_t n, int32_t* bins_out,
+                        double* u_out);
+
+/* Device time in milliseconds of the last reconstruction kernel launched by
+ * dr_reconstruct on this geometry (HIP events on the launch stream; waits for
+ * them), and of the totals reduction after it.  Timing is recorded only after
+ * dr_enable_timing(geom, 1). */
+dr_status dr_enable_timing(dr_geom geom, int enable);
+dr_status dr_last_timing(dr_geom geom, double* kernel_ms, double* totals_ms);
+
+/* -------------------------------------------------------------- batches */
+
+/* One scan of a batch: device images [n_steps][ny][nx], device out, device
+ * totals (or NULL), each scan with its own geometry. */
+typedef struct {
+    dr_geom geom;
+    const uint16_t* images;
+    float* out;
+    float* totals;
+} dr_batch_item;
+
+#define DR_BATCH_AUTOTUNE 1 /* time launch shapes on the batch and keep the best */
+#define DR_BATCH_GRAPH 2    /* capture the launch sequence in a hipGraph */
+
+/* Plan one persistent launch over many scans of uneven size: work items are
+ * (scan, row tile) pairs ordered by cost and pulled by workgroups from a
+ * device queue.  The plan keeps the item pointers, so the buffers must stay
+ * allocated while the batch exists; their contents may change between runs.
+ * With DR_BATCH_AUTOTUNE the outputs are overwritten while tuning.
+ * Errors: DR_E_INVAL (n < 1, NULL items, geometries of another context),
+ * DR_E_NOMEM, DR_E_DEVICE. */
+dr_status dr_batch_create(dr_ctx ctx, int32_t n, const dr_batch_item* items, int32_t flags,
+                          dr_batch* out);
+
+/* Run the batch on `stream` (NULL = context stream): replays the captured
+ * graph when the batch has one.  Returns after enqueueing. */
+dr_status dr_batch_run(dr_batch batch, void* stream);
+
+/* The launch shape the batch uses. */
+dr_status dr_batch_tile(dr_batch batch, dr_tile_config* tile);
+
+dr_status dr_batch_free(dr_batch batch);
+
+/* ---------------------------------------------------------------- serving */
+
+/* Queue one reconstruction request with the context's scheduler and return
+ * at once with a ticket.  Requests are admitted in arrival order while the
+ * device memory they need (image staging for host images, plus scratch) fits
+ * the context budget; admitted requests are continuously batched: each
+ * scheduling epoch is one persistent launch over row tiles of every admitted
+ * request whose images are resident, so requests that arrive while others
+ * run join the next epoch.  Each pixel's result is bitwise the same as with
+ * dr_reconstruct.  images: host (pinned) or device per images_on_device;
+ * out/totals: device, as in dr_reconstruct.  The caller keeps every buffer
+ * valid until dr_poll reports DR_OK or an error for the ticket.
+ * Errors: DR_E_INVAL, DR_E_NOMEM (the request can never fit the budget). */
+dr_status dr_submit(dr_ctx ctx, dr_geom geom, const uint16_t* images, int images_on_device,
+                    float* out, float* totals, uint64_t* ticket);
+
+/* DR_PENDING while the request is queued or running, DR_OK once its results
+ * are complete in device memory, a negative error if it failed (sticky),
+ * DR_E_NOTFOUND for an unknown or already-collected ticket.  A ticket is
+ * forgotten after dr_poll has returned DR_OK or an error for it once. */
+dr_status dr_poll(dr_ctx ctx, uint64_t ticket);
+
+/* Block until the ticket completes; same results as dr_poll. */
+dr_status dr_wait(dr_ctx ctx, uint64_t ticket);
+
+/* Scheduler counters. */
+typedef struct {
+    uint64_t submitted, admitted, completed, epochs, tiles_launched;
+    uint64_t bytes_h2d;
+    size_t hbm_in_use, hbm_budget;
+} dr_stats;
+dr_status dr_ctx_stats(dr_ctx ctx, dr_stats* out);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* dr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DR_H */

@@ -1,0 +1,58 @@
+"""Build the HIP library libdr.so for gfx950 (hipcc), in-tree.
+
+Objects go to _build/ at the repository root; the shared library lands next to
+this file so that it travels with the source tree.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+from concurrent.futures import ThreadPoolExecutor
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+BUILD = os.path.join(ROOT, "_build")
+LIB_PATH = os.path.join(PKG, "libdr.so")
+ARCH = os.environ.get("PYTORCH_ROCM_ARCH", "gfx950").split(";")[0] or "gfx950"
+
+# -ffp-contract=off: FP64 geometry must not be contracted into FMAs (bin
+# indices are exact results of a fixed operation order).  Packed FP32 ops are
+# disabled for all device code.
+COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall", f"-I{INCLUDE}", f"-I{CSRC}"]
+DEVICE = ["-x", "hip", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
+          "-packed-fp32-ops"]
+SOURCES = [("dr_kernels.hip", True), ("dr_runtime.cpp", False), ("dr_serve.cpp", False)]
+
+
+def _compile(src: str, device: bool) -> str:
+    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    cmd = ["hipcc", *COMMON, *(DEVICE if device else []), "-c", os.path.join(CSRC, src), "-o", obj]
+    subprocess.run(cmd, check=True, stderr=subprocess.PIPE, stdout=subprocess.PIPE)
+    return obj
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    with ThreadPoolExecutor(len(SOURCES)) as ex:
+        futs = [ex.submit(_compile, s, d) for s, d in SOURCES]
+        objs = []
+        for f in futs:
+            try:
+                objs.append(f.result())
+            except subprocess.CalledProcessError as e:
+                raise RuntimeError("hipcc failed:\n" + e.stderr.decode(errors="replace")) from e
+    tmp = LIB_PATH + ".tmp"
+    link = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-lpthread"]
+    r = subprocess.run(link, stderr=subprocess.PIPE, stdout=subprocess.PIPE)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc link failed:\n" + r.stderr.decode(errors="replace"))
+    os.replace(tmp, LIB_PATH)
+    if verbose:
+        print("built", LIB_PATH)
+    return LIB_PATH
+
+
+if __name__ == "__main__":
+    build(verbose=True)

@@ -1,0 +1,99 @@
+// Internal declarations shared by the HIP kernels (dr_kernels.hip) and the
+// host runtime (dr_runtime.cpp).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dr {
+
+// Row classes of the per-row bin plan: how the leading edge moves over the scan.
+enum RowClass : int8_t { kRowGeneric = 0, kRowIncreasing = 1, kRowDecreasing = 2 };
+
+// Plan of the FP64 bin positions of one (row, interval k): the interval
+// [u_k, u_{k+1}] touches bins bl .. bl+nb-1 with positive overlap; the first
+// bin receives fraction f0, the last f1, the ones between fm (= 1/len).
+struct PlanTables {
+    int32_t* bl;   // [ny][n_steps-1]
+    int32_t* nb;
+    float* f0;     // FP32 copies for the FP32 kernel
+    float* fm;
+    float* f1;
+    double* d0;    // FP64 fractions for the FP64 kernel
+    double* dm;
+    double* d1;
+    int8_t* row_class;  // [ny]
+    int8_t* row_sign;   // [ny] leading-edge side s_p (+1 / -1)
+};
+
+// One scan as seen by the reconstruction kernels.  The image buffer holds
+// detector rows [row_base, row_base + rows held) of every step.
+struct ScanArgs {
+    const uint16_t* img;  // element (step 0, buffer row 0, column 0)
+    int64_t img_step;     // elements between consecutive steps
+    int64_t img_row;      // elements between consecutive rows
+    int32_t row_base;     // detector row stored at buffer row 0
+    int32_t nx, ny;
+    int32_t row_begin, row_end;  // detector rows to process
+    int32_t tiles_per_row;
+    int32_t n_steps, n_bins;
+    void* out;            // element (bin 0, row 0, column 0); float or double
+    int64_t out_plane;    // elements between bins (ny*nx)
+    void* partials;       // per-wave partial sums of totals, [slots][n_bins]
+    // plan tables (row mode)
+    const int32_t* bl;
+    const int32_t* nb;
+    const float* f0;
+    const float* fm;
+    const float* f1;
+    const double* d0;
+    const double* dm;
+    const double* d1;
+    const int8_t* row_class;
+};
+
+// Geometry as seen by the table builder and the debug kernel.
+struct GeomArgs {
+    int32_t nx, ny, n_steps, n_bins;
+    double radius, first_center, width;
+    const double* wire_yz;  // [n_steps][2]
+    const double* pix_yz;   // [ny][nx][2] or null (affine map below)
+    double oy, uy, vy, oz, uz, vz;
+};
+
+struct BatchArgs {
+    const ScanArgs* scans;     // [n_scans] in work order
+    const int64_t* tile_start; // [n_scans + 1] prefix sums of tile counts
+    int32_t n_scans;
+    int64_t total_tiles;
+    unsigned long long* counter;  // queue head, reset before each launch
+};
+
+struct TileCfg {
+    int ppl, waves, prefetch;
+};
+
+// Launch wrappers (dr_kernels.hip).  All return the launch status.
+bool tile_supported(const TileCfg& t);
+int tile_width(const TileCfg& t);
+int num_tile_variants();
+TileCfg tile_variant(int i);
+
+hipError_t launch_build_plans(const GeomArgs& g, const PlanTables& t, int* d_status,
+                              hipStream_t s);
+hipError_t launch_rows_f32(const TileCfg& t, const ScanArgs& a, hipStream_t s);
+hipError_t launch_rows_f64(const ScanArgs& a, hipStream_t s);
+hipError_t launch_batch_f32(const TileCfg& t, const BatchArgs& b, int groups, hipStream_t s);
+hipError_t launch_reset_counter(unsigned long long* counter, hipStream_t s);
+// totals[b] = sum over slots of partials[slot][b] (FP64 sum, stored as T)
+hipError_t launch_totals_f32(const float* partials, int64_t slots, int n_bins, double* work,
+                             int work_rows, float* totals, hipStream_t s);
+hipError_t launch_totals_f64(const double* partials, int64_t slots, int n_bins, double* work,
+                             int work_rows, double* totals, hipStream_t s);
+hipError_t launch_debug_plan(const GeomArgs& g, const int64_t* pixels, int n, int32_t* bins,
+                             double* upos, hipStream_t s);
+
+constexpr int kPlanChunk = 1024;  // intervals staged in LDS at a time
+constexpr int kTotalsWorkRows = 64;
+
+}  // namespace dr

@@ -1,0 +1,666 @@
+// HIP kernels (gfx950) of the wire-scan depth reconstruction.
+//
+// Work split (paper Sec. III-C maps one GPU thread to one image element and
+// adds into shared depth arrays with an emulated double atomicAdd; here a lane
+// owns PPL adjacent pixels of one detector row for the whole scan, so every
+// output element has exactly one writer and nothing is atomic):
+//
+//   build_plans_kernel   once per geometry: FP64 leading-edge positions u_k of
+//                        each detector row (all pixels of a row share their
+//                        (y, z) centre bit for bit), and the bins and overlap
+//                        fractions of every interval [u_k, u_{k+1}] -> tables.
+//   rows kernels         per (row, tile of PPL*64*WAVES pixels): stage the
+//                        row's plan in LDS, stream uint16 images step by step
+//                        with PF steps in flight, FP32 differences, accumulate
+//                        the open bin in registers, store each finished bin
+//                        once (non-temporal), per-wave partial totals.
+//   batch kernel         the same tile body in a persistent grid pulling
+//                        (scan, tile) items from a queue counter.
+//   totals kernels       FP64 sum of the per-wave partial totals.
+//
+// FP64 geometry follows a fixed operation order without contraction so that
+// bin indices are exact; build with -ffp-contract=off.
+#include "dr_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace dr {
+
+// ------------------------------------------------------------- FP64 geometry
+
+// Depth at which the ray from pixel (py, pz), tangent to the wire disc centred
+// at (cy, cz) on side sr/r (sr = s*r, s = +1 is the +z side), meets the beam:
+// d = Cz - (Cy*tz + s*r*L2)/ty with a = C - P, L2 = |a|^2, kk = sqrt(L2 - r^2),
+// t = a*kk + s*r*a_perp.  Every term is O(wire height), free of cancellation.
+__device__ __forceinline__ double tangent_depth(double py, double pz, double cy, double cz,
+                                                double r, double sr)
+{
+    const double ay = cy - py;
+    const double az = cz - pz;
+    const double L2 = az * az + ay * ay;
+    const double q = L2 - r * r;
+    if (!(q > 0.0)) return __builtin_nan("");
+    const double kk = __builtin_sqrt(q);
+    const double tz = az * kk - ay * sr;
+    const double ty = ay * kk + az * sr;
+    return cz - (cy * tz + sr * L2) / ty;
+}
+
+__device__ __forceinline__ void pixel_key(const GeomArgs& g, int64_t p, double& py, double& pz)
+{
+    if (g.pix_yz) {
+        py = g.pix_yz[2 * p];
+        pz = g.pix_yz[2 * p + 1];
+        return;
+    }
+    const double i = (double)(p % g.nx);
+    const double j = (double)(p / g.nx);
+    py = (g.oy + i * g.uy) + j * g.vy;
+    pz = (g.oz + i * g.uz) + j * g.vz;
+}
+
+// Leading-edge side: +1 when the +z tangent depth of the last step exceeds
+// that of the first.
+__device__ __forceinline__ int leading_sign(const GeomArgs& g, double py, double pz)
+{
+    const int l = g.n_steps - 1;
+    const double d0 = tangent_depth(py, pz, g.wire_yz[0], g.wire_yz[1], g.radius, g.radius);
+    const double d1 = tangent_depth(py, pz, g.wire_yz[2 * l], g.wire_yz[2 * l + 1], g.radius,
+                                    g.radius);
+    return d1 > d0 ? 1 : -1;
+}
+
+__device__ __forceinline__ double edge_position(const GeomArgs& g, double py, double pz, int k,
+                                                double sr, double e0, double invw)
+{
+    const double d = tangent_depth(py, pz, g.wire_yz[2 * k], g.wire_yz[2 * k + 1], g.radius, sr);
+    return (d - e0) * invw;
+}
+
+__device__ __forceinline__ int32_t floor_to_i32(double x)
+{
+    const double f = __builtin_floor(x);
+    if (f < -2147483648.0) return INT32_MIN;
+    if (f > 2147483647.0) return INT32_MAX;
+    return (int32_t)f;
+}
+
+struct PlanD {
+    int bl, nb;
+    double f0, fm, f1;
+};
+
+// Bins of the interval between positions ua and ub (bin units) that overlap it
+// by a positive length, and their fractions overlap/length.  A zero-length
+// interval is a point mass in bin floor(ua).  Parts outside [0, B) drop out.
+__device__ __forceinline__ PlanD make_plan(double ua, double ub, int B)
+{
+    PlanD e{0, 0, 0.0, 0.0, 0.0};
+    const double lo = ua < ub ? ua : ub;
+    const double hi = ua < ub ? ub : ua;
+    const double len = hi - lo;
+    if (len > 0.0) {
+        double first = __builtin_floor(lo), last = __builtin_floor(hi);
+        if (first < 0.0) first = 0.0;
+        if (last > (double)(B - 1)) last = (double)(B - 1);
+        double ovf = 0.0, ovl = 0.0;
+        while (first <= last) {
+            const double top = hi < first + 1.0 ? hi : first + 1.0;
+            const double bot = lo > first ? lo : first;
+            ovf = top - bot;
+            if (ovf > 0.0) break;
+            first += 1.0;
+        }
+        while (last >= first) {
+            const double top = hi < last + 1.0 ? hi : last + 1.0;
+            const double bot = lo > last ? lo : last;
+            ovl = top - bot;
+            if (ovl > 0.0) break;
+            last -= 1.0;
+        }
+        if (first <= last) {
+            e.bl = (int)first;
+            e.nb = (int)(last - first) + 1;
+            e.f0 = ovf / len;
+            e.f1 = ovl / len;
+            e.fm = 1.0 / len;  // interior bins overlap by exactly one bin
+        }
+    } else {
+        const double bd = __builtin_floor(lo);
+        if (bd >= 0.0 && bd < (double)B) {
+            e.bl = (int)bd;
+            e.nb = 1;
+            e.f0 = e.fm = e.f1 = 1.0;
+        }
+    }
+    return e;
+}
+
+// One workgroup per detector row: plan tables, row class, checks.
+// status bit 0: a non-finite position (pixel inside the wire or degenerate);
+// bit 1: a wire position not strictly between beam and detector in y.
+__global__ __launch_bounds__(256) void build_plans_kernel(GeomArgs g, PlanTables t, int* status)
+{
+    const int row = blockIdx.x;
+    const int N = g.n_steps, B = g.n_bins, nint = N - 1;
+    double py, pz;
+    pixel_key(g, (int64_t)row * g.nx, py, pz);
+    const int s = leading_sign(g, py, pz);
+    const double sr = (double)s * g.radius;
+    const double e0 = g.first_center - g.width / 2.0;
+    const double invw = 1.0 / g.width;
+    int inc = 1, dec = 1, bad = 0;
+    for (int k = threadIdx.x; k < nint; k += blockDim.x) {
+        const double ua = edge_position(g, py, pz, k, sr, e0, invw);
+        const double ub = edge_position(g, py, pz, k + 1, sr, e0, invw);
+        if (!__builtin_isfinite(ua) || !__builtin_isfinite(ub)) bad |= 1;
+        for (int kk = k; kk <= k + 1; ++kk) {
+            const double cy = g.wire_yz[2 * kk];
+            if (!(cy > 0.0 && cy < py)) bad |= 2;
+        }
+        inc &= (ub >= ua);
+        dec &= (ub <= ua);
+        const PlanD e = make_plan(ua, ub, B);
+        const int64_t o = (int64_t)row * nint + k;
+        t.bl[o] = e.bl;
+        t.nb[o] = e.nb;
+        t.f0[o] = (float)e.f0;
+        t.fm[o] = (float)e.fm;
+        t.f1[o] = (float)e.f1;
+        if (t.d0) {
+            t.d0[o] = e.f0;
+            t.dm[o] = e.fm;
+            t.d1[o] = e.f1;
+        }
+    }
+    inc = __syncthreads_and(inc);
+    dec = __syncthreads_and(dec);
+    const int bad1 = __syncthreads_or(bad & 1) ? 1 : 0;
+    const int bad2 = __syncthreads_or(bad & 2) ? 2 : 0;
+    bad = bad1 | bad2;
+    if (threadIdx.x == 0) {
+        t.row_class[row] = inc ? kRowIncreasing : (dec ? kRowDecreasing : kRowGeneric);
+        t.row_sign[row] = (int8_t)s;
+        if (bad) atomicOr(status, bad);
+    }
+}
+
+// ------------------------------------------------------------ tile kernels
+
+template <int PPL> struct U16V;
+template <> struct U16V<1> { typedef unsigned short T; };
+template <> struct U16V<2> { typedef unsigned int T; };
+template <> struct U16V<4> { typedef unsigned int T __attribute__((ext_vector_type(2))); };
+template <> struct U16V<8> { typedef unsigned int T __attribute__((ext_vector_type(4))); };
+
+template <int PPL>
+__device__ __forceinline__ int pix(const typename U16V<PPL>::T& v, int p)
+{
+    if constexpr (PPL == 1) return (int)v;
+    else if constexpr (PPL == 2) return (int)((v >> (16 * p)) & 0xffffu);
+    else return (int)((v[p >> 1] >> (16 * (p & 1))) & 0xffffu);
+}
+
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <typename Acc, int PPL>
+__device__ __forceinline__ void store_bins(Acc* p, const Acc (&a)[PPL])
+{
+    if constexpr (sizeof(Acc) == 8 || PPL == 1) {
+#pragma unroll
+        for (int q = 0; q < PPL; ++q) __builtin_nontemporal_store(a[q], p + q);
+    } else if constexpr (PPL == 2) {
+        f32x2 v = {a[0], a[1]};
+        __builtin_nontemporal_store(v, (f32x2*)p);
+    } else {
+#pragma unroll
+        for (int q = 0; q < PPL; q += 4) {
+            f32x4 v = {a[q], a[q + 1], a[q + 2], a[q + 3]};
+            __builtin_nontemporal_store(v, (f32x4*)(p + q));
+        }
+    }
+}
+
+template <typename Acc>
+__device__ __forceinline__ Acc wave_sum(Acc s)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    return s;
+}
+
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ float uni(float x)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+__device__ __forceinline__ double uni(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <typename Acc> struct PlanLds {
+    int bl[kPlanChunk];
+    int nb[kPlanChunk];
+    Acc f0[kPlanChunk];
+    Acc fm[kPlanChunk];
+    Acc f1[kPlanChunk];
+};
+
+template <typename Acc>
+__device__ __forceinline__ void stage_plan(const ScanArgs& a, int row, int kc, int nk,
+                                           PlanLds<Acc>& L)
+{
+    const int64_t base = (int64_t)row * (a.n_steps - 1) + kc;
+    for (int e = threadIdx.x; e < nk; e += blockDim.x) {
+        L.bl[e] = a.bl[base + e];
+        L.nb[e] = a.nb[base + e];
+        if constexpr (sizeof(Acc) == 4) {
+            L.f0[e] = a.f0[base + e];
+            L.fm[e] = a.fm[base + e];
+            L.f1[e] = a.f1[base + e];
+        } else {
+            L.f0[e] = a.d0[base + e];
+            L.fm[e] = a.dm[base + e];
+            L.f1[e] = a.d1[base + e];
+        }
+    }
+}
+
+// acc + f*dI: one rounding (fma) in FP32; in FP64 the product and the sum are
+// rounded separately, the oracle's order.
+__device__ __forceinline__ float madd(float f, float dI, float acc) { return __builtin_fmaf(f, dI, acc); }
+__device__ __forceinline__ double madd(double f, double dI, double acc) { return acc + dI * f; }
+
+// Non-monotone rows: zero the tile's bins, then read-modify-write every
+// contribution in step order (each lane touches only its own pixels).
+template <typename Acc, int PPL, int WAVES>
+__device__ void process_tile_generic(const ScanArgs& a, int row, int tile, PlanLds<Acc>& L)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int TW = 64 * WAVES * PPL;
+    const int col0 = tile * TW + tid * PPL;
+    const bool act = col0 < a.nx;
+    const int N = a.n_steps, B = a.n_bins, nint = N - 1;
+    const uint16_t* ip = a.img + (int64_t)(row - a.row_base) * a.img_row + col0;
+    Acc* op = (Acc*)a.out + (int64_t)row * a.nx + col0;
+    const int64_t plane = a.out_plane;
+    Acc* part = a.partials ? (Acc*)a.partials +
+                                 ((int64_t)(row * a.tiles_per_row + tile) * WAVES + wave) * B
+                           : nullptr;
+    if (act)
+        for (int b = 0; b < B; ++b)
+#pragma unroll
+            for (int q = 0; q < PPL; ++q) op[(int64_t)b * plane + q] = (Acc)0;
+    for (int kc = 0; kc < nint; kc += kPlanChunk) {
+        const int nk = min(kPlanChunk, nint - kc);
+        __syncthreads();
+        stage_plan<Acc>(a, row, kc, nk, L);
+        __syncthreads();
+        for (int kk = 0; kk < nk; ++kk) {
+            const int bl = uni(L.bl[kk]), nb = uni(L.nb[kk]);
+            if (nb == 0 || !act) continue;
+            const Acc f0 = uni(L.f0[kk]), fm = uni(L.fm[kk]), f1 = uni(L.f1[kk]);
+            const int k = kc + kk;
+            const int bh = bl + nb - 1;
+#pragma unroll
+            for (int q = 0; q < PPL; ++q) {
+                const Acc dI = (Acc)((int)ip[(int64_t)k * a.img_step + q] -
+                                     (int)ip[(int64_t)(k + 1) * a.img_step + q]);
+                for (int b = bl; b <= bh; ++b) {
+                    const Acc f = (b == bl) ? f0 : ((b == bh) ? f1 : fm);
+                    Acc* o = op + (int64_t)b * plane + q;
+                    *o = madd(f, dI, *o);
+                }
+            }
+        }
+    }
+    if (part) {
+        for (int b = 0; b < B; ++b) {
+            Acc s = (Acc)0;
+            if (act)
+#pragma unroll
+                for (int q = 0; q < PPL; ++q) s += op[(int64_t)b * plane + q];
+            s = wave_sum(s);
+            if (lane == 0) part[b] = s;
+        }
+    }
+}
+
+// One tile: PPL adjacent pixels per lane, 64*WAVES lanes, one detector row.
+template <typename Acc, int PPL, int WAVES, int PF>
+__device__ __forceinline__ void process_tile(const ScanArgs& a, int row, int tile,
+                                             PlanLds<Acc>& L)
+{
+    using V = typename U16V<PPL>::T;
+    constexpr int TW = 64 * WAVES * PPL;
+    const int cls = a.row_class[row];
+    if (cls == kRowGeneric) {
+        process_tile_generic<Acc, PPL, WAVES>(a, row, tile, L);
+        return;
+    }
+    const int dir = (cls == kRowIncreasing) ? 1 : -1;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int col0 = tile * TW + tid * PPL;
+    const bool act = col0 < a.nx;
+    const int N = a.n_steps, B = a.n_bins, nint = N - 1;
+    const V* ip = (const V*)(a.img + (int64_t)(row - a.row_base) * a.img_row + col0);
+    const int64_t vstep = a.img_step / PPL;
+    Acc* op = (Acc*)a.out + (int64_t)row * a.nx + col0;
+    const int64_t plane = a.out_plane;
+    Acc* part = a.partials ? (Acc*)a.partials +
+                                 ((int64_t)(row * a.tiles_per_row + tile) * WAVES + wave) * B
+                           : nullptr;
+
+    auto load = [&](int k) -> V {
+        V v = (V)0;
+        if (act) v = __builtin_nontemporal_load(ip + (int64_t)k * vstep);
+        return v;
+    };
+    Acc acc[PPL];
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) acc[q] = (Acc)0;
+    int cb = -1;                      // open bin (uniform), -1 = none
+    int nxt = dir > 0 ? 0 : B - 1;    // next bin not yet stored (uniform)
+
+    auto put = [&](int b, const Acc (&v)[PPL]) {
+        if (act) store_bins<Acc, PPL>(op + (int64_t)b * plane, v);
+        if (part) {
+            Acc s = (Acc)0;
+#pragma unroll
+            for (int q = 0; q < PPL; ++q) s += v[q];
+            s = wave_sum(s);
+            if (lane == 0) part[b] = s;
+        }
+    };
+    auto put_zero = [&](int b) {
+        Acc z[PPL];
+#pragma unroll
+        for (int q = 0; q < PPL; ++q) z[q] = (Acc)0;
+        if (act) store_bins<Acc, PPL>(op + (int64_t)b * plane, z);
+        if (part && lane == 0) part[b] = (Acc)0;
+    };
+    auto flush = [&]() {
+        if (cb >= 0) {
+            if (dir > 0) {
+                for (int z = nxt; z < cb; ++z) put_zero(z);
+            } else {
+                for (int z = nxt; z > cb; --z) put_zero(z);
+            }
+            put(cb, acc);
+            nxt = cb + dir;
+        }
+    };
+    auto interval = [&](int kk, const V& prev, const V& cur) {
+        const int nb = uni(L.nb[kk]);
+        if (nb == 0) return;
+        const int bl = uni(L.bl[kk]);
+        const Acc f0 = uni(L.f0[kk]), fm = uni(L.fm[kk]), f1 = uni(L.f1[kk]);
+        Acc dI[PPL];
+#pragma unroll
+        for (int q = 0; q < PPL; ++q) dI[q] = (Acc)(pix<PPL>(prev, q) - pix<PPL>(cur, q));
+        const int bh = bl + nb - 1;
+        for (int e = 0; e < nb; ++e) {
+            const int b = dir > 0 ? bl + e : bh - e;
+            const Acc f = (b == bl) ? f0 : ((b == bh) ? f1 : fm);
+            if (b != cb) {
+                flush();
+                cb = b;
+#pragma unroll
+                for (int q = 0; q < PPL; ++q) acc[q] = (Acc)0;
+            }
+#pragma unroll
+            for (int q = 0; q < PPL; ++q) acc[q] = madd(f, dI[q], acc[q]);
+        }
+    };
+
+    V prev = load(0);
+    V ring[PF];
+#pragma unroll
+    for (int d = 0; d < PF; ++d) ring[d] = (1 + d < N) ? load(1 + d) : (V)0;
+
+    for (int kc = 0; kc < nint; kc += kPlanChunk) {
+        const int nk = min(kPlanChunk, nint - kc);
+        __syncthreads();
+        stage_plan<Acc>(a, row, kc, nk, L);
+        __syncthreads();
+        int kk = 0;
+        for (; kk + PF <= nk; kk += PF) {
+#pragma unroll
+            for (int d = 0; d < PF; ++d) {
+                const V cur = ring[d];
+                const int kn = kc + kk + d + 1 + PF;
+                if (kn < N) ring[d] = load(kn);
+                interval(kk + d, prev, cur);
+                prev = cur;
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < PF; ++d) {
+            if (kk + d < nk) {
+                const V cur = ring[d];
+                interval(kk + d, prev, cur);
+                prev = cur;
+            }
+        }
+    }
+    flush();
+    if (dir > 0) {
+        for (int z = nxt; z < B; ++z) put_zero(z);
+    } else {
+        for (int z = nxt; z >= 0; --z) put_zero(z);
+    }
+}
+
+template <int PPL, int WAVES, int PF>
+__global__ __launch_bounds__(64 * WAVES) void rows_f32_kernel(ScanArgs a)
+{
+    __shared__ PlanLds<float> L;
+    const int row = a.row_begin + (int)(blockIdx.x / (unsigned)a.tiles_per_row);
+    const int tile = (int)(blockIdx.x % (unsigned)a.tiles_per_row);
+    process_tile<float, PPL, WAVES, PF>(a, row, tile, L);
+}
+
+__global__ __launch_bounds__(256) void rows_f64_kernel(ScanArgs a)
+{
+    __shared__ PlanLds<double> L;
+    const int row = a.row_begin + (int)(blockIdx.x / (unsigned)a.tiles_per_row);
+    const int tile = (int)(blockIdx.x % (unsigned)a.tiles_per_row);
+    process_tile<double, 1, 4, 4>(a, row, tile, L);
+}
+
+// Persistent grid: workgroups pull (scan, tile) items until the queue is dry.
+template <int PPL, int WAVES, int PF>
+__global__ __launch_bounds__(64 * WAVES) void batch_f32_kernel(BatchArgs b)
+{
+    __shared__ PlanLds<float> L;
+    __shared__ unsigned long long s_item;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_item = atomicAdd(b.counter, 1ull);
+        __syncthreads();
+        const long long item = (long long)s_item;
+        if (item >= b.total_tiles) break;
+        int si = 0;
+        while (si + 1 < b.n_scans && b.tile_start[si + 1] <= item) ++si;
+        const ScanArgs a = b.scans[si];
+        const long long t = item - b.tile_start[si];
+        const int row = a.row_begin + (int)(t / a.tiles_per_row);
+        const int tile = (int)(t % a.tiles_per_row);
+        process_tile<float, PPL, WAVES, PF>(a, row, tile, L);
+    }
+}
+
+__global__ void reset_counter_kernel(unsigned long long* c) { *c = 0ull; }
+
+// ------------------------------------------------------------------ totals
+
+template <typename T>
+__global__ __launch_bounds__(256) void totals_stage1(const T* part, int64_t slots, int B,
+                                                     double* work)
+{
+    __shared__ double red[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int b = blockIdx.x * 64 + lane;
+    double s = 0.0;
+    if (b < B)
+        for (int64_t sl = (int64_t)blockIdx.y * 4 + w; sl < slots; sl += (int64_t)gridDim.y * 4)
+            s += (double)part[sl * B + b];
+    red[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && b < B)
+        work[(int64_t)blockIdx.y * B + b] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void totals_stage2(const double* work, int rows, int B, T* tot)
+{
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    if (b >= B) return;
+    double s = 0.0;
+    for (int r = 0; r < rows; ++r) s += work[(int64_t)r * B + b];
+    tot[b] = (T)s;
+}
+
+// ------------------------------------------------------------------- debug
+
+__global__ __launch_bounds__(64) void debug_plan_kernel(GeomArgs g, const int64_t* pix, int n,
+                                                        int32_t* bins, double* upos)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n) return;
+    double py, pz;
+    pixel_key(g, pix[idx], py, pz);
+    const int s = leading_sign(g, py, pz);
+    const double sr = (double)s * g.radius;
+    const double e0 = g.first_center - g.width / 2.0;
+    const double invw = 1.0 / g.width;
+    for (int k = 0; k < g.n_steps; ++k) {
+        const double u = edge_position(g, py, pz, k, sr, e0, invw);
+        if (bins) bins[(int64_t)idx * g.n_steps + k] = floor_to_i32(u);
+        if (upos) upos[(int64_t)idx * g.n_steps + k] = u;
+    }
+}
+
+// ---------------------------------------------------------- launch wrappers
+
+static const TileCfg kVariants[] = {
+    {1, 2, 4}, {1, 2, 8}, {1, 4, 4}, {1, 4, 8},
+    {2, 2, 4}, {2, 2, 8}, {2, 4, 4}, {2, 4, 8},
+    {4, 2, 4}, {4, 2, 8}, {4, 4, 4}, {4, 4, 8},
+    {8, 2, 4}, {8, 2, 8}, {8, 4, 4}, {8, 4, 8},
+};
+
+int num_tile_variants() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
+TileCfg tile_variant(int i) { return kVariants[i]; }
+
+bool tile_supported(const TileCfg& t)
+{
+    for (const TileCfg& v : kVariants)
+        if (v.ppl == t.ppl && v.waves == t.waves && v.prefetch == t.prefetch) return true;
+    return false;
+}
+
+int tile_width(const TileCfg& t) { return 64 * t.waves * t.ppl; }
+
+#define DR_DISPATCH(T, KERNEL, GRID, ARGS, STREAM)                                            \
+    do {                                                                                      \
+        const dim3 blk(64 * (T).waves);                                                       \
+        switch ((T).ppl * 100 + (T).waves * 10 + (T).prefetch / 4) {                          \
+        case 121: hipLaunchKernelGGL((KERNEL<1, 2, 4>), GRID, blk, 0, STREAM, ARGS); break;   \
+        case 122: hipLaunchKernelGGL((KERNEL<1, 2, 8>), GRID, blk, 0, STREAM, ARGS); break;   \
+        case 141: hipLaunchKernelGGL((KERNEL<1, 4, 4>), GRID, blk, 0, STREAM, ARGS); break;   \
+        case 142: hipLaunchKernelGGL((KERNEL<1, 4, 8>), GRID, blk, 0, STREAM, ARGS); break;   \
+        case 221: hipLaunchKernelGGL((KERNEL<2, 2, 4>), GRID, blk, 0, STREAM, ARGS); break;   \
+        case 222: hipLaunchKernelGGL((KERNEL<2, 2, 8>), GRID, blk, 0, STREAM, ARGS); break;   \
+        case 241: hipLaunchKernelGGL((KERNEL<2, 4, 4>), GRID, blk, 0, STREAM, ARGS); break;   \
+        case 242: hipLaunchKernelGGL((KERNEL<2, 4, 8>), GRID, blk, 0, STREAM, ARGS); break;   \
+        case 421: hipLaunchKernelGGL((KERNEL<4, 2, 4>), GRID, blk, 0, STREAM, ARGS); break;   \
+        case 422: hipLaunchKernelGGL((KERNEL<4, 2, 8>), GRID, blk, 0, STREAM, ARGS); break;   \
+        case 441: hipLaunchKernelGGL((KERNEL<4, 4, 4>), GRID, blk, 0, STREAM, ARGS); break;   \
+        case 442: hipLaunchKernelGGL((KERNEL<4, 4, 8>), GRID, blk, 0, STREAM, ARGS); break;   \
+        case 821: hipLaunchKernelGGL((KERNEL<8, 2, 4>), GRID, blk, 0, STREAM, ARGS); break;   \
+        case 822: hipLaunchKernelGGL((KERNEL<8, 2, 8>), GRID, blk, 0, STREAM, ARGS); break;   \
+        case 841: hipLaunchKernelGGL((KERNEL<8, 4, 4>), GRID, blk, 0, STREAM, ARGS); break;   \
+        case 842: hipLaunchKernelGGL((KERNEL<8, 4, 8>), GRID, blk, 0, STREAM, ARGS); break;   \
+        default: return hipErrorInvalidValue;                                                 \
+        }                                                                                     \
+    } while (0)
+
+hipError_t launch_build_plans(const GeomArgs& g, const PlanTables& t, int* d_status,
+                              hipStream_t s)
+{
+    hipLaunchKernelGGL(build_plans_kernel, dim3(g.ny), dim3(256), 0, s, g, t, d_status);
+    return hipGetLastError();
+}
+
+hipError_t launch_rows_f32(const TileCfg& t, const ScanArgs& a, hipStream_t s)
+{
+    const int64_t rows = a.row_end - a.row_begin;
+    if (rows <= 0) return hipSuccess;
+    const dim3 grid((unsigned)(rows * a.tiles_per_row));
+    DR_DISPATCH(t, rows_f32_kernel, grid, a, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_rows_f64(const ScanArgs& a, hipStream_t s)
+{
+    const int64_t rows = a.row_end - a.row_begin;
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(rows_f64_kernel, dim3((unsigned)(rows * a.tiles_per_row)), dim3(256), 0,
+                       s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_f32(const TileCfg& t, const BatchArgs& b, int groups, hipStream_t s)
+{
+    const dim3 grid((unsigned)groups);
+    DR_DISPATCH(t, batch_f32_kernel, grid, b, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_counter(unsigned long long* counter, hipStream_t s)
+{
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, counter);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_totals(const T* partials, int64_t slots, int n_bins, double* work,
+                                int work_rows, T* totals, hipStream_t s)
+{
+    const dim3 g1((unsigned)((n_bins + 63) / 64), (unsigned)work_rows);
+    hipLaunchKernelGGL(totals_stage1<T>, g1, dim3(256), 0, s, partials, slots, n_bins, work);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(totals_stage2<T>, dim3((unsigned)((n_bins + 255) / 256)), dim3(256), 0, s,
+                       (const double*)work, work_rows, n_bins, totals);
+    return hipGetLastError();
+}
+
+hipError_t launch_totals_f32(const float* partials, int64_t slots, int n_bins, double* work,
+                             int work_rows, float* totals, hipStream_t s)
+{
+    return launch_totals<float>(partials, slots, n_bins, work, work_rows, totals, s);
+}
+
+hipError_t launch_totals_f64(const double* partials, int64_t slots, int n_bins, double* work,
+                             int work_rows, double* totals, hipStream_t s)
+{
+    return launch_totals<double>(partials, slots, n_bins, work, work_rows, totals, s);
+}
+
+hipError_t launch_debug_plan(const GeomArgs& g, const int64_t* pixels, int n, int32_t* bins,
+                             double* upos, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(debug_plan_kernel, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, g,
+                       pixels, n, bins, upos);
+    return hipGetLastError();
+}
+
+}  // namespace dr

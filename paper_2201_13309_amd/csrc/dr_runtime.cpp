@@ -1,0 +1,834 @@
+// Host runtime behind the C ABI: contexts, geometries, single-scan and
+// slab-streamed reconstruction, the autotuner and captured batch launches.
+#include "dr_runtime.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+
+namespace dr {
+
+static thread_local std::string g_last_error;
+
+dr_status set_error(dr_status code, const std::string& msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+dr_status hip_error(hipError_t e, const char* what)
+{
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    if (e == hipErrorOutOfMemory) return set_error(DR_E_NOMEM, m);
+    return set_error(DR_E_DEVICE, m);
+}
+
+static dr_status ok()
+{
+    g_last_error.clear();
+    return DR_OK;
+}
+
+static bool finite3(const double* v)
+{
+    return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]);
+}
+
+static bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+// ------------------------------------------------------------ launch shapes
+
+bool tile_fits(const dr_geom g, const TileCfg& t, const void* img, const void* out)
+{
+    if (!tile_supported(t)) return false;
+    if (g->nx % t.ppl != 0) return false;
+    if (img && !aligned(img, 2 * (size_t)t.ppl)) return false;
+    if (out && !aligned(out, std::min<size_t>(16, 4 * (size_t)t.ppl))) return false;
+    return true;
+}
+
+TileCfg default_tile(const dr_geom g, const void* img, const void* out)
+{
+    static const TileCfg prefs[] = {{4, 4, 8}, {2, 4, 8}, {1, 4, 8}};
+    for (const TileCfg& t : prefs)
+        if (tile_fits(g, t, img, out)) return t;
+    return TileCfg{1, 4, 8};
+}
+
+static int tiles_per_row(const dr_geom g, const TileCfg& t)
+{
+    const int tw = tile_width(t);
+    return (g->nx + tw - 1) / tw;
+}
+
+int64_t partial_slots(const dr_geom g, const TileCfg& t)
+{
+    return (int64_t)g->ny * tiles_per_row(g, t) * t.waves;
+}
+
+ScanArgs scan_args(const dr_geom g, const TileCfg& t, const uint16_t* img, int64_t img_step,
+                   int row_base, int row_begin, int row_end, float* out, float* partials)
+{
+    ScanArgs a{};
+    a.img = img;
+    a.img_step = img_step;
+    a.img_row = g->nx;
+    a.row_base = row_base;
+    a.nx = g->nx;
+    a.ny = g->ny;
+    a.row_begin = row_begin;
+    a.row_end = row_end;
+    a.tiles_per_row = tiles_per_row(g, t);
+    a.n_steps = g->n_steps;
+    a.n_bins = g->n_bins;
+    a.out = out;
+    a.out_plane = (int64_t)g->nx * g->ny;
+    a.partials = partials;
+    a.bl = g->t.bl;
+    a.nb = g->t.nb;
+    a.f0 = g->t.f0;
+    a.fm = g->t.fm;
+    a.f1 = g->t.f1;
+    a.d0 = g->t.d0;
+    a.dm = g->t.dm;
+    a.d1 = g->t.d1;
+    a.row_class = g->t.row_class;
+    return a;
+}
+
+hipError_t enqueue_totals(const dr_geom g, const float* partials, int64_t slots, double* work,
+                          float* totals, hipStream_t s)
+{
+    return launch_totals_f32(partials, slots, g->n_bins, work, kTotalsWorkRows, totals, s);
+}
+
+static TileCfg choose_tile(dr_geom g, const void* img, const void* out)
+{
+    std::lock_guard<std::mutex> lk(g->mu);
+    if ((g->forced || g->tuned) && tile_fits(g, g->tile, img, out)) return g->tile;
+    return default_tile(g, img, out);
+}
+
+static dr_status ensure_scratch(dr_geom g, const TileCfg& t, float** part)
+{
+    std::lock_guard<std::mutex> lk(g->mu);
+    const size_t need = (size_t)partial_slots(g, t) * g->n_bins * sizeof(float);
+    DR_HIP(g->part32.reserve(need));
+    DR_HIP(g->work.reserve((size_t)kTotalsWorkRows * g->n_bins * sizeof(double)));
+    *part = g->part32.as<float>();
+    return DR_OK;
+}
+
+// ------------------------------------------------------------- tune cache
+
+static std::string size_class(const dr_ctx c, const char* kind, int nx, int64_t pixels, int n,
+                              int b)
+{
+    auto p2 = [](int64_t x) {
+        int64_t r = 1;
+        while (r < x) r <<= 1;
+        return r;
+    };
+    std::ostringstream os;
+    os << c->arch << "|" << kind << "|nx=" << nx << "|px=" << p2(pixels) << "|N=" << p2(n)
+       << "|B=" << p2(b);
+    return os.str();
+}
+
+static void load_tune_file(dr_ctx c)
+{
+    if (c->tune_file.empty()) return;
+    std::ifstream f(c->tune_file);
+    if (!f) return;
+    std::string line;
+    // one entry per line: "key": [ppl, waves, prefetch, gpc],
+    while (std::getline(f, line)) {
+        size_t q0 = line.find('"');
+        size_t q1 = line.find('"', q0 + 1);
+        size_t b0 = line.find('[', q1);
+        if (q0 == std::string::npos || q1 == std::string::npos || b0 == std::string::npos)
+            continue;
+        TileCfg t{0, 0, 0};
+        int gpc = 0;
+        if (sscanf(line.c_str() + b0, "[%d, %d, %d, %d]", &t.ppl, &t.waves, &t.prefetch, &gpc) >= 3
+            && tile_supported(t))
+            c->tune_cache[line.substr(q0 + 1, q1 - q0 - 1)] = t;
+    }
+}
+
+static void save_tune_file(dr_ctx c)
+{
+    if (c->tune_file.empty()) return;
+    std::ofstream f(c->tune_file + ".tmp");
+    if (!f) return;
+    f << "{\n";
+    size_t i = 0;
+    for (auto& kv : c->tune_cache) {
+        f << "  \"" << kv.first << "\": [" << kv.second.ppl << ", " << kv.second.waves << ", "
+          << kv.second.prefetch << ", 0]" << (++i < c->tune_cache.size() ? "," : "") << "\n";
+    }
+    f << "}\n";
+    f.close();
+    std::rename((c->tune_file + ".tmp").c_str(), c->tune_file.c_str());
+}
+
+}  // namespace dr
+
+using namespace dr;
+
+// ================================================================== C ABI
+
+extern "C" {
+
+const char* dr_last_error(void) { return g_last_error.c_str(); }
+
+dr_status dr_ctx_create(int device, size_t hbm_budget_bytes, dr_ctx* out)
+{
+    if (!out) return set_error(DR_E_INVAL, "dr_ctx_create: out is NULL");
+    *out = nullptr;
+    int n = 0;
+    DR_HIP(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return set_error(DR_E_INVAL, "dr_ctx_create: bad device");
+    DR_HIP(hipSetDevice(device));
+    auto c = std::make_unique<dr_ctx_s>();
+    c->device = device;
+    hipDeviceProp_t prop;
+    DR_HIP(hipGetDeviceProperties(&prop, device));
+    c->arch = prop.gcnArchName;
+    size_t colon = c->arch.find(':');
+    if (colon != std::string::npos) c->arch = c->arch.substr(0, colon);
+    c->cus = prop.multiProcessorCount;
+    size_t free_b = 0, total_b = 0;
+    DR_HIP(hipMemGetInfo(&free_b, &total_b));
+    c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)free_b);
+    DR_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    DR_HIP(hipStreamCreateWithFlags(&c->copy, hipStreamNonBlocking));
+    for (int i = 0; i < 2; ++i) {
+        DR_HIP(hipEventCreateWithFlags(&c->slab_ready[i], hipEventDisableTiming));
+        DR_HIP(hipEventCreateWithFlags(&c->slab_free[i], hipEventDisableTiming));
+    }
+    if (const char* f = std::getenv("DR_TUNE_CACHE")) c->tune_file = f;
+    load_tune_file(c.get());
+    *out = c.release();
+    return ok();
+}
+
+dr_status dr_ctx_destroy(dr_ctx c)
+{
+    if (!c) return set_error(DR_E_INVAL, "dr_ctx_destroy: NULL context");
+    if (c->sched) {
+        destroy_scheduler(c->sched);
+        c->sched = nullptr;
+    }
+    if (c->live_geoms.load() != 0 || c->live_batches.load() != 0)
+        return set_error(DR_E_BUSY, "dr_ctx_destroy: geometries or batches still alive");
+    DR_HIP(hipSetDevice(c->device));
+    DR_HIP(hipDeviceSynchronize());
+    for (int i = 0; i < 2; ++i) {
+        c->slab[i].release();
+        (void)hipEventDestroy(c->slab_ready[i]);
+        (void)hipEventDestroy(c->slab_free[i]);
+    }
+    (void)hipStreamDestroy(c->stream);
+    (void)hipStreamDestroy(c->copy);
+    delete c;
+    return ok();
+}
+
+dr_status dr_geometry_init(dr_ctx c, const dr_detector* det, const dr_wire* wire,
+                           const dr_depth_grid* grid, dr_geom* out)
+{
+    if (!c || !det || !wire || !grid || !out)
+        return set_error(DR_E_INVAL, "dr_geometry_init: NULL argument");
+    *out = nullptr;
+    if (det->nx < 1 || det->ny < 1) return set_error(DR_E_INVAL, "detector nx, ny must be >= 1");
+    if (wire->n_steps < 2 || !wire->centers)
+        return set_error(DR_E_INVAL, "wire needs n_steps >= 2 and centers");
+    if (grid->n_bins < 1) return set_error(DR_E_INVAL, "depth grid needs n_bins >= 1");
+    if (!(wire->radius > 0.0) || !std::isfinite(wire->radius))
+        return set_error(DR_E_INVAL, "wire radius must be > 0");
+    if (!(grid->width > 0.0) || !std::isfinite(grid->width) || !std::isfinite(grid->first_center))
+        return set_error(DR_E_INVAL, "depth grid width must be > 0 and finite");
+    if (!finite3(det->origin) || !finite3(det->u) || !finite3(det->v))
+        return set_error(DR_E_INVAL, "detector origin/u/v must be finite");
+    if (!(wire->axis[0] == 1.0 && wire->axis[1] == 0.0 && wire->axis[2] == 0.0))
+        return set_error(DR_E_UNSUPPORTED, "only a wire axis along x (1,0,0) is supported");
+    if (wire->edge != DR_EDGE_LEADING)
+        return set_error(DR_E_UNSUPPORTED, "only DR_EDGE_LEADING is supported");
+    const int nx = det->nx, ny = det->ny, N = wire->n_steps, B = grid->n_bins;
+    if ((int64_t)nx * ny > (int64_t)1 << 31)
+        return set_error(DR_E_INVAL, "detector larger than 2^31 pixels");
+    for (int k = 0; k < N; ++k)
+        if (!finite3(wire->centers + 3 * k))
+            return set_error(DR_E_INVAL, "wire centers must be finite");
+
+    // Rows share one bit-identical (y, z) centre when u has no y or z part,
+    // or when the explicit table says so row by row.
+    bool row_mode = true;
+    std::vector<double> pyz;
+    if (det->pixel_xyz) {
+        pyz.resize((size_t)nx * ny * 2);
+        for (int64_t p = 0; p < (int64_t)nx * ny; ++p) {
+            const double* q = det->pixel_xyz + 3 * p;
+            if (!finite3(q)) return set_error(DR_E_INVAL, "pixel_xyz must be finite");
+            pyz[2 * p] = q[1];
+            pyz[2 * p + 1] = q[2];
+        }
+        for (int j = 0; j < ny && row_mode; ++j) {
+            const double* r0 = pyz.data() + (size_t)2 * j * nx;
+            for (int i = 1; i < nx; ++i)
+                if (std::memcmp(r0, r0 + 2 * i, 2 * sizeof(double)) != 0) {
+                    row_mode = false;
+                    break;
+                }
+        }
+    } else {
+        row_mode = (det->u[1] == 0.0 && det->u[2] == 0.0);
+    }
+    if (!row_mode)
+        return set_error(DR_E_UNSUPPORTED,
+                         "detector rows must share their (y, z) pixel centre (u with no y or z "
+                         "component); a per-pixel geometry is not supported yet");
+
+    DR_HIP(hipSetDevice(c->device));
+    auto g = std::make_unique<dr_geom_s>();
+    g->ctx = c;
+    g->nx = nx;
+    g->ny = ny;
+    g->n_steps = N;
+    g->n_bins = B;
+    g->radius = wire->radius;
+    g->first_center = grid->first_center;
+    g->width = grid->width;
+    g->row_mode = row_mode;
+
+    std::vector<double> wyz((size_t)N * 2);
+    for (int k = 0; k < N; ++k) {
+        wyz[2 * k] = wire->centers[3 * k + 1];
+        wyz[2 * k + 1] = wire->centers[3 * k + 2];
+    }
+    DR_HIP(g->wire.reserve(wyz.size() * sizeof(double)));
+    DR_HIP(hipMemcpy(g->wire.p, wyz.data(), wyz.size() * sizeof(double), hipMemcpyHostToDevice));
+    if (!pyz.empty()) {
+        DR_HIP(g->pix.reserve(pyz.size() * sizeof(double)));
+        DR_HIP(hipMemcpy(g->pix.p, pyz.data(), pyz.size() * sizeof(double),
+                         hipMemcpyHostToDevice));
+    }
+
+    GeomArgs& ga = g->g;
+    ga.nx = nx;
+    ga.ny = ny;
+    ga.n_steps = N;
+    ga.n_bins = B;
+    ga.radius = wire->radius;
+    ga.first_center = grid->first_center;
+    ga.width = grid->width;
+    ga.wire_yz = g->wire.as<double>();
+    ga.pix_yz = g->pix.as<double>();
+    ga.oy = det->origin[1];
+    ga.uy = det->u[1];
+    ga.vy = det->v[1];
+    ga.oz = det->origin[2];
+    ga.uz = det->u[2];
+    ga.vz = det->v[2];
+
+    // plan tables: bl, nb (int32), f0, fm, f1 (float), d0, dm, d1 (double), class, sign
+    const size_t ent = (size_t)ny * (N - 1);
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t o_bl = 0, o_nb = o_bl + up(ent * 4), o_f0 = o_nb + up(ent * 4),
+                 o_fm = o_f0 + up(ent * 4), o_f1 = o_fm + up(ent * 4), o_d0 = o_f1 + up(ent * 4),
+                 o_dm = o_d0 + up(ent * 8), o_d1 = o_dm + up(ent * 8), o_cls = o_d1 + up(ent * 8),
+                 o_sgn = o_cls + up(ny), o_st = o_sgn + up(ny), total = o_st + 256;
+    DR_HIP(g->plan.reserve(total));
+    char* base = g->plan.as<char>();
+    PlanTables& t = g->t;
+    t.bl = (int32_t*)(base + o_bl);
+    t.nb = (int32_t*)(base + o_nb);
+    t.f0 = (float*)(base + o_f0);
+    t.fm = (float*)(base + o_fm);
+    t.f1 = (float*)(base + o_f1);
+    t.d0 = (double*)(base + o_d0);
+    t.dm = (double*)(base + o_dm);
+    t.d1 = (double*)(base + o_d1);
+    t.row_class = (int8_t*)(base + o_cls);
+    t.row_sign = (int8_t*)(base + o_sgn);
+    int* d_status = (int*)(base + o_st);
+    DR_HIP(hipMemsetAsync(d_status, 0, sizeof(int), c->stream));
+    DR_HIP(launch_build_plans(ga, t, d_status, c->stream));
+    int status = 0;
+    DR_HIP(hipMemcpyAsync(&status, d_status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    DR_HIP(hipStreamSynchronize(c->stream));
+    if (status & 1)
+        return set_error(DR_E_INVAL, "geometry gives a non-finite depth (pixel inside the wire "
+                                     "or a ray parallel to the beam)");
+    if (status & 2)
+        return set_error(DR_E_INVAL, "wire not strictly between the beam and the detector in y");
+    for (int i = 0; i < 3; ++i) DR_HIP(hipEventCreate(&g->ev[i]));
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        auto it = c->tune_cache.find(size_class(c, "rows", nx, (int64_t)nx * ny, N, B));
+        if (it != c->tune_cache.end()) {
+            g->tile = it->second;
+            g->tuned = true;
+        }
+    }
+    c->live_geoms++;
+    *out = g.release();
+    return ok();
+}
+
+dr_status dr_geometry_free(dr_geom g)
+{
+    if (!g) return set_error(DR_E_INVAL, "dr_geometry_free: NULL geometry");
+    if (g->inflight.load() != 0)
+        return set_error(DR_E_BUSY, "dr_geometry_free: serving requests still use it");
+    DR_HIP(hipSetDevice(g->ctx->device));
+    DR_HIP(hipDeviceSynchronize());
+    for (int i = 0; i < 3; ++i)
+        if (g->ev[i]) (void)hipEventDestroy(g->ev[i]);
+    g->ctx->live_geoms--;
+    delete g;
+    return ok();
+}
+
+dr_status dr_set_tile(dr_geom g, const dr_tile_config* tile)
+{
+    if (!g) return set_error(DR_E_INVAL, "dr_set_tile: NULL geometry");
+    std::lock_guard<std::mutex> lk(g->mu);
+    if (!tile) {
+        g->forced = false;
+        return ok();
+    }
+    TileCfg t{tile->pixels_per_lane, tile->waves_per_group, tile->prefetch};
+    if (!tile_supported(t) || g->nx % t.ppl != 0)
+        return set_error(DR_E_INVAL, "dr_set_tile: unsupported launch shape for this geometry");
+    g->tile = t;
+    g->forced = true;
+    return ok();
+}
+
+static dr_status reconstruct_device(dr_geom g, const TileCfg& t, const uint16_t* images,
+                                    float* out, float* totals, hipStream_t s)
+{
+    float* part = nullptr;
+    if (totals) {
+        dr_status st = ensure_scratch(g, t, &part);
+        if (st != DR_OK) return st;
+    }
+    ScanArgs a = scan_args(g, t, images, (int64_t)g->nx * g->ny, 0, 0, g->ny, out, part);
+    if (g->timing) DR_HIP(hipEventRecord(g->ev[0], s));
+    DR_HIP(launch_rows_f32(t, a, s));
+    if (g->timing) DR_HIP(hipEventRecord(g->ev[1], s));
+    if (totals)
+        DR_HIP(enqueue_totals(g, part, partial_slots(g, t), g->work.as<double>(), totals, s));
+    if (g->timing) {
+        DR_HIP(hipEventRecord(g->ev[2], s));
+        g->timed = true;
+    }
+    return DR_OK;
+}
+
+static int slab_rows(const dr_geom g)
+{
+    size_t target = (size_t)256 << 20;
+    if (const char* e = std::getenv("DR_SLAB_MB")) target = (size_t)std::max(1, atoi(e)) << 20;
+    const size_t row_bytes = (size_t)g->nx * g->n_steps * sizeof(uint16_t);
+    int r = (int)std::max<size_t>(1, target / row_bytes);
+    if (const char* e = std::getenv("DR_SLAB_ROWS")) r = std::max(1, atoi(e));
+    return std::min(r, g->ny);
+}
+
+// Host images: row slabs of every step copied on the copy stream into two
+// alternating buffers; the kernel of slab s overlaps the copy of slab s+1.
+static dr_status reconstruct_streamed(dr_geom g, const TileCfg& t, const uint16_t* images,
+                                      float* out, float* totals, hipStream_t s)
+{
+    dr_ctx c = g->ctx;
+    float* part = nullptr;
+    if (totals) {
+        dr_status st = ensure_scratch(g, t, &part);
+        if (st != DR_OK) return st;
+    }
+    const int R = slab_rows(g);
+    const size_t slab_bytes = (size_t)R * g->nx * g->n_steps * sizeof(uint16_t);
+    std::lock_guard<std::mutex> lk(c->mu);
+    for (int i = 0; i < 2; ++i) {
+        if (c->slab[i].bytes < slab_bytes) {
+            DR_HIP(hipStreamSynchronize(c->copy));
+            DR_HIP(hipStreamSynchronize(c->stream));
+            DR_HIP(hipDeviceSynchronize());
+            DR_HIP(c->slab[i].reserve(slab_bytes));
+        }
+    }
+    const int64_t plane_in = (int64_t)g->nx * g->ny;
+    int n = 0;
+    for (int r0 = 0; r0 < g->ny; r0 += R, ++n) {
+        const int rs = std::min(R, g->ny - r0);
+        const int b = n & 1;
+        DR_HIP(hipStreamWaitEvent(c->copy, c->slab_free[b], 0));
+        DR_HIP(hipMemcpy2DAsync(c->slab[b].p, (size_t)R * g->nx * sizeof(uint16_t),
+                                images + (int64_t)r0 * g->nx, (size_t)plane_in * sizeof(uint16_t),
+                                (size_t)rs * g->nx * sizeof(uint16_t), (size_t)g->n_steps,
+                                hipMemcpyHostToDevice, c->copy));
+        DR_HIP(hipEventRecord(c->slab_ready[b], c->copy));
+        DR_HIP(hipStreamWaitEvent(s, c->slab_ready[b], 0));
+        ScanArgs a = scan_args(g, t, c->slab[b].as<uint16_t>(), (int64_t)R * g->nx, r0, r0,
+                               r0 + rs, out, part);
+        if (g->timing && n == 0) DR_HIP(hipEventRecord(g->ev[0], s));
+        DR_HIP(launch_rows_f32(t, a, s));
+        DR_HIP(hipEventRecord(c->slab_free[b], s));
+    }
+    if (g->timing) DR_HIP(hipEventRecord(g->ev[1], s));
+    if (totals)
+        DR_HIP(enqueue_totals(g, part, partial_slots(g, t), g->work.as<double>(), totals, s));
+    if (g->timing) {
+        DR_HIP(hipEventRecord(g->ev[2], s));
+        g->timed = true;
+    }
+    return DR_OK;
+}
+
+dr_status dr_reconstruct(dr_geom g, const uint16_t* images, int images_on_device, float* out,
+                         float* totals, void* stream)
+{
+    if (!g || !images || !out) return set_error(DR_E_INVAL, "dr_reconstruct: NULL argument");
+    if (!aligned(out, 4) || (totals && !aligned(totals, 4)) || !aligned(images, 2))
+        return set_error(DR_E_INVAL, "dr_reconstruct: misaligned buffer");
+    DR_HIP(hipSetDevice(g->ctx->device));
+    hipStream_t s = stream ? (hipStream_t)stream : g->ctx->stream;
+    if (images_on_device) {
+        const TileCfg t = choose_tile(g, images, out);
+        dr_status st = reconstruct_device(g, t, images, out, totals, s);
+        return st == DR_OK ? ok() : st;
+    }
+    // slab buffers are our own allocations, aligned for every shape
+    const TileCfg t = choose_tile(g, nullptr, out);
+    dr_status st = reconstruct_streamed(g, t, images, out, totals, s);
+    return st == DR_OK ? ok() : st;
+}
+
+dr_status dr_reconstruct_f64(dr_geom g, const uint16_t* images, double* out, double* totals,
+                             void* stream)
+{
+    if (!g || !images || !out) return set_error(DR_E_INVAL, "dr_reconstruct_f64: NULL argument");
+    if (!aligned(out, 8) || (totals && !aligned(totals, 8)) || !aligned(images, 2))
+        return set_error(DR_E_INVAL, "dr_reconstruct_f64: misaligned buffer");
+    DR_HIP(hipSetDevice(g->ctx->device));
+    hipStream_t s = stream ? (hipStream_t)stream : g->ctx->stream;
+    const TileCfg t{1, 4, 4};
+    double* part = nullptr;
+    if (totals) {
+        std::lock_guard<std::mutex> lk(g->mu);
+        DR_HIP(g->part64.reserve((size_t)partial_slots(g, t) * g->n_bins * sizeof(double)));
+        DR_HIP(g->work.reserve((size_t)kTotalsWorkRows * g->n_bins * sizeof(double)));
+        part = g->part64.as<double>();
+    }
+    ScanArgs a = scan_args(g, t, images, (int64_t)g->nx * g->ny, 0, 0, g->ny, nullptr, nullptr);
+    a.out = out;
+    a.partials = part;
+    DR_HIP(launch_rows_f64(a, s));
+    if (totals)
+        DR_HIP(launch_totals_f64(part, partial_slots(g, t), g->n_bins, g->work.as<double>(),
+                                 kTotalsWorkRows, totals, s));
+    return ok();
+}
+
+dr_status dr_debug_plan(dr_geom g, const int64_t* pixels, int32_t n, int32_t* bins_out,
+                        double* u_out)
+{
+    if (!g || (n > 0 && !pixels)) return set_error(DR_E_INVAL, "dr_debug_plan: NULL argument");
+    if (n < 0) return set_error(DR_E_INVAL, "dr_debug_plan: n < 0");
+    if (n == 0) return ok();
+    const int64_t np = (int64_t)g->nx * g->ny;
+    for (int32_t i = 0; i < n; ++i)
+        if (pixels[i] < 0 || pixels[i] >= np)
+            return set_error(DR_E_INVAL, "dr_debug_plan: pixel index out of range");
+    DR_HIP(hipSetDevice(g->ctx->device));
+    hipStream_t s = g->ctx->stream;
+    DevBuf dp, db, du;
+    const size_t cnt = (size_t)n * g->n_steps;
+    DR_HIP(dp.reserve((size_t)n * sizeof(int64_t)));
+    if (bins_out) DR_HIP(db.reserve(cnt * sizeof(int32_t)));
+    if (u_out) DR_HIP(du.reserve(cnt * sizeof(double)));
+    DR_HIP(hipMemcpyAsync(dp.p, pixels, (size_t)n * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    DR_HIP(launch_debug_plan(g->g, dp.as<int64_t>(), n, db.as<int32_t>(), du.as<double>(), s));
+    if (bins_out)
+        DR_HIP(hipMemcpyAsync(bins_out, db.p, cnt * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    if (u_out) DR_HIP(hipMemcpyAsync(u_out, du.p, cnt * sizeof(double), hipMemcpyDeviceToHost, s));
+    DR_HIP(hipStreamSynchronize(s));
+    return ok();
+}
+
+dr_status dr_enable_timing(dr_geom g, int enable)
+{
+    if (!g) return set_error(DR_E_INVAL, "dr_enable_timing: NULL geometry");
+    g->timing = enable != 0;
+    g->timed = false;
+    return ok();
+}
+
+dr_status dr_last_timing(dr_geom g, double* kernel_ms, double* totals_ms)
+{
+    if (!g) return set_error(DR_E_INVAL, "dr_last_timing: NULL geometry");
+    if (!g->timed) return set_error(DR_E_INVAL, "dr_last_timing: no timed launch yet");
+    DR_HIP(hipEventSynchronize(g->ev[2]));
+    float a = 0.f, b = 0.f;
+    DR_HIP(hipEventElapsedTime(&a, g->ev[0], g->ev[1]));
+    DR_HIP(hipEventElapsedTime(&b, g->ev[1], g->ev[2]));
+    if (kernel_ms) *kernel_ms = a;
+    if (totals_ms) *totals_ms = b;
+    return ok();
+}
+
+dr_status dr_autotune(dr_geom g, const uint16_t* images, float* out, dr_tile_config* chosen)
+{
+    if (!g || !images || !out) return set_error(DR_E_INVAL, "dr_autotune: NULL argument");
+    dr_ctx c = g->ctx;
+    DR_HIP(hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    hipEvent_t e0, e1;
+    DR_HIP(hipEventCreate(&e0));
+    DR_HIP(hipEventCreate(&e1));
+    // totals are part of every call that asks for them; tune with them on
+    DevBuf tot;
+    DR_HIP(tot.reserve((size_t)g->n_bins * sizeof(float)));
+    float best = 1e30f;
+    TileCfg best_t = default_tile(g, images, out);
+    const bool was_timing = g->timing;
+    g->timing = false;
+    for (int i = 0; i < num_tile_variants(); ++i) {
+        const TileCfg t = tile_variant(i);
+        if (!tile_fits(g, t, images, out)) continue;
+        dr_status st = reconstruct_device(g, t, images, out, tot.as<float>(), s);  // warm-up
+        if (st != DR_OK) return st;
+        float ms[3];
+        for (int r = 0; r < 3; ++r) {
+            DR_HIP(hipEventRecord(e0, s));
+            st = reconstruct_device(g, t, images, out, tot.as<float>(), s);
+            if (st != DR_OK) return st;
+            DR_HIP(hipEventRecord(e1, s));
+            DR_HIP(hipEventSynchronize(e1));
+            DR_HIP(hipEventElapsedTime(&ms[r], e0, e1));
+        }
+        std::sort(ms, ms + 3);
+        if (ms[1] < best) {
+            best = ms[1];
+            best_t = t;
+        }
+    }
+    g->timing = was_timing;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        g->tile = best_t;
+        g->tuned = true;
+    }
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        c->tune_cache[size_class(c, "rows", g->nx, (int64_t)g->nx * g->ny, g->n_steps,
+                                 g->n_bins)] = best_t;
+        save_tune_file(c);
+    }
+    if (chosen) *chosen = dr_tile_config{best_t.ppl, best_t.waves, best_t.prefetch, 0};
+    return ok();
+}
+
+// ----------------------------------------------------------------- batches
+
+static dr_status batch_build_args(dr_batch b, const TileCfg& t, int gpc)
+{
+    dr_ctx c = b->ctx;
+    const int n = (int)b->items.size();
+    // work order: most expensive tiles first (longest-processing-time rule);
+    // a tile's cost is its pixels times (steps read + bins written)
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        const dr_geom gx = b->geoms[x], gy = b->geoms[y];
+        const int64_t cx = (int64_t)std::min(tile_width(t), gx->nx) * (gx->n_steps + gx->n_bins);
+        const int64_t cy = (int64_t)std::min(tile_width(t), gy->nx) * (gy->n_steps + gy->n_bins);
+        return cx > cy;
+    });
+    b->part_off.assign(n, 0);
+    b->slots.assign(n, 0);
+    int64_t poff = 0;
+    for (int i = 0; i < n; ++i) {
+        b->slots[i] = b->items[i].totals ? partial_slots(b->geoms[i], t) : 0;
+        b->part_off[i] = poff;
+        poff += b->slots[i] * b->geoms[i]->n_bins;
+    }
+    DR_HIP(b->parts.reserve(std::max<size_t>(4, (size_t)poff * sizeof(float))));
+    int maxB = 1;
+    for (int i = 0; i < n; ++i) maxB = std::max(maxB, b->geoms[i]->n_bins);
+    b->max_bins = maxB;
+    DR_HIP(b->work.reserve((size_t)n * kTotalsWorkRows * maxB * sizeof(double)));
+    std::vector<ScanArgs> args(n);
+    std::vector<int64_t> start(n + 1, 0);
+    for (int w = 0; w < n; ++w) {
+        const int i = order[w];
+        const dr_geom g = b->geoms[i];
+        float* part = b->items[i].totals ? b->parts.as<float>() + b->part_off[i] : nullptr;
+        args[w] = scan_args(g, t, b->items[i].images, (int64_t)g->nx * g->ny, 0, 0, g->ny,
+                            b->items[i].out, part);
+        start[w + 1] = start[w] + (int64_t)g->ny * args[w].tiles_per_row;
+    }
+    DR_HIP(b->scans.reserve(sizeof(ScanArgs) * n));
+    DR_HIP(b->starts.reserve(sizeof(int64_t) * (n + 1)));
+    DR_HIP(b->counter.reserve(sizeof(unsigned long long)));
+    DR_HIP(hipMemcpy(b->scans.p, args.data(), sizeof(ScanArgs) * n, hipMemcpyHostToDevice));
+    DR_HIP(hipMemcpy(b->starts.p, start.data(), sizeof(int64_t) * (n + 1),
+                     hipMemcpyHostToDevice));
+    b->total_tiles = start[n];
+    b->tile = t;
+    b->gpc = gpc;
+    b->groups = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)c->cus * gpc, b->total_tiles));
+    return DR_OK;
+}
+
+static dr_status batch_enqueue(dr_batch b, hipStream_t s)
+{
+    BatchArgs ba{};
+    ba.scans = b->scans.as<ScanArgs>();
+    ba.tile_start = b->starts.as<int64_t>();
+    ba.n_scans = (int)b->items.size();
+    ba.total_tiles = b->total_tiles;
+    ba.counter = b->counter.as<unsigned long long>();
+    DR_HIP(launch_reset_counter(ba.counter, s));
+    DR_HIP(launch_batch_f32(b->tile, ba, b->groups, s));
+    for (size_t i = 0; i < b->items.size(); ++i) {
+        if (!b->items[i].totals) continue;
+        const dr_geom g = b->geoms[i];
+        double* work = b->work.as<double>() + i * (size_t)kTotalsWorkRows * b->max_bins;
+        DR_HIP(launch_totals_f32(b->parts.as<float>() + b->part_off[i], b->slots[i], g->n_bins,
+                                 work, kTotalsWorkRows, b->items[i].totals, s));
+    }
+    return DR_OK;
+}
+
+dr_status dr_batch_create(dr_ctx c, int32_t n, const dr_batch_item* items, int32_t flags,
+                          dr_batch* out)
+{
+    if (!c || !items || !out || n < 1) return set_error(DR_E_INVAL, "dr_batch_create: bad argument");
+    *out = nullptr;
+    auto b = std::make_unique<dr_batch_s>();
+    b->ctx = c;
+    for (int i = 0; i < n; ++i) {
+        const dr_batch_item& it = items[i];
+        if (!it.geom || !it.images || !it.out)
+            return set_error(DR_E_INVAL, "dr_batch_create: NULL item field");
+        if (it.geom->ctx != c)
+            return set_error(DR_E_INVAL, "dr_batch_create: geometry of another context");
+        b->items.push_back(it);
+        b->geoms.push_back(it.geom);
+    }
+    DR_HIP(hipSetDevice(c->device));
+    // launch shapes valid for every scan
+    std::vector<TileCfg> cands;
+    for (int v = 0; v < num_tile_variants(); ++v) {
+        const TileCfg t = tile_variant(v);
+        bool okall = true;
+        for (int i = 0; i < n && okall; ++i)
+            okall = tile_fits(b->geoms[i], t, items[i].images, items[i].out);
+        if (okall) cands.push_back(t);
+    }
+    if (cands.empty()) return set_error(DR_E_INVAL, "dr_batch_create: no launch shape fits");
+    TileCfg t = cands.back();
+    for (const TileCfg& x : cands)
+        if (x.ppl == 4 && x.waves == 4 && x.prefetch == 8) t = x;
+    int gpc = 2;
+    hipStream_t s = c->stream;
+    if (flags & DR_BATCH_AUTOTUNE) {
+        hipEvent_t e0, e1;
+        DR_HIP(hipEventCreate(&e0));
+        DR_HIP(hipEventCreate(&e1));
+        float best = 1e30f;
+        TileCfg bt = t;
+        int bg = gpc;
+        for (const TileCfg& x : cands) {
+            for (int g : {1, 2, 4, 8}) {
+                if (64 * x.waves * g > 2048) continue;  // CU thread limit
+                dr_status st = batch_build_args(b.get(), x, g);
+                if (st != DR_OK) return st;
+                st = batch_enqueue(b.get(), s);  // warm-up
+                if (st != DR_OK) return st;
+                float ms[3];
+                for (int r = 0; r < 3; ++r) {
+                    DR_HIP(hipEventRecord(e0, s));
+                    st = batch_enqueue(b.get(), s);
+                    if (st != DR_OK) return st;
+                    DR_HIP(hipEventRecord(e1, s));
+                    DR_HIP(hipEventSynchronize(e1));
+                    DR_HIP(hipEventElapsedTime(&ms[r], e0, e1));
+                }
+                std::sort(ms, ms + 3);
+                if (ms[1] < best) {
+                    best = ms[1];
+                    bt = x;
+                    bg = g;
+                }
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        t = bt;
+        gpc = bg;
+    }
+    dr_status st = batch_build_args(b.get(), t, gpc);
+    if (st != DR_OK) return st;
+    if (flags & DR_BATCH_GRAPH) {
+        hipStream_t cs;
+        DR_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        DR_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        st = batch_enqueue(b.get(), cs);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(cs, &graph);
+        (void)hipStreamDestroy(cs);
+        if (st != DR_OK) return st;
+        if (e != hipSuccess) return hip_error(e, "hipStreamEndCapture");
+        b->graph = graph;
+        DR_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    }
+    DR_HIP(hipStreamSynchronize(s));
+    c->live_batches++;
+    *out = b.release();
+    return ok();
+}
+
+dr_status dr_batch_run(dr_batch b, void* stream)
+{
+    if (!b) return set_error(DR_E_INVAL, "dr_batch_run: NULL batch");
+    DR_HIP(hipSetDevice(b->ctx->device));
+    hipStream_t s = stream ? (hipStream_t)stream : b->ctx->stream;
+    if (b->exec) {
+        DR_HIP(hipGraphLaunch(b->exec, s));
+        return ok();
+    }
+    dr_status st = batch_enqueue(b, s);
+    return st == DR_OK ? ok() : st;
+}
+
+dr_status dr_batch_tile(dr_batch b, dr_tile_config* tile)
+{
+    if (!b || !tile) return set_error(DR_E_INVAL, "dr_batch_tile: NULL argument");
+    *tile = dr_tile_config{b->tile.ppl, b->tile.waves, b->tile.prefetch, b->gpc};
+    return ok();
+}
+
+dr_status dr_batch_free(dr_batch b)
+{
+    if (!b) return set_error(DR_E_INVAL, "dr_batch_free: NULL batch");
+    DR_HIP(hipSetDevice(b->ctx->device));
+    DR_HIP(hipDeviceSynchronize());
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->ctx->live_batches--;
+    delete b;
+    return ok();
+}
+
+}  // extern "C"

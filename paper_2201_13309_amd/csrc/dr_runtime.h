@@ -1,0 +1,123 @@
+// Host-side objects behind the C ABI (not public).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "dr.h"
+#include "dr_internal.h"
+
+namespace dr {
+
+struct Scheduler;  // dr_serve.cpp
+
+dr_status set_error(dr_status code, const std::string& msg);
+dr_status hip_error(hipError_t e, const char* what);
+
+#define DR_HIP(call)                                                    \
+    do {                                                                \
+        hipError_t _e = (call);                                         \
+        if (_e != hipSuccess) return ::dr::hip_error(_e, #call);        \
+    } while (0)
+
+// Device allocation owned by a host object.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    ~DevBuf() { release(); }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    // grow to at least n bytes (contents are not kept)
+    hipError_t reserve(size_t n)
+    {
+        if (n <= bytes) return hipSuccess;
+        release();
+        hipError_t e = hipMalloc(&p, n);
+        if (e != hipSuccess) {
+            p = nullptr;
+            return e;
+        }
+        bytes = n;
+        return hipSuccess;
+    }
+    template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+}  // namespace dr
+
+struct dr_ctx_s {
+    int device = 0;
+    std::string arch;
+    int cus = 0;
+    size_t budget = 0;
+    hipStream_t stream = nullptr;  // compute stream (default priority)
+    hipStream_t copy = nullptr;    // host-to-device copies
+    std::mutex mu;                 // guards the slab buffers and the tune cache
+    dr::DevBuf slab[2];
+    hipEvent_t slab_ready[2] = {nullptr, nullptr};
+    hipEvent_t slab_free[2] = {nullptr, nullptr};
+    std::map<std::string, dr::TileCfg> tune_cache;
+    std::string tune_file;
+    std::atomic<int> live_geoms{0};
+    std::atomic<int> live_batches{0};
+    dr::Scheduler* sched = nullptr;  // created on the first dr_submit
+};
+
+struct dr_geom_s {
+    dr_ctx ctx = nullptr;
+    int nx = 0, ny = 0, n_steps = 0, n_bins = 0;
+    double radius = 0, first_center = 0, width = 0;
+    bool row_mode = true;
+    dr::GeomArgs g{};
+    dr::PlanTables t{};
+    dr::DevBuf wire, pix, plan;  // plan: all plan tables in one allocation
+    dr::DevBuf part32, part64, work;
+    std::mutex mu;
+    bool forced = false, tuned = false;
+    dr::TileCfg tile{0, 0, 0};
+    bool timing = false, timed = false;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    std::atomic<int> inflight{0};  // serving requests using this geometry
+};
+
+struct dr_batch_s {
+    dr_ctx ctx = nullptr;
+    std::vector<dr_batch_item> items;
+    std::vector<dr_geom> geoms;
+    dr::TileCfg tile{0, 0, 0};
+    int groups = 0;
+    int gpc = 0;
+    int max_bins = 1;
+    dr::DevBuf scans, starts, counter, parts, work;
+    std::vector<int64_t> part_off;  // per item offset into parts (floats)
+    std::vector<int64_t> slots;     // per item partial slots
+    int64_t total_tiles = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace dr {
+
+// Shared helpers (dr_runtime.cpp) used by the scheduler.
+bool tile_fits(const dr_geom g, const TileCfg& t, const void* img, const void* out);
+TileCfg default_tile(const dr_geom g, const void* img, const void* out);
+int64_t partial_slots(const dr_geom g, const TileCfg& t);
+ScanArgs scan_args(const dr_geom g, const TileCfg& t, const uint16_t* img, int64_t img_step,
+                   int row_base, int row_begin, int row_end, float* out, float* partials);
+hipError_t enqueue_totals(const dr_geom g, const float* partials, int64_t slots, double* work,
+                          float* totals, hipStream_t s);
+
+Scheduler* make_scheduler(dr_ctx ctx);
+void destroy_scheduler(Scheduler* s);
+
+}  // namespace dr
