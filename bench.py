@@ -63,11 +63,11 @@ def cpu_baseline(scan, target_s: float):
     import oracle
     cores = min(16, os.cpu_count() or 1)
     det, N = scan.detector, scan.wire.n_steps
-    r0 = det.ny // 2
+    r0 = det.ny // 4
     t0 = time.perf_counter()
-    oracle.reconstruct(scan, row0=r0, nrows=1, nthreads=cores)
-    one = max(time.perf_counter() - t0, 1e-3)
-    rows = int(max(1, min(det.ny - r0, target_s / one)))
+    oracle.reconstruct(scan, row0=r0, nrows=cores, nthreads=cores)  # one row per thread
+    per_row = max(time.perf_counter() - t0, 1e-3) / cores
+    rows = int(max(cores, min(det.ny - r0, target_s / per_row)))
     t0 = time.perf_counter()
     oracle.reconstruct(scan, row0=r0, nrows=rows, nthreads=cores)
     dt = time.perf_counter() - t0
@@ -87,6 +87,11 @@ def main():
     ap.add_argument("--no-e2e", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--workload", default="config3", choices=["config2", "config3"])
+    ap.add_argument("--tile", default=None,
+                    help="force a launch shape 'pixels_per_lane,waves,prefetch' (no autotune)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device-to-device copy of known size (for scaling "
+                         "the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -99,6 +104,16 @@ def main():
 
     dr.load()
     assert torch.cuda.is_available(), "bench needs a GPU"
+    if args.copy_calibration:
+        n = 1 << 30  # 1 GiB of int16 elements = 2 GiB read and 2 GiB written per copy
+        a = torch.ones(n, dtype=torch.int16, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": 2 * n, "copy_calibration_bytes_written": 2 * n,
+                          "copies": 3}), flush=True)
+        return
     gen = synth.config3 if args.workload == "config3" else synth.config2
     s = gen(render_now=False)
     det, grid, N = s.detector, s.grid, s.wire.n_steps
@@ -113,9 +128,14 @@ def main():
     tot = torch.empty((B,), dtype=torch.float32, device="cuda")
     ctx = dr.dr_ctx_create(0, 0)
     g = dr.dr_geometry_init(ctx, det, s.wire, grid)
-    stream = torch.cuda.current_stream()
+    stream = torch.cuda.Stream()  # default priority
+    torch.cuda.set_stream(stream)
     tile = None
-    if not args.no_autotune:
+    if args.tile:
+        tile = tuple(int(x) for x in args.tile.split(",")) + (0,)
+        dr.dr_set_tile(g, tile[:3])
+        log(f"forced launch shape {tile[:3]}")
+    elif not args.no_autotune:
         tile = dr.dr_autotune(g, dev, out)
         log(f"autotuned launch shape (pixels/lane, waves, prefetch): {tile[:3]}")
     for _ in range(args.warmup):

@@ -96,7 +96,7 @@ typedef struct {
 
 /* Launch shape of the reconstruction kernel.  pixels_per_lane in {1,2,4,8},
  * waves_per_group in {2,4}, prefetch (wire steps in flight per lane) in
- * {4,8}; groups_per_cu only matters for persistent (batched) launches.
+ * {4,8,16}; groups_per_cu only matters for persistent (batched) launches.
  * A zero field means "choose". */
 typedef struct {
     int32_t pixels_per_lane, waves_per_group, prefetch, groups_per_cu;
@@ -104,7 +104,9 @@ typedef struct {
 
 /* ------------------------------------------------------------- context */
 
-/* Create a context on HIP device `device`.  hbm_budget_bytes bounds the device
+/* Create a context on HIP device `device`, with its own compute and copy
+ * streams (used by dr_geometry_init, dr_autotune, dr_debug_plan and the
+ * serving scheduler).  hbm_budget_bytes bounds the device
  * memory the serving scheduler may hold for admitted requests (0 = 90% of the
  * free memory at creation).  Errors: DR_E_INVAL (bad device or NULL out),
  * DR_E_DEVICE (HIP failure). */
@@ -157,7 +159,7 @@ dr_status dr_autotune(dr_geom geom, const uint16_t* images_dev, float* out_dev,
  *     it is streamed to the device in row slabs, each slab's copy on the
  *     context's copy stream overlapping the kernel of the previous slab - the
  *     paper's pass-per-row-slab scheme (Sec. III-B) with double buffering.
- * stream is a hipStream_t (NULL = the context's compute stream).  The call
+ * stream is a hipStream_t (NULL = the HIP null stream).  The call
  * returns after enqueueing; buffers must stay valid and unchanged until the
  * stream reaches the end of the enqueued work.  Errors: DR_E_INVAL for NULL
  * or misaligned pointers, DR_E_DEVICE for HIP failures. */
@@ -210,8 +212,9 @@ typedef struct {
 dr_status dr_batch_create(dr_ctx ctx, int32_t n, const dr_batch_item* items, int32_t flags,
                           dr_batch* out);
 
-/* Run the batch on `stream` (NULL = context stream): replays the captured
- * graph when the batch has one.  Returns after enqueueing. */
+/* Run the batch on `stream` (a hipStream_t; NULL = the HIP null stream):
+ * replays the captured graph when the batch has one.  Returns after
+ * enqueueing. */
 dr_status dr_batch_run(dr_batch batch, void* stream);
 
 /* The launch shape the batch uses. */

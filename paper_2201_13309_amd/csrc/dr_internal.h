@@ -8,7 +8,9 @@
 namespace dr {
 
 // Row classes of the per-row bin plan: how the leading edge moves over the scan.
-enum RowClass : int8_t { kRowGeneric = 0, kRowIncreasing = 1, kRowDecreasing = 2 };
+// kRowNarrow is or-ed into a monotone class when no interval of the row
+// touches more than two bins.
+enum RowClass : int8_t { kRowGeneric = 0, kRowIncreasing = 1, kRowDecreasing = 2, kRowNarrow = 8 };
 
 // Plan of the FP64 bin positions of one (row, interval k): the interval
 // [u_k, u_{k+1}] touches bins bl .. bl+nb-1 with positive overlap; the first
@@ -24,6 +26,8 @@ struct PlanTables {
     double* d1;
     int8_t* row_class;  // [ny]
     int8_t* row_sign;   // [ny] leading-edge side s_p (+1 / -1)
+    int32_t* row_lo;    // [ny] first and last bin the row touches (lo > hi: none)
+    int32_t* row_hi;
 };
 
 // One scan as seen by the reconstruction kernels.  The image buffer holds
@@ -50,6 +54,8 @@ struct ScanArgs {
     const double* dm;
     const double* d1;
     const int8_t* row_class;
+    const int32_t* row_lo;
+    const int32_t* row_hi;
 };
 
 // Geometry as seen by the table builder and the debug kernel.

@@ -178,9 +178,46 @@ __global__ __launch_bounds__(256) void build_plans_kernel(GeomArgs g, PlanTables
     const int bad1 = __syncthreads_or(bad & 1) ? 1 : 0;
     const int bad2 = __syncthreads_or(bad & 2) ? 2 : 0;
     bad = bad1 | bad2;
+    // Range of bins the row touches, and a check that a monotone row visits
+    // them contiguously (each interval starts in, or right after, the last bin
+    // of the previous touched interval), which the streaming tile relies on.
+    __shared__ int s_lo, s_hi;
     if (threadIdx.x == 0) {
-        t.row_class[row] = inc ? kRowIncreasing : (dec ? kRowDecreasing : kRowGeneric);
+        s_lo = B;
+        s_hi = -1;
+    }
+    __syncthreads();  // also makes this row's plan entries visible block-wide
+    int lo = B, hi = -1, gap = 0, wide = 0;
+    const int64_t base = (int64_t)row * nint;
+    for (int k = threadIdx.x; k < nint; k += blockDim.x) {
+        const int nb = t.nb[base + k];
+        if (nb == 0) continue;
+        const int bl = t.bl[base + k], bh = bl + nb - 1;
+        wide |= nb > 2;
+        lo = min(lo, bl);
+        hi = max(hi, bh);
+        // nearest touched interval after k
+        for (int k2 = k + 1; k2 < nint; ++k2) {
+            const int nb2 = t.nb[base + k2];
+            if (nb2 == 0) continue;
+            const int bl2 = t.bl[base + k2], bh2 = bl2 + nb2 - 1;
+            if (inc && !(bl2 == bh || bl2 == bh + 1)) gap = 1;
+            if (dec && !(bh2 == bl || bh2 == bl - 1)) gap = 1;
+            break;
+        }
+    }
+    atomicMin(&s_lo, lo);
+    atomicMax(&s_hi, hi);
+    gap = __syncthreads_or(gap);
+    wide = __syncthreads_or(wide);
+    if (threadIdx.x == 0) {
+        int cls = inc ? kRowIncreasing : (dec ? kRowDecreasing : kRowGeneric);
+        if (gap) cls = kRowGeneric;
+        if (cls != kRowGeneric && !wide) cls |= kRowNarrow;
+        t.row_class[row] = (int8_t)cls;
         t.row_sign[row] = (int8_t)s;
+        t.row_lo[row] = s_lo;
+        t.row_hi[row] = s_hi;
         if (bad) atomicOr(status, bad);
     }
 }
@@ -222,12 +259,39 @@ __device__ __forceinline__ void store_bins(Acc* p, const Acc (&a)[PPL])
     }
 }
 
-template <typename Acc>
-__device__ __forceinline__ Acc wave_sum(Acc s)
+// Sum over the 64 lanes of a wave, returned to every lane (deterministic order).
+// FP32: inclusive scan inside each 16-lane row with DPP row shifts, then the
+// row totals carried by row broadcasts; lane 63 ends with the total.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_shift(float v)
+{
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, true));
+}
+
+__device__ __forceinline__ float wave_total(float v)
+{
+    v += dpp_shift<0x111, 0xf>(v);  // row_shr:1
+    v += dpp_shift<0x112, 0xf>(v);  // row_shr:2
+    v += dpp_shift<0x114, 0xf>(v);  // row_shr:4
+    v += dpp_shift<0x118, 0xf>(v);  // row_shr:8
+    v += dpp_shift<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_shift<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+__device__ __forceinline__ double wave_total(double v)
 {
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-    return s;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// `old` with lane `lane` replaced by the uniform value v.
+template <typename T>
+__device__ __forceinline__ T write_lane(T old, T v, int lane)
+{
+    return ((int)(threadIdx.x & 63) == lane) ? v : old;
 }
 
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
@@ -276,10 +340,44 @@ __device__ __forceinline__ void stage_plan(const ScanArgs& a, int row, int kc, i
 __device__ __forceinline__ float madd(float f, float dI, float acc) { return __builtin_fmaf(f, dI, acc); }
 __device__ __forceinline__ double madd(double f, double dI, double acc) { return acc + dI * f; }
 
+// Per-wave partial totals: lane l of `pw` holds the total of bin pbase + l of
+// the current 64-bin window; a window is written to the wave's partial row
+// when the tile moves past it.  Bins are visited monotonically, so each
+// window is written once; windows never visited are written as zeros.
+template <typename Acc>
+struct PartialWindow {
+    Acc* row = nullptr;  // this wave's partial row [B], or null (no totals)
+    int B = 0;
+    int pbase = -1, wfirst = -1;
+    Acc pw = (Acc)0;
+    __device__ __forceinline__ void flush(int lane)
+    {
+        if (pbase >= 0 && pbase + lane < B) row[pbase + lane] = pw;
+    }
+    __device__ __forceinline__ void add(int b, Acc s, int lane)
+    {
+        const int wb = b & ~63;
+        if (wb != pbase) {
+            flush(lane);
+            if (wfirst < 0) wfirst = wb;
+            pbase = wb;
+            pw = (Acc)0;
+        }
+        pw = write_lane(pw, s, b - wb);
+    }
+    __device__ __forceinline__ void finish(int lane)
+    {
+        flush(lane);
+        const int a0 = wfirst < 0 ? B : min(wfirst, pbase), a1 = wfirst < 0 ? -1 : max(wfirst, pbase);
+        for (int wb = 0; wb < B; wb += 64)
+            if ((wb < a0 || wb > a1) && wb + lane < B) row[wb + lane] = (Acc)0;
+    }
+};
+
 // Non-monotone rows: zero the tile's bins, then read-modify-write every
 // contribution in step order (each lane touches only its own pixels).
 template <typename Acc, int PPL, int WAVES>
-__device__ void process_tile_generic(const ScanArgs& a, int row, int tile, PlanLds<Acc>& L)
+__device__ __forceinline__ void process_tile_generic(const ScanArgs& a, int row, int tile, PlanLds<Acc>& L)
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     constexpr int TW = 64 * WAVES * PPL;
@@ -289,9 +387,6 @@ __device__ void process_tile_generic(const ScanArgs& a, int row, int tile, PlanL
     const uint16_t* ip = a.img + (int64_t)(row - a.row_base) * a.img_row + col0;
     Acc* op = (Acc*)a.out + (int64_t)row * a.nx + col0;
     const int64_t plane = a.out_plane;
-    Acc* part = a.partials ? (Acc*)a.partials +
-                                 ((int64_t)(row * a.tiles_per_row + tile) * WAVES + wave) * B
-                           : nullptr;
     if (act)
         for (int b = 0; b < B; ++b)
 #pragma unroll
@@ -319,80 +414,66 @@ __device__ void process_tile_generic(const ScanArgs& a, int row, int tile, PlanL
             }
         }
     }
-    if (part) {
+    if (a.partials) {
+        PartialWindow<Acc> pwin;
+        pwin.row = (Acc*)a.partials + ((int64_t)(row * a.tiles_per_row + tile) * WAVES + wave) * B;
+        pwin.B = B;
         for (int b = 0; b < B; ++b) {
             Acc s = (Acc)0;
             if (act)
 #pragma unroll
                 for (int q = 0; q < PPL; ++q) s += op[(int64_t)b * plane + q];
-            s = wave_sum(s);
-            if (lane == 0) part[b] = s;
+            pwin.add(b, wave_total(s), lane);
         }
+        pwin.finish(lane);
     }
 }
 
 // One tile: PPL adjacent pixels per lane, 64*WAVES lanes, one detector row.
-template <typename Acc, int PPL, int WAVES, int PF>
-__device__ __forceinline__ void process_tile(const ScanArgs& a, int row, int tile,
-                                             PlanLds<Acc>& L)
+// Monotone rows stream the steps once: PF image loads in flight per lane (all
+// unconditional, so the prefetch ring stays in registers), the open bin in
+// registers, each touched bin stored once as soon as the edge has passed it,
+// untouched bins zeroed after the last load.
+template <typename Acc, int PPL, int WAVES, int PF, bool NB2>
+__device__ __forceinline__ void process_tile_mono(const ScanArgs& a, int row, int tile,
+                                                  PlanLds<Acc>& L, int cls)
 {
     using V = typename U16V<PPL>::T;
     constexpr int TW = 64 * WAVES * PPL;
-    const int cls = a.row_class[row];
-    if (cls == kRowGeneric) {
-        process_tile_generic<Acc, PPL, WAVES>(a, row, tile, L);
-        return;
-    }
-    const int dir = (cls == kRowIncreasing) ? 1 : -1;
+    const int dir = ((cls & 3) == kRowIncreasing) ? 1 : -1;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int col0 = tile * TW + tid * PPL;
     const bool act = col0 < a.nx;
     const int N = a.n_steps, B = a.n_bins, nint = N - 1;
-    const V* ip = (const V*)(a.img + (int64_t)(row - a.row_base) * a.img_row + col0);
-    const int64_t vstep = a.img_step / PPL;
-    Acc* op = (Acc*)a.out + (int64_t)row * a.nx + col0;
+    // uniform 64-bit row bases plus 32-bit lane offsets; lanes past the row end
+    // read the row's first pixels and never store
+    const uint16_t* irow = a.img + (int64_t)(row - a.row_base) * a.img_row;
+    const uint32_t ioff = act ? (uint32_t)col0 : 0u;
+    Acc* orow = (Acc*)a.out + (int64_t)row * a.nx;
+    const uint32_t ooff = (uint32_t)col0;
     const int64_t plane = a.out_plane;
-    Acc* part = a.partials ? (Acc*)a.partials +
-                                 ((int64_t)(row * a.tiles_per_row + tile) * WAVES + wave) * B
-                           : nullptr;
+    const int64_t istep = a.img_step;
+    PartialWindow<Acc> pwin;
+    if (a.partials)
+        pwin.row = (Acc*)a.partials + ((int64_t)(row * a.tiles_per_row + tile) * WAVES + wave) * B;
+    pwin.B = B;
 
     auto load = [&](int k) -> V {
-        V v = (V)0;
-        if (act) v = __builtin_nontemporal_load(ip + (int64_t)k * vstep);
-        return v;
+        return __builtin_nontemporal_load((const V*)(irow + (int64_t)k * istep + ioff));
     };
+    auto outp = [&](int b) -> Acc* { return orow + (int64_t)b * plane + ooff; };
     Acc acc[PPL];
 #pragma unroll
     for (int q = 0; q < PPL; ++q) acc[q] = (Acc)0;
-    int cb = -1;                      // open bin (uniform), -1 = none
-    int nxt = dir > 0 ? 0 : B - 1;    // next bin not yet stored (uniform)
+    int cb = -1;  // open bin (uniform), -1 = none
 
-    auto put = [&](int b, const Acc (&v)[PPL]) {
-        if (act) store_bins<Acc, PPL>(op + (int64_t)b * plane, v);
-        if (part) {
+    auto put = [&]() {
+        if (act) store_bins<Acc, PPL>(outp(cb), acc);
+        if (pwin.row) {
             Acc s = (Acc)0;
 #pragma unroll
-            for (int q = 0; q < PPL; ++q) s += v[q];
-            s = wave_sum(s);
-            if (lane == 0) part[b] = s;
-        }
-    };
-    auto put_zero = [&](int b) {
-        Acc z[PPL];
-#pragma unroll
-        for (int q = 0; q < PPL; ++q) z[q] = (Acc)0;
-        if (act) store_bins<Acc, PPL>(op + (int64_t)b * plane, z);
-        if (part && lane == 0) part[b] = (Acc)0;
-    };
-    auto flush = [&]() {
-        if (cb >= 0) {
-            if (dir > 0) {
-                for (int z = nxt; z < cb; ++z) put_zero(z);
-            } else {
-                for (int z = nxt; z > cb; --z) put_zero(z);
-            }
-            put(cb, acc);
-            nxt = cb + dir;
+            for (int q = 0; q < PPL; ++q) s += acc[q];
+            pwin.add(cb, wave_total(act ? s : (Acc)0), lane);
         }
     };
     auto interval = [&](int kk, const V& prev, const V& cur) {
@@ -404,56 +485,91 @@ __device__ __forceinline__ void process_tile(const ScanArgs& a, int row, int til
 #pragma unroll
         for (int q = 0; q < PPL; ++q) dI[q] = (Acc)(pix<PPL>(prev, q) - pix<PPL>(cur, q));
         const int bh = bl + nb - 1;
-        for (int e = 0; e < nb; ++e) {
-            const int b = dir > 0 ? bl + e : bh - e;
-            const Acc f = (b == bl) ? f0 : ((b == bh) ? f1 : fm);
+        auto visit = [&](int b, Acc f) {
             if (b != cb) {
-                flush();
+                if (cb >= 0) put();
                 cb = b;
 #pragma unroll
-                for (int q = 0; q < PPL; ++q) acc[q] = (Acc)0;
-            }
+                for (int q = 0; q < PPL; ++q) acc[q] = madd(f, dI[q], (Acc)0);
+            } else {
 #pragma unroll
-            for (int q = 0; q < PPL; ++q) acc[q] = madd(f, dI[q], acc[q]);
+                for (int q = 0; q < PPL; ++q) acc[q] = madd(f, dI[q], acc[q]);
+            }
+        };
+        if constexpr (NB2) {
+            // at most two bins: straight-line code keeps the load pipeline
+            // analysable (no loop with stores between a load and its use)
+            if (dir > 0) {
+                visit(bl, f0);
+                if (nb == 2) visit(bh, f1);
+            } else {
+                visit(bh, f1);
+                if (nb == 2) visit(bl, f0);
+            }
+        } else {
+            int b = dir > 0 ? bl : bh;
+            for (int e = 0; e < nb; ++e, b += dir) visit(b, (b == bl) ? f0 : ((b == bh) ? f1 : fm));
         }
     };
 
-    V prev = load(0);
-    V ring[PF];
+    // Ring of U = PF+1 image slots consumed in place: interval k reads slots
+    // k % U (step k) and (k+1) % U (step k+1), then slot k % U is refilled
+    // with step k + U.  Steps past the end re-read the last image (unused).
+    constexpr int U = PF + 1;
+    constexpr int KCU = (kPlanChunk / U) * U;  // plan chunk, a whole number of rings
+    V ring[U];
 #pragma unroll
-    for (int d = 0; d < PF; ++d) ring[d] = (1 + d < N) ? load(1 + d) : (V)0;
+    for (int d = 0; d < U; ++d) ring[d] = load(min(d, N - 1));
 
-    for (int kc = 0; kc < nint; kc += kPlanChunk) {
-        const int nk = min(kPlanChunk, nint - kc);
+    for (int kc = 0; kc < nint; kc += KCU) {
+        const int nk = min(KCU, nint - kc);
         __syncthreads();
         stage_plan<Acc>(a, row, kc, nk, L);
         __syncthreads();
         int kk = 0;
-        for (; kk + PF <= nk; kk += PF) {
+        for (; kk + U <= nk; kk += U) {
 #pragma unroll
-            for (int d = 0; d < PF; ++d) {
-                const V cur = ring[d];
-                const int kn = kc + kk + d + 1 + PF;
-                if (kn < N) ring[d] = load(kn);
-                interval(kk + d, prev, cur);
-                prev = cur;
+            for (int d = 0; d < U; ++d) {
+                interval(kk + d, ring[d], ring[(d + 1) % U]);
+                ring[d] = load(min(kc + kk + d + U, N - 1));
             }
         }
 #pragma unroll
-        for (int d = 0; d < PF; ++d) {
+        for (int d = 0; d < U; ++d) {
             if (kk + d < nk) {
-                const V cur = ring[d];
-                interval(kk + d, prev, cur);
-                prev = cur;
+                interval(kk + d, ring[d], ring[(d + 1) % U]);
+                ring[d] = load(min(kc + kk + d + U, N - 1));
             }
         }
     }
-    flush();
-    if (dir > 0) {
-        for (int z = nxt; z < B; ++z) put_zero(z);
-    } else {
-        for (int z = nxt; z >= 0; --z) put_zero(z);
+    if (cb >= 0) put();
+    // bins outside the row's touched range are zero; stored after the last load
+    const int blo = a.row_lo[row], bhi = a.row_hi[row];
+    if (act) {
+        Acc z[PPL];
+#pragma unroll
+        for (int q = 0; q < PPL; ++q) z[q] = (Acc)0;
+        if (blo > bhi) {
+            for (int b = 0; b < B; ++b) store_bins<Acc, PPL>(outp(b), z);
+        } else {
+            for (int b = 0; b < blo; ++b) store_bins<Acc, PPL>(outp(b), z);
+            for (int b = bhi + 1; b < B; ++b) store_bins<Acc, PPL>(outp(b), z);
+        }
     }
+    if (pwin.row) pwin.finish(lane);
+}
+
+template <typename Acc, int PPL, int WAVES, int PF>
+__device__ __forceinline__ void process_tile(const ScanArgs& a, int row, int tile,
+                                             PlanLds<Acc>& L)
+{
+    const int cls = a.row_class[row];
+    if (cls == kRowGeneric)
+        process_tile_generic<Acc, PPL, WAVES>(a, row, tile, L);
+    else if (cls & kRowNarrow)
+        process_tile_mono<Acc, PPL, WAVES, PF, true>(a, row, tile, L, cls);
+    else  // intervals wider than two bins: rare, a short prefetch suffices
+        process_tile_mono<Acc, PPL, WAVES, (PF < 4 ? PF : 4), false>(a, row, tile, L, cls);
 }
 
 template <int PPL, int WAVES, int PF>
@@ -549,10 +665,10 @@ __global__ __launch_bounds__(64) void debug_plan_kernel(GeomArgs g, const int64_
 // ---------------------------------------------------------- launch wrappers
 
 static const TileCfg kVariants[] = {
-    {1, 2, 4}, {1, 2, 8}, {1, 4, 4}, {1, 4, 8},
-    {2, 2, 4}, {2, 2, 8}, {2, 4, 4}, {2, 4, 8},
-    {4, 2, 4}, {4, 2, 8}, {4, 4, 4}, {4, 4, 8},
-    {8, 2, 4}, {8, 2, 8}, {8, 4, 4}, {8, 4, 8},
+    {1, 2, 4}, {1, 2, 8}, {1, 2, 16}, {1, 4, 4}, {1, 4, 8}, {1, 4, 16},
+    {2, 2, 4}, {2, 2, 8}, {2, 2, 16}, {2, 4, 4}, {2, 4, 8}, {2, 4, 16},
+    {4, 2, 4}, {4, 2, 8}, {4, 2, 16}, {4, 4, 4}, {4, 4, 8}, {4, 4, 16},
+    {8, 2, 4}, {8, 2, 8}, {8, 2, 16}, {8, 4, 4}, {8, 4, 8}, {8, 4, 16},
 };
 
 int num_tile_variants() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
@@ -567,28 +683,26 @@ bool tile_supported(const TileCfg& t)
 
 int tile_width(const TileCfg& t) { return 64 * t.waves * t.ppl; }
 
-#define DR_DISPATCH(T, KERNEL, GRID, ARGS, STREAM)                                            \
-    do {                                                                                      \
-        const dim3 blk(64 * (T).waves);                                                       \
-        switch ((T).ppl * 100 + (T).waves * 10 + (T).prefetch / 4) {                          \
-        case 121: hipLaunchKernelGGL((KERNEL<1, 2, 4>), GRID, blk, 0, STREAM, ARGS); break;   \
-        case 122: hipLaunchKernelGGL((KERNEL<1, 2, 8>), GRID, blk, 0, STREAM, ARGS); break;   \
-        case 141: hipLaunchKernelGGL((KERNEL<1, 4, 4>), GRID, blk, 0, STREAM, ARGS); break;   \
-        case 142: hipLaunchKernelGGL((KERNEL<1, 4, 8>), GRID, blk, 0, STREAM, ARGS); break;   \
-        case 221: hipLaunchKernelGGL((KERNEL<2, 2, 4>), GRID, blk, 0, STREAM, ARGS); break;   \
-        case 222: hipLaunchKernelGGL((KERNEL<2, 2, 8>), GRID, blk, 0, STREAM, ARGS); break;   \
-        case 241: hipLaunchKernelGGL((KERNEL<2, 4, 4>), GRID, blk, 0, STREAM, ARGS); break;   \
-        case 242: hipLaunchKernelGGL((KERNEL<2, 4, 8>), GRID, blk, 0, STREAM, ARGS); break;   \
-        case 421: hipLaunchKernelGGL((KERNEL<4, 2, 4>), GRID, blk, 0, STREAM, ARGS); break;   \
-        case 422: hipLaunchKernelGGL((KERNEL<4, 2, 8>), GRID, blk, 0, STREAM, ARGS); break;   \
-        case 441: hipLaunchKernelGGL((KERNEL<4, 4, 4>), GRID, blk, 0, STREAM, ARGS); break;   \
-        case 442: hipLaunchKernelGGL((KERNEL<4, 4, 8>), GRID, blk, 0, STREAM, ARGS); break;   \
-        case 821: hipLaunchKernelGGL((KERNEL<8, 2, 4>), GRID, blk, 0, STREAM, ARGS); break;   \
-        case 822: hipLaunchKernelGGL((KERNEL<8, 2, 8>), GRID, blk, 0, STREAM, ARGS); break;   \
-        case 841: hipLaunchKernelGGL((KERNEL<8, 4, 4>), GRID, blk, 0, STREAM, ARGS); break;   \
-        case 842: hipLaunchKernelGGL((KERNEL<8, 4, 8>), GRID, blk, 0, STREAM, ARGS); break;   \
-        default: return hipErrorInvalidValue;                                                 \
-        }                                                                                     \
+#define DR_CASE(KERNEL, P, W, F, GRID, ARGS, STREAM)                                \
+    case P * 1000 + W * 100 + F:                                                    \
+        hipLaunchKernelGGL((KERNEL<P, W, F>), GRID, dim3(64 * W), 0, STREAM, ARGS); \
+        break;
+#define DR_CASES_P(KERNEL, P, GRID, ARGS, STREAM)        \
+    DR_CASE(KERNEL, P, 2, 4, GRID, ARGS, STREAM)         \
+    DR_CASE(KERNEL, P, 2, 8, GRID, ARGS, STREAM)         \
+    DR_CASE(KERNEL, P, 2, 16, GRID, ARGS, STREAM)        \
+    DR_CASE(KERNEL, P, 4, 4, GRID, ARGS, STREAM)         \
+    DR_CASE(KERNEL, P, 4, 8, GRID, ARGS, STREAM)         \
+    DR_CASE(KERNEL, P, 4, 16, GRID, ARGS, STREAM)
+#define DR_DISPATCH(T, KERNEL, GRID, ARGS, STREAM)                   \
+    do {                                                             \
+        switch ((T).ppl * 1000 + (T).waves * 100 + (T).prefetch) {   \
+            DR_CASES_P(KERNEL, 1, GRID, ARGS, STREAM)                \
+            DR_CASES_P(KERNEL, 2, GRID, ARGS, STREAM)                \
+            DR_CASES_P(KERNEL, 4, GRID, ARGS, STREAM)                \
+            DR_CASES_P(KERNEL, 8, GRID, ARGS, STREAM)                \
+        default: return hipErrorInvalidValue;                        \
+        }                                                            \
     } while (0)
 
 hipError_t launch_build_plans(const GeomArgs& g, const PlanTables& t, int* d_status,

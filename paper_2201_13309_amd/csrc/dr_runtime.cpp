@@ -53,10 +53,10 @@ bool tile_fits(const dr_geom g, const TileCfg& t, const void* img, const void* o
 
 TileCfg default_tile(const dr_geom g, const void* img, const void* out)
 {
-    static const TileCfg prefs[] = {{4, 4, 8}, {2, 4, 8}, {1, 4, 8}};
+    static const TileCfg prefs[] = {{2, 4, 16}, {1, 4, 16}};
     for (const TileCfg& t : prefs)
         if (tile_fits(g, t, img, out)) return t;
-    return TileCfg{1, 4, 8};
+    return TileCfg{1, 4, 16};
 }
 
 static int tiles_per_row(const dr_geom g, const TileCfg& t)
@@ -97,6 +97,8 @@ ScanArgs scan_args(const dr_geom g, const TileCfg& t, const uint16_t* img, int64
     a.dm = g->t.dm;
     a.d1 = g->t.d1;
     a.row_class = g->t.row_class;
+    a.row_lo = g->t.row_lo;
+    a.row_hi = g->t.row_hi;
     return a;
 }
 
@@ -342,7 +344,8 @@ dr_status dr_geometry_init(dr_ctx c, const dr_detector* det, const dr_wire* wire
     const size_t o_bl = 0, o_nb = o_bl + up(ent * 4), o_f0 = o_nb + up(ent * 4),
                  o_fm = o_f0 + up(ent * 4), o_f1 = o_fm + up(ent * 4), o_d0 = o_f1 + up(ent * 4),
                  o_dm = o_d0 + up(ent * 8), o_d1 = o_dm + up(ent * 8), o_cls = o_d1 + up(ent * 8),
-                 o_sgn = o_cls + up(ny), o_st = o_sgn + up(ny), total = o_st + 256;
+                 o_sgn = o_cls + up(ny), o_lo = o_sgn + up(ny), o_hi = o_lo + up((size_t)ny * 4),
+                 o_st = o_hi + up((size_t)ny * 4), total = o_st + 256;
     DR_HIP(g->plan.reserve(total));
     char* base = g->plan.as<char>();
     PlanTables& t = g->t;
@@ -356,6 +359,8 @@ dr_status dr_geometry_init(dr_ctx c, const dr_detector* det, const dr_wire* wire
     t.d1 = (double*)(base + o_d1);
     t.row_class = (int8_t*)(base + o_cls);
     t.row_sign = (int8_t*)(base + o_sgn);
+    t.row_lo = (int32_t*)(base + o_lo);
+    t.row_hi = (int32_t*)(base + o_hi);
     int* d_status = (int*)(base + o_st);
     DR_HIP(hipMemsetAsync(d_status, 0, sizeof(int), c->stream));
     DR_HIP(launch_build_plans(ga, t, d_status, c->stream));
@@ -499,7 +504,7 @@ dr_status dr_reconstruct(dr_geom g, const uint16_t* images, int images_on_device
     if (!aligned(out, 4) || (totals && !aligned(totals, 4)) || !aligned(images, 2))
         return set_error(DR_E_INVAL, "dr_reconstruct: misaligned buffer");
     DR_HIP(hipSetDevice(g->ctx->device));
-    hipStream_t s = stream ? (hipStream_t)stream : g->ctx->stream;
+    hipStream_t s = (hipStream_t)stream;  // NULL is the null stream
     if (images_on_device) {
         const TileCfg t = choose_tile(g, images, out);
         dr_status st = reconstruct_device(g, t, images, out, totals, s);
@@ -518,7 +523,7 @@ dr_status dr_reconstruct_f64(dr_geom g, const uint16_t* images, double* out, dou
     if (!aligned(out, 8) || (totals && !aligned(totals, 8)) || !aligned(images, 2))
         return set_error(DR_E_INVAL, "dr_reconstruct_f64: misaligned buffer");
     DR_HIP(hipSetDevice(g->ctx->device));
-    hipStream_t s = stream ? (hipStream_t)stream : g->ctx->stream;
+    hipStream_t s = (hipStream_t)stream;  // NULL is the null stream
     const TileCfg t{1, 4, 4};
     double* part = nullptr;
     if (totals) {
@@ -739,7 +744,7 @@ dr_status dr_batch_create(dr_ctx c, int32_t n, const dr_batch_item* items, int32
     if (cands.empty()) return set_error(DR_E_INVAL, "dr_batch_create: no launch shape fits");
     TileCfg t = cands.back();
     for (const TileCfg& x : cands)
-        if (x.ppl == 4 && x.waves == 4 && x.prefetch == 8) t = x;
+        if (x.ppl == 2 && x.waves == 4 && x.prefetch == 16) t = x;
     int gpc = 2;
     hipStream_t s = c->stream;
     if (flags & DR_BATCH_AUTOTUNE) {
@@ -803,7 +808,7 @@ dr_status dr_batch_run(dr_batch b, void* stream)
 {
     if (!b) return set_error(DR_E_INVAL, "dr_batch_run: NULL batch");
     DR_HIP(hipSetDevice(b->ctx->device));
-    hipStream_t s = stream ? (hipStream_t)stream : b->ctx->stream;
+    hipStream_t s = (hipStream_t)stream;  // NULL is the null stream
     if (b->exec) {
         DR_HIP(hipGraphLaunch(b->exec, s));
         return ok();

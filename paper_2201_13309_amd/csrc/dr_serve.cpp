@@ -42,7 +42,7 @@ struct Request {
     float* out = nullptr;
     float* totals = nullptr;
     size_t footprint = 0;
-    TileCfg tile{4, 4, 8};
+    TileCfg tile{4, 4, 16};
     uint16_t* staged = nullptr;        // device copy of host images
     float* parts = nullptr;
     double* work = nullptr;
@@ -285,7 +285,7 @@ struct Scheduler {
             ba.n_scans = nseg[gi];
             ba.total_tiles = tiles[gi];
             ba.counter = d_cnt + gi;
-            const TileCfg t{kPpl[gi], 4, 8};
+            const TileCfg t{kPpl[gi], 4, 16};
             const int groups = (int)std::max<int64_t>(1, std::min<int64_t>(ctx->cus * 2, tiles[gi]));
             e = launch_reset_counter(ba.counter, s);
             if (e == hipSuccess) e = launch_batch_f32(t, ba, groups, s);
@@ -452,7 +452,7 @@ dr_status dr_submit(dr_ctx c, dr_geom g, const uint16_t* images, int images_on_d
     r->totals = totals;
     r->tile = default_tile(g, r->on_device ? (const void*)images : nullptr, out);
     r->tile.waves = 4;
-    r->tile.prefetch = 8;
+    r->tile.prefetch = 16;
     if (!tile_fits(g, r->tile, r->on_device ? (const void*)images : nullptr, out))
         return set_error(DR_E_INVAL, "dr_submit: misaligned buffer");
     r->footprint = Scheduler::staging_bytes(r.get()) + Scheduler::parts_bytes(r.get());
