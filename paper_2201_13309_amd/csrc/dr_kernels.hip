@@ -24,7 +24,36 @@
 
 #pragma clang fp contract(off)
 
+// Cache policy of the streaming accesses (each image element is read once and
+// each bin written once): 1 = non-temporal, 0 = default.
+#ifndef DR_NT_LOADS
+#define DR_NT_LOADS 1
+#endif
+#ifndef DR_NT_STORES
+#define DR_NT_STORES 1
+#endif
+
 namespace dr {
+
+template <typename T>
+__device__ __forceinline__ void stream_store(T v, T* p)
+{
+#if DR_NT_STORES
+    __builtin_nontemporal_store(v, p);
+#else
+    *p = v;
+#endif
+}
+
+template <typename T>
+__device__ __forceinline__ T stream_load(const T* p)
+{
+#if DR_NT_LOADS
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
 
 // ------------------------------------------------------------- FP64 geometry
 
@@ -246,15 +275,15 @@ __device__ __forceinline__ void store_bins(Acc* p, const Acc (&a)[PPL])
 {
     if constexpr (sizeof(Acc) == 8 || PPL == 1) {
 #pragma unroll
-        for (int q = 0; q < PPL; ++q) __builtin_nontemporal_store(a[q], p + q);
+        for (int q = 0; q < PPL; ++q) stream_store(a[q], p + q);
     } else if constexpr (PPL == 2) {
         f32x2 v = {a[0], a[1]};
-        __builtin_nontemporal_store(v, (f32x2*)p);
+        stream_store(v, (f32x2*)p);
     } else {
 #pragma unroll
         for (int q = 0; q < PPL; q += 4) {
             f32x4 v = {a[q], a[q + 1], a[q + 2], a[q + 3]};
-            __builtin_nontemporal_store(v, (f32x4*)(p + q));
+            stream_store(v, (f32x4*)(p + q));
         }
     }
 }
@@ -459,7 +488,7 @@ __device__ __forceinline__ void process_tile_mono(const ScanArgs& a, int row, in
     pwin.B = B;
 
     auto load = [&](int k) -> V {
-        return __builtin_nontemporal_load((const V*)(irow + (int64_t)k * istep + ioff));
+        return stream_load((const V*)(irow + (int64_t)k * istep + ioff));
     };
     auto outp = [&](int b) -> Acc* { return orow + (int64_t)b * plane + ooff; };
     Acc acc[PPL];
