@@ -46,16 +46,21 @@ def algorithmic_bytes(nx, ny, n_steps, n_bins):
     return 2 * P * n_steps + 4 * P * n_bins + 20 * ny * (n_steps - 1) + 4 * n_bins
 
 
-def measured_traffic(digest: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, when
-    it was taken on the current kernel source."""
-    p = os.path.join(ROOT, "profiles", "traffic_rows_f32_config3.json")
-    if not os.path.exists(p):
+def measured_traffic(digest: str, shape):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, used
+    only when it was taken on the current kernel source and launch shape."""
+    p = os.path.join(ROOT, "profiles", "traffic_rows_f32_config3.txt")
+    if not os.path.exists(p) or shape is None:
         return None
-    d = json.load(open(p))
-    if d.get("kernel_source_sha256_16") != digest:
+    d = {}
+    for line in open(p):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            d[k.strip()] = v.strip()
+    want = "rows_f32_kernel<%d, %d, %d>" % tuple(shape[:3])
+    if d.get("kernel_source_sha256_16") != digest or want not in d.get("kernel", ""):
         return None
-    return d.get("hbm_bytes_per_launch")
+    return float(d["hbm_bytes_per_launch"])
 
 
 def cpu_baseline(scan, target_s: float):
@@ -322,7 +327,7 @@ def main():
     alg = algorithmic_bytes(nx, ny, N, B)
     achieved = alg / (k_avg * 1e-3) / 1e9
     digest = kernel_source_digest()
-    traffic = measured_traffic(digest)
+    traffic = measured_traffic(digest, tile)
     work = nx * ny * N
     result = {
         "metric": METRIC,
