@@ -45,13 +45,13 @@ def load(path: Optional[str] = None):
         lib.oracle_tangent_depth.restype = d
         lib.oracle_edge_sign.argtypes = [d, d, i32, p, d]
         lib.oracle_edge_sign.restype = i32
-        lib.oracle_bin_profile.argtypes = [p, p, i32, i32, p, i64]
+        lib.oracle_bin_profile.argtypes = [p, p, i32, i32, i32, p, i64]
         lib.oracle_bin_profile.restype = None
-        lib.oracle_reconstruct.argtypes = [i32, i32, p, p, p, p, d, i32, p, i32, d, d, p,
+        lib.oracle_reconstruct.argtypes = [i32, i32, p, p, p, p, d, i32, p, i32, d, d, i32, p,
                                            i32, i32, p, p, p, i32]
         lib.oracle_reconstruct.restype = i32
         lib.oracle_reconstruct_pixels.argtypes = [i32, i32, p, p, p, p, d, i32, p, i32, d, d,
-                                                  p, p, p, i64, p, p, p, i32]
+                                                  i32, p, p, p, i64, p, p, p, i32]
         lib.oracle_reconstruct_pixels.restype = i32
         _libs[path] = lib
     return _libs[path]
@@ -79,13 +79,18 @@ def edge_sign(py, pz, centers, r, lib=None) -> int:
     return (lib or load()).oracle_edge_sign(float(py), float(pz), c.shape[0], _p(c), float(r))
 
 
-def bin_profile(u, intensities, n_bins: int, lib=None) -> np.ndarray:
-    """Binning of one pixel given its positions u_k (bin units) and counts."""
+EDGE_LEADING, EDGE_TRAILING, EDGE_BOTH = 0, 1, 2
+
+
+def bin_profile(u, intensities, n_bins: int, trailing: bool = False, lib=None) -> np.ndarray:
+    """Binning of one pixel given its positions u_k (bin units) and counts;
+    trailing=True takes dI_k = I_{k+1} - I_k."""
     u = _f64(u)
     I = _f64(intensities)
     assert u.shape == I.shape and u.ndim == 1
     out = np.zeros(n_bins, dtype=np.float64)
-    (lib or load()).oracle_bin_profile(_p(u), _p(I), u.shape[0], int(n_bins), _p(out), 1)
+    (lib or load()).oracle_bin_profile(_p(u), _p(I), u.shape[0], int(n_bins), 1 if trailing else 0,
+                                       _p(out), 1)
     return out
 
 
@@ -97,7 +102,7 @@ def _geom_args(scan):
     keep = (origin, u, v, pxyz, centers)
     args = (int(det.nx), int(det.ny), _p(origin), _p(u), _p(v), _p(pxyz), float(wire.radius),
             int(centers.shape[0]), _p(centers), int(grid.n_bins), float(grid.first_center),
-            float(grid.width))
+            float(grid.width), int(getattr(wire, "edge", EDGE_LEADING)))
     return args, keep
 
 

@@ -22,7 +22,11 @@
  *              with a = C - P, L2 = |a|^2, kk = sqrt(L2 - r^2),
  *              tz = az*kk - ay*s*r, ty = ay*kk + az*s*r.
  *   edge       s_p = +1 when that +z-side depth moves toward +z over the scan
- *              (last step vs first step), else -1; the leading edge uses s_p.
+ *              (last step vs first step), else -1.  The leading edge uses
+ *              side s_p and dI_k = I_k - I_{k+1} (intensity lost as the edge
+ *              covers the slice); the trailing edge uses side -s_p and
+ *              dI_k = I_{k+1} - I_k (intensity regained as it uncovers it);
+ *              "both" is the average of the two reconstructions.
  *   binning    u_k = (d_k - e0) * (1/width), e0 = first_center - width/2.
  *              For k = 0..N-2 the difference dI_k = I_k - I_{k+1} is spread
  *              over [lo, hi] = [min, max](u_k, u_{k+1}): bin b gets
@@ -49,6 +53,10 @@
 
 #define ORACLE_OK 0
 #define ORACLE_EINVAL (-1)
+
+#define EDGE_LEADING 0
+#define EDGE_TRAILING 1
+#define EDGE_BOTH 2
 
 /* Depth at which the ray from (py, pz), tangent to the wire disc centred at
  * (cy, cz) on side s, meets the beam.  Returns NAN when the pixel is inside
@@ -99,12 +107,14 @@ static int32_t floor_to_i32(double x)
     return (int32_t)f;
 }
 
-/* Positions u_k of the leading edge in bin units for one pixel.  Returns
- * ORACLE_EINVAL if the pixel is inside the wire or a value is not finite. */
+/* Positions u_k of one edge (leading, or trailing when `trailing` is set) in
+ * bin units for one pixel.  Returns ORACLE_EINVAL if the pixel is inside the
+ * wire or a value is not finite. */
 static int pixel_positions(double py, double pz, int n_steps, const double* centers, double r,
-                           double e0, double invw, double* u)
+                           double e0, double invw, int trailing, double* u)
 {
     int s = oracle_edge_sign(py, pz, n_steps, centers, r);
+    if (trailing) s = -s;
     for (int k = 0; k < n_steps; ++k) {
         double d = oracle_tangent_depth(py, pz, centers[3 * k + 1], centers[3 * k + 2], r, s);
         u[k] = (d - e0) * invw;
@@ -114,15 +124,16 @@ static int pixel_positions(double py, double pz, int n_steps, const double* cent
 }
 
 /* Spread the intensity differences of one pixel over the depth bins.
- *   u      [n_steps] leading-edge positions in bin units
- *   I      [n_steps] intensities (counts), read as doubles
- *   out    [n_bins] accumulated in place (caller zeroes it)
- *   stride distance between consecutive bins of out */
-void oracle_bin_profile(const double* u, const double* I, int n_steps, int n_bins,
+ *   u        [n_steps] edge positions in bin units
+ *   I        [n_steps] intensities (counts), read as doubles
+ *   trailing 0: dI_k = I_k - I_{k+1}; 1: dI_k = I_{k+1} - I_k
+ *   out      [n_bins] accumulated in place (caller zeroes it)
+ *   stride   distance between consecutive bins of out */
+void oracle_bin_profile(const double* u, const double* I, int n_steps, int n_bins, int trailing,
                         double* out, int64_t stride)
 {
     for (int k = 0; k + 1 < n_steps; ++k) {
-        double dI = I[k] - I[k + 1];
+        double dI = trailing ? I[k + 1] - I[k] : I[k] - I[k + 1];
         double lo = u[k] < u[k + 1] ? u[k] : u[k + 1];
         double hi = u[k] < u[k + 1] ? u[k + 1] : u[k];
         double len = hi - lo;
@@ -143,22 +154,50 @@ void oracle_bin_profile(const double* u, const double* I, int n_steps, int n_bin
     }
 }
 
+/* Profile of one pixel for edge LEADING, TRAILING or BOTH into o (stride
+ * between bins; the caller zeroes it).  uk [n_steps] and tmp [n_bins] are
+ * scratch; the positions of the reported edge (trailing for TRAILING, else
+ * leading) are left in uk. */
+static int pixel_profile(double py, double pz, const double* Ik, int n_steps,
+                         const double* centers, double r, double e0, double invw, int n_bins,
+                         int edge, double* o, int64_t stride, double* uk, double* tmp)
+{
+    if (edge == EDGE_BOTH) {
+        if (pixel_positions(py, pz, n_steps, centers, r, e0, invw, 1, uk) != ORACLE_OK)
+            return ORACLE_EINVAL;
+        for (int b = 0; b < n_bins; ++b) tmp[b] = 0.0;
+        oracle_bin_profile(uk, Ik, n_steps, n_bins, 1, tmp, 1);
+        if (pixel_positions(py, pz, n_steps, centers, r, e0, invw, 0, uk) != ORACLE_OK)
+            return ORACLE_EINVAL;
+        oracle_bin_profile(uk, Ik, n_steps, n_bins, 0, o, stride);
+        for (int b = 0; b < n_bins; ++b) o[(int64_t)b * stride] = 0.5 * (o[(int64_t)b * stride] + tmp[b]);
+        return ORACLE_OK;
+    }
+    const int trailing = edge == EDGE_TRAILING;
+    if (pixel_positions(py, pz, n_steps, centers, r, e0, invw, trailing, uk) != ORACLE_OK)
+        return ORACLE_EINVAL;
+    oracle_bin_profile(uk, Ik, n_steps, n_bins, trailing, o, stride);
+    return ORACLE_OK;
+}
+
 /*
  * Full reconstruction of detector rows [row0, row0 + nrows).
+ *   edge    EDGE_LEADING, EDGE_TRAILING or EDGE_BOTH
  *   images  [n_steps][ny][nx] uint16, step slowest
  *   out     [n_bins][nrows][nx] FP64, overwritten
  *   totals  [n_bins] FP64 sums over the processed pixels, or NULL
- *   bins    [nrows*nx][n_steps] int32 floor(u_k), or NULL
+ *   bins    [nrows*nx][n_steps] int32 floor(u_k) of the reported edge, or NULL
  * Returns ORACLE_OK or ORACLE_EINVAL.
  */
 int oracle_reconstruct(int nx, int ny, const double* origin, const double* u, const double* v,
                        const double* pixel_xyz, double radius, int n_steps, const double* centers,
-                       int n_bins, double first_center, double width, const uint16_t* images,
-                       int row0, int nrows, double* out, double* totals, int32_t* bins,
-                       int nthreads)
+                       int n_bins, double first_center, double width, int edge,
+                       const uint16_t* images, int row0, int nrows, double* out, double* totals,
+                       int32_t* bins, int nthreads)
 {
     if (nx <= 0 || ny <= 0 || n_steps < 2 || n_bins <= 0 || !(width > 0.0) || !(radius > 0.0))
         return ORACLE_EINVAL;
+    if (edge < EDGE_LEADING || edge > EDGE_BOTH) return ORACLE_EINVAL;
     if (row0 < 0 || nrows < 0 || row0 + nrows > ny) return ORACLE_EINVAL;
     const double e0 = first_center - width / 2.0;
     const double invw = 1.0 / width;
@@ -176,6 +215,7 @@ int oracle_reconstruct(int nx, int ny, const double* origin, const double* u, co
     {
         double* uk = (double*)malloc(sizeof(double) * (size_t)n_steps);
         double* Ik = (double*)malloc(sizeof(double) * (size_t)n_steps);
+        double* tmp = (double*)malloc(sizeof(double) * (size_t)n_bins);
 #pragma omp for schedule(dynamic, 1)
         for (int jr = 0; jr < nrows; ++jr) {
             for (int i = 0; i < nx; ++i) {
@@ -183,19 +223,20 @@ int oracle_reconstruct(int nx, int ny, const double* origin, const double* u, co
                 int64_t q = (int64_t)jr * nx + i;
                 double py, pz;
                 pixel_center(nx, origin, u, v, pixel_xyz, p, &py, &pz);
-                if (pixel_positions(py, pz, n_steps, centers, radius, e0, invw, uk) != ORACLE_OK) {
+                for (int k = 0; k < n_steps; ++k) Ik[k] = (double)images[(int64_t)k * plane_in + p];
+                if (pixel_profile(py, pz, Ik, n_steps, centers, radius, e0, invw, n_bins, edge,
+                                  out + q, plane_out, uk, tmp) != ORACLE_OK) {
 #pragma omp atomic write
                     status = ORACLE_EINVAL;
                     continue;
                 }
                 if (bins)
                     for (int k = 0; k < n_steps; ++k) bins[q * n_steps + k] = floor_to_i32(uk[k]);
-                for (int k = 0; k < n_steps; ++k) Ik[k] = (double)images[(int64_t)k * plane_in + p];
-                oracle_bin_profile(uk, Ik, n_steps, n_bins, out + q, plane_out);
             }
         }
         free(uk);
         free(Ik);
+        free(tmp);
     }
     if (status != ORACLE_OK) return status;
     if (totals) {
@@ -212,21 +253,22 @@ int oracle_reconstruct(int nx, int ny, const double* origin, const double* u, co
  * Reconstruction of an explicit list of pixels (flat indices j*nx + i), for
  * sampled checks of large scans.  Intensities come from `images`
  * ([n_steps][ny][nx]) or, when `series` is not NULL, from series[n][n_steps]
- * (the time series of the n-th listed pixel).
+ * (the time series of the n-th listed pixel); with neither, only positions.
  *   out   [npix][n_bins] FP64 profile of each listed pixel
- *   bins  [npix][n_steps] int32 floor(u_k), or NULL
- *   upos  [npix][n_steps] FP64 u_k, or NULL
+ *   bins  [npix][n_steps] int32 floor(u_k) of the reported edge, or NULL
+ *   upos  [npix][n_steps] FP64 u_k of the reported edge, or NULL
  */
 int oracle_reconstruct_pixels(int nx, int ny, const double* origin, const double* u,
                               const double* v, const double* pixel_xyz, double radius,
                               int n_steps, const double* centers, int n_bins,
-                              double first_center, double width, const uint16_t* images,
-                              const uint16_t* series, const int64_t* pixels, int64_t npix,
-                              double* out, int32_t* bins,
+                              double first_center, double width, int edge,
+                              const uint16_t* images, const uint16_t* series,
+                              const int64_t* pixels, int64_t npix, double* out, int32_t* bins,
                               double* upos, int nthreads)
 {
     if (nx <= 0 || ny <= 0 || n_steps < 2 || n_bins <= 0 || !(width > 0.0) || !(radius > 0.0))
         return ORACLE_EINVAL;
+    if (edge < EDGE_LEADING || edge > EDGE_BOTH) return ORACLE_EINVAL;
     const double e0 = first_center - width / 2.0;
     const double invw = 1.0 / width;
     const int64_t plane_in = (int64_t)nx * ny;
@@ -240,6 +282,7 @@ int oracle_reconstruct_pixels(int nx, int ny, const double* origin, const double
     {
         double* uk = (double*)malloc(sizeof(double) * (size_t)n_steps);
         double* Ik = (double*)malloc(sizeof(double) * (size_t)n_steps);
+        double* tmp = (double*)malloc(sizeof(double) * (size_t)n_bins);
 #pragma omp for schedule(dynamic, 16)
         for (int64_t n = 0; n < npix; ++n) {
             int64_t p = pixels[n];
@@ -252,25 +295,25 @@ int oracle_reconstruct_pixels(int nx, int ny, const double* origin, const double
             }
             double py, pz;
             pixel_center(nx, origin, u, v, pixel_xyz, p, &py, &pz);
-            if (pixel_positions(py, pz, n_steps, centers, radius, e0, invw, uk) != ORACLE_OK) {
+            for (int k = 0; k < n_steps; ++k)
+                Ik[k] = series ? (double)series[n * n_steps + k]
+                               : (images ? (double)images[(int64_t)k * plane_in + p] : 0.0);
+            if (pixel_profile(py, pz, Ik, n_steps, centers, radius, e0, invw, n_bins, edge, o, 1,
+                              uk, tmp) != ORACLE_OK) {
 #pragma omp atomic write
                 status = ORACLE_EINVAL;
                 continue;
             }
+            if (!series && !images)
+                for (int b = 0; b < n_bins; ++b) o[b] = 0.0;
             if (bins)
                 for (int k = 0; k < n_steps; ++k) bins[n * n_steps + k] = floor_to_i32(uk[k]);
             if (upos)
                 for (int k = 0; k < n_steps; ++k) upos[n * n_steps + k] = uk[k];
-            if (series) {
-                for (int k = 0; k < n_steps; ++k) Ik[k] = (double)series[n * n_steps + k];
-                oracle_bin_profile(uk, Ik, n_steps, n_bins, o, 1);
-            } else if (images) {
-                for (int k = 0; k < n_steps; ++k) Ik[k] = (double)images[(int64_t)k * plane_in + p];
-                oracle_bin_profile(uk, Ik, n_steps, n_bins, o, 1);
-            }
         }
         free(uk);
         free(Ik);
+        free(tmp);
     }
     return status;
 }

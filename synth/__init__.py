@@ -89,11 +89,15 @@ class Detector:
                 np.ascontiguousarray(np.broadcast_to(z, (self.ny, self.nx))))
 
 
+EDGE_LEADING, EDGE_TRAILING, EDGE_BOTH = 0, 1, 2
+
+
 @dataclass
 class Wire:
     radius: float
     centers: np.ndarray  # [n_steps][3] um
     axis: np.ndarray = field(default_factory=lambda: np.array([1.0, 0.0, 0.0]))
+    edge: int = EDGE_LEADING  # which wire edge the reconstruction uses
 
     @property
     def n_steps(self) -> int:

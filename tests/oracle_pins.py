@@ -168,20 +168,32 @@ def pin_conservation_random(lib):
 
 def pin_conservation_scan(lib):
     """Config-1 scan: every pixel's sweep lies inside the grid, so each pixel
-    conserves intensity and the totals sum to the total first-minus-last."""
+    conserves intensity (leading: I_0 - I_{N-1}; trailing: I_{N-1} - I_0;
+    their average: 0) and the totals sum to the total of the same."""
     s = synth.config1()
-    out, tot, _ = oracle.reconstruct(s, lib=lib)
+    s.grid = synth.centered_grid(201, 1.0)  # wide enough for the trailing sweep too
     I = s.images.astype(np.float64)
     scale = np.abs(np.diff(I, axis=0)).sum(0) + 1.0
-    assert np.all(np.abs(out.sum(0) - (I[0] - I[-1])) <= 1e-9 * scale)
-    assert abs(tot.sum() - (I[0] - I[-1]).sum()) <= 1e-9 * scale.sum()
+    for edge, want in ((synth.EDGE_LEADING, I[0] - I[-1]), (synth.EDGE_TRAILING, I[-1] - I[0]),
+                       (synth.EDGE_BOTH, 0.0 * I[0])):
+        s.wire.edge = edge
+        out, tot, bins = oracle.reconstruct(s, want_bins=True, lib=lib)
+        assert bins.min() >= 0 and bins.max() <= s.grid.n_bins - 1
+        assert np.all(np.abs(out.sum(0) - want) <= 1e-9 * scale), edge
+        assert abs(tot.sum() - want.sum()) <= 1e-9 * scale.sum(), edge
 
 
-def brute_force_pixel(py, pz, centers, r, grid, I, samples_per_bin=4000):
-    """Depth profile of one pixel by sub-sampling the beam: the intensity lost
-    between steps k and k+1 is spread uniformly over the beam points that are
-    clear at step k and blocked at step k+1 (the slice the leading edge sweeps).
+def brute_force_pixel(py, pz, centers, r, grid, I, samples_per_bin=4000, edge=0):
+    """Depth profile of one pixel by sub-sampling the beam.  Leading edge: the
+    intensity lost between steps k and k+1 is spread uniformly over the beam
+    points that are clear at step k and blocked at step k+1 (the slice the
+    leading edge covers).  Trailing edge: the intensity regained is spread over
+    the points blocked at k and clear at k+1.  Both: the average of the two.
     Returns (profile, per-bin error bound)."""
+    if edge == synth.EDGE_BOTH:
+        p1, e1 = brute_force_pixel(py, pz, centers, r, grid, I, samples_per_bin, 0)
+        p2, e2 = brute_force_pixel(py, pz, centers, r, grid, I, samples_per_bin, 1)
+        return 0.5 * (p1 + p2), 0.5 * (e1 + e2)
     B, w, c0 = grid.n_bins, grid.width, grid.first_center
     e0 = c0 - 0.5 * w
     h = w / samples_per_bin
@@ -194,9 +206,13 @@ def brute_force_pixel(py, pz, centers, r, grid, I, samples_per_bin=4000):
     prof = np.zeros(B)
     err = np.zeros(B)
     for k in range(len(centers) - 1):
-        newly = occ[k + 1] & ~occ[k]
+        if edge == synth.EDGE_TRAILING:
+            newly = occ[k] & ~occ[k + 1]
+            dI = float(I[k + 1]) - float(I[k])
+        else:
+            newly = occ[k + 1] & ~occ[k]
+            dI = float(I[k]) - float(I[k + 1])
         n = int(newly.sum())
-        dI = float(I[k]) - float(I[k + 1])
         if n == 0:
             continue
         sel = newly & inside
@@ -208,54 +224,85 @@ def brute_force_pixel(py, pz, centers, r, grid, I, samples_per_bin=4000):
 
 
 def pin_brute_force(lib):
-    """Tiny scans (4x4 px, 9 steps, 15 bins) against brute-force integration."""
-    for seed, step, width in ((21, 1.0, 1.0), (22, 0.5, 0.5), (23, 2.0, 1.0)):
+    """Tiny scans (4x4 px, 9 steps, 15 bins) against brute-force integration,
+    for the leading edge, the trailing edge and their average."""
+    for seed, step, width, edge in ((21, 1.0, 1.0, 0), (22, 0.5, 0.5, 0), (23, 2.0, 1.0, 0),
+                                    (24, 1.0, 1.0, 1), (25, 2.0, 1.0, 2)):
         s = synth.tiny(4, 4, 9, 15, seed=seed, pitch=3000.0, step=step, width=width,
                        n_src=6, dark=50.0, sigma=1.0)
+        s.wire.edge = edge
         out, _, _ = oracle.reconstruct(s, lib=lib)
         py, pz = s.detector.pixel_yz()
         for j in range(4):
             for i in range(4):
                 prof, err = brute_force_pixel(py[j, i], pz[j, i], s.wire.centers,
-                                              s.wire.radius, s.grid, s.images[:, j, i])
+                                              s.wire.radius, s.grid, s.images[:, j, i],
+                                              edge=edge)
                 got = out[:, j, i]
                 assert np.all(np.abs(got - prof) <= err + 1e-9), (seed, j, i, got, prof, err)
 
 
 def pin_planted_sources(lib):
-    """Noise-free single-pixel sources with integer amplitude: the source depth
-    lies inside the interval of the step at which it goes dark, and the bins of
-    that interval receive exactly its amplitude."""
-    s = synth.tiny(48, 48, 61, 121, seed=31, step=1.0, width=1.0, n_src=30, dark=0.0,
-                   noise=False, sigma=0.0, integer_amp=True)
-    out, _, bins = oracle.reconstruct(s, want_bins=True, lib=lib)
+    """Noise-free single-pixel sources with integer amplitude.  Leading edge:
+    the source depth lies inside the interval of the step at which the pixel
+    goes dark, and the bins of that interval receive exactly the amplitude.
+    Trailing edge: the same for the step at which it comes back.  Both: the
+    union of the two intervals' bins receives the amplitude (half from each)."""
+    # long enough for the trailing edge (one shadow width, ~52 um, behind the
+    # leading one) to pass the sources again before the scan ends
+    s = synth.tiny(48, 48, 161, 161, seed=31, step=1.0, width=1.0, n_src=30, dark=0.0,
+                   noise=False, sigma=0.0, integer_amp=True, zlo=-50.0, zhi=0.0)
     src = s.sources
     ii = np.rint(src.ci).astype(int)
     jj = np.rint(src.cj).astype(int)
     flat = jj * s.detector.nx + ii
     uniq, cnt = np.unique(flat, return_counts=True)
     single = set(uniq[cnt == 1].tolist())
-    _, _, upos = oracle.reconstruct_pixels(s, flat, want_u=True, lib=lib)
     e0 = s.grid.first_center - 0.5 * s.grid.width
-    checked = 0
+    B = s.grid.n_bins
+    outs, ups = {}, {}
+    for edge in (0, 1, 2):
+        s.wire.edge = edge
+        outs[edge], _, _ = oracle.reconstruct(s, lib=lib)
+        _, _, ups[edge] = oracle.reconstruct_pixels(s, flat, want_u=True, lib=lib)
+
+    def bins_of(u0, u1):
+        b0 = max(0, int(math.floor(min(u0, u1))))
+        b1 = min(B - 1, int(math.floor(max(u0, u1))))
+        return set(range(b0, b1 + 1))
+
+    checked = {0: 0, 1: 0, 2: 0}
     for n in range(len(flat)):
         if flat[n] not in single:
             continue
         I = s.images[:, jj[n], ii[n]].astype(np.int64)
-        drops = np.nonzero(I[:-1] > I[1:])[0]
-        if len(drops) == 0:
-            continue  # never occluded during the scan
-        k = int(drops[0])
-        assert I[k] - I[k + 1] == int(src.amp[n])
-        u0, u1 = upos[n, k], upos[n, k + 1]
         zu = (src.zs[n] - e0) / s.grid.width
-        assert min(u0, u1) - 1e-9 <= zu <= max(u0, u1) + 1e-9, (zu, u0, u1)
-        b0 = max(0, int(math.floor(min(u0, u1))))
-        b1 = min(s.grid.n_bins - 1, int(math.floor(max(u0, u1))))
-        got = out[b0:b1 + 1, jj[n], ii[n]].sum()
-        assert abs(got - src.amp[n]) < 1e-8 * src.amp[n], (got, src.amp[n])
-        checked += 1
-    assert checked >= 10, checked
+        drops = np.nonzero(I[:-1] > I[1:])[0]
+        rises = np.nonzero(I[:-1] < I[1:])[0]
+        lead = trail = None
+        if len(drops):
+            k = int(drops[0])
+            assert I[k] - I[k + 1] == int(src.amp[n])
+            u0, u1 = ups[0][n, k], ups[0][n, k + 1]
+            assert min(u0, u1) - 1e-9 <= zu <= max(u0, u1) + 1e-9, (zu, u0, u1)
+            lead = bins_of(u0, u1)
+            got = sum(outs[0][b, jj[n], ii[n]] for b in lead)
+            assert abs(got - src.amp[n]) < 1e-8 * src.amp[n], (got, src.amp[n])
+            checked[0] += 1
+        if len(rises) and len(drops) and rises[-1] > drops[0]:
+            k = int(rises[-1])
+            assert I[k + 1] - I[k] == int(src.amp[n])
+            u0, u1 = ups[1][n, k], ups[1][n, k + 1]
+            assert min(u0, u1) - 1e-9 <= zu <= max(u0, u1) + 1e-9, (zu, u0, u1)
+            trail = bins_of(u0, u1)
+            got = sum(outs[1][b, jj[n], ii[n]] for b in trail)
+            assert abs(got - src.amp[n]) < 1e-8 * src.amp[n], (got, src.amp[n])
+            checked[1] += 1
+        if lead is not None and trail is not None:
+            got = sum(outs[2][b, jj[n], ii[n]] for b in (lead | trail))
+            assert abs(got - src.amp[n]) < 1e-8 * src.amp[n], (got, src.amp[n])
+            checked[2] += 1
+    assert min(checked.values()) >= 8, checked
 
 
 def pin_poisson_recovery(lib):

@@ -24,8 +24,17 @@ MUTANTS = [
     ("u_offset_sign", "u[k] = (d - e0) * invw;", "u[k] = (d + e0) * invw;"),
     ("e0_half_bin", "const double e0 = first_center - width / 2.0;",
      "const double e0 = first_center;"),
-    ("dI_sign", "double dI = I[k] - I[k + 1];", "double dI = I[k + 1] - I[k];"),
-    ("dI_index", "double dI = I[k] - I[k + 1];", "double dI = I[k] - I[n_steps - 1];"),
+    ("dI_sign", "double dI = trailing ? I[k + 1] - I[k] : I[k] - I[k + 1];",
+     "double dI = trailing ? I[k + 1] - I[k] : I[k + 1] - I[k];"),
+    ("dI_index", "double dI = trailing ? I[k + 1] - I[k] : I[k] - I[k + 1];",
+     "double dI = trailing ? I[k + 1] - I[k] : I[k] - I[n_steps - 1];"),
+    ("trailing_dI_sign", "double dI = trailing ? I[k + 1] - I[k] : I[k] - I[k + 1];",
+     "double dI = trailing ? I[k] - I[k + 1] : I[k] - I[k + 1];"),
+    ("trailing_side", "if (trailing) s = -s;", "if (trailing) s = s;"),
+    ("both_not_averaged", "o[(int64_t)b * stride] = 0.5 * (o[(int64_t)b * stride] + tmp[b]);",
+     "o[(int64_t)b * stride] = (o[(int64_t)b * stride] + tmp[b]);"),
+    ("both_drops_trailing", "o[(int64_t)b * stride] = 0.5 * (o[(int64_t)b * stride] + tmp[b]);",
+     "o[(int64_t)b * stride] = 0.5 * (o[(int64_t)b * stride] + o[(int64_t)b * stride]);"),
     ("top_swap", "double top = hi < bd + 1.0 ? hi : bd + 1.0;",
      "double top = hi < bd + 1.0 ? bd + 1.0 : hi;"),
     ("no_normalise", "out[(int64_t)bd * stride] += dI * (ov / len);",
