@@ -62,7 +62,15 @@ typedef int32_t dr_status;
 #define DR_E_BUSY (-5)
 #define DR_E_NOTFOUND (-6)
 
+/* Wire edges (dr_wire.edge).  Leading: the side whose shadow advances with
+ * the scan, I_k - I_{k+1} spread over its interval (intensity lost as the edge
+ * covers a depth slice).  Trailing: the opposite side, I_{k+1} - I_k
+ * (intensity regained as it uncovers the slice).  Both: the average of the
+ * two reconstructions (a true source keeps its amplitude, the mirrored
+ * negative ghosts of the two edges are halved). */
 #define DR_EDGE_LEADING 0
+#define DR_EDGE_TRAILING 1
+#define DR_EDGE_BOTH 2
 
 typedef struct dr_ctx_s* dr_ctx;     /* one GPU: streams, slab buffers, scheduler */
 typedef struct dr_geom_s* dr_geom;   /* device-resident tables of one geometry */
@@ -79,7 +87,7 @@ typedef struct {
 
 /* Wire: a cylinder of `radius` um with axis `axis` (must be (1,0,0));
  * centers is a host array [n_steps][3] of the axis position at each step (the
- * x coordinate is ignored).  edge must be DR_EDGE_LEADING. */
+ * x coordinate is ignored).  edge: DR_EDGE_LEADING, _TRAILING or _BOTH. */
 typedef struct {
     double radius;
     double axis[3];
@@ -124,8 +132,8 @@ dr_status dr_ctx_destroy(dr_ctx ctx);
  * and check it on the device.  Copies every input, so the caller may free its
  * arrays on return; the library owns *out until dr_geometry_free.
  * Errors: DR_E_INVAL for NULL pointers, nx/ny/n_bins < 1, n_steps < 2,
- * radius <= 0, width <= 0, an axis other than (1,0,0) or an edge other than
- * DR_EDGE_LEADING (DR_E_UNSUPPORTED for those two), a pixel inside the wire,
+ * radius <= 0, width <= 0, an unknown edge, an axis other than (1,0,0)
+ * (DR_E_UNSUPPORTED), a pixel inside the wire,
  * a wire position not strictly between beam and detector in y, or any
  * non-finite depth; DR_E_NOMEM / DR_E_DEVICE for allocation or HIP failures.
  * Synchronous. */
@@ -173,13 +181,15 @@ dr_status dr_reconstruct(dr_geom geom, const uint16_t* images, int images_on_dev
 dr_status dr_reconstruct_f64(dr_geom geom, const uint16_t* images_dev, double* out,
                              double* totals, void* stream);
 
-/* Positions of the leading edge, computed by the device code the kernels use,
- * for a host list of pixels (flat indices j*nx + i): bins_out[n][n_steps]
- * receives floor(u_k) as int32 (saturated) and u_out[n][n_steps] the FP64
- * u_k = (d_k - e0)/width-scaled positions; either output may be NULL.  Host
- * buffers; synchronous.  DR_E_INVAL for an out-of-range pixel. */
-dr_status dr_debug_plan(dr_geom geom, const int64_t* pixels, int32_t n, int32_t* bins_out,
-                        double* u_out);
+/* Positions of one wire edge (edge: DR_EDGE_LEADING or DR_EDGE_TRAILING),
+ * computed by the device code the kernels use, for a host list of pixels
+ * (flat indices j*nx + i): bins_out[n][n_steps] receives floor(u_k) as int32
+ * (saturated) and u_out[n][n_steps] the FP64 positions in bin units,
+ * u_k = (d_k - e0) * (1/width) with e0 = first_center - width/2; either output
+ * may be NULL.  Host buffers; synchronous.  DR_E_INVAL for an out-of-range
+ * pixel or edge. */
+dr_status dr_debug_plan(dr_geom geom, const int64_t* pixels, int32_t n, int32_t edge,
+                        int32_t* bins_out, double* u_out);
 
 /* Device time in milliseconds of the last reconstruction kernel launched by
  * dr_reconstruct on this geometry (HIP events on the launch stream; waits for

@@ -44,6 +44,8 @@ struct ScanArgs {
     void* out;            // element (bin 0, row 0, column 0); float or double
     int64_t out_plane;    // elements between bins (ny*nx)
     void* partials;       // per-wave partial sums of totals, [slots][n_bins]
+    int32_t pass;         // 0: single pass; 1, 2: first and second pass of a two-edge
+                          // reconstruction (the second adds onto the first's output)
     // plan tables (row mode)
     const int32_t* bl;
     const int32_t* nb;
@@ -85,8 +87,12 @@ int tile_width(const TileCfg& t);
 int num_tile_variants();
 TileCfg tile_variant(int i);
 
-hipError_t launch_build_plans(const GeomArgs& g, const PlanTables& t, int* d_status,
-                              hipStream_t s);
+// side: 0 = leading edge, 1 = trailing edge; scale multiplies every fraction
+// (-1 turns I_k - I_{k+1} into I_{k+1} - I_k; 1/2 averages two edges).
+hipError_t launch_build_plans(const GeomArgs& g, const PlanTables& t, int side, double scale,
+                              int* d_status, hipStream_t s);
+// rows generic in either of two plans become generic in both
+hipError_t launch_unify_classes(int8_t* a, int8_t* b, int ny, hipStream_t s);
 hipError_t launch_rows_f32(const TileCfg& t, const ScanArgs& a, hipStream_t s);
 hipError_t launch_rows_f64(const ScanArgs& a, hipStream_t s);
 hipError_t launch_batch_f32(const TileCfg& t, const BatchArgs& b, int groups, hipStream_t s);
@@ -96,8 +102,8 @@ hipError_t launch_totals_f32(const float* partials, int64_t slots, int n_bins, d
                              int work_rows, float* totals, hipStream_t s);
 hipError_t launch_totals_f64(const double* partials, int64_t slots, int n_bins, double* work,
                              int work_rows, double* totals, hipStream_t s);
-hipError_t launch_debug_plan(const GeomArgs& g, const int64_t* pixels, int n, int32_t* bins,
-                             double* upos, hipStream_t s);
+hipError_t launch_debug_plan(const GeomArgs& g, const int64_t* pixels, int n, int side,
+                             int32_t* bins, double* upos, hipStream_t s);
 
 constexpr int kPlanChunk = 1024;  // intervals staged in LDS at a time
 constexpr int kTotalsWorkRows = 64;

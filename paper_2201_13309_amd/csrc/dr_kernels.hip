@@ -168,13 +168,14 @@ __device__ __forceinline__ PlanD make_plan(double ua, double ub, int B)
 // One workgroup per detector row: plan tables, row class, checks.
 // status bit 0: a non-finite position (pixel inside the wire or degenerate);
 // bit 1: a wire position not strictly between beam and detector in y.
-__global__ __launch_bounds__(256) void build_plans_kernel(GeomArgs g, PlanTables t, int* status)
+__global__ __launch_bounds__(256) void build_plans_kernel(GeomArgs g, PlanTables t, int side,
+                                                          double scale, int* status)
 {
     const int row = blockIdx.x;
     const int N = g.n_steps, B = g.n_bins, nint = N - 1;
     double py, pz;
     pixel_key(g, (int64_t)row * g.nx, py, pz);
-    const int s = leading_sign(g, py, pz);
+    const int s = side ? -leading_sign(g, py, pz) : leading_sign(g, py, pz);
     const double sr = (double)s * g.radius;
     const double e0 = g.first_center - g.width / 2.0;
     const double invw = 1.0 / g.width;
@@ -191,15 +192,18 @@ __global__ __launch_bounds__(256) void build_plans_kernel(GeomArgs g, PlanTables
         dec &= (ub <= ua);
         const PlanD e = make_plan(ua, ub, B);
         const int64_t o = (int64_t)row * nint + k;
+        // scale is +-1 or +-1/2: exact, so the FP64 fractions stay the
+        // oracle's ov/len up to sign and a power of two
+        const double f0 = e.f0 * scale, fm = e.fm * scale, f1 = e.f1 * scale;
         t.bl[o] = e.bl;
         t.nb[o] = e.nb;
-        t.f0[o] = (float)e.f0;
-        t.fm[o] = (float)e.fm;
-        t.f1[o] = (float)e.f1;
+        t.f0[o] = (float)f0;
+        t.fm[o] = (float)fm;
+        t.f1[o] = (float)f1;
         if (t.d0) {
-            t.d0[o] = e.f0;
-            t.dm[o] = e.fm;
-            t.d1[o] = e.f1;
+            t.d0[o] = f0;
+            t.dm[o] = fm;
+            t.d1[o] = f1;
         }
     }
     inc = __syncthreads_and(inc);
@@ -249,6 +253,13 @@ __global__ __launch_bounds__(256) void build_plans_kernel(GeomArgs g, PlanTables
         t.row_hi[row] = s_hi;
         if (bad) atomicOr(status, bad);
     }
+}
+
+__global__ void unify_classes_kernel(int8_t* a, int8_t* b, int ny)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= ny) return;
+    if (a[j] == kRowGeneric || b[j] == kRowGeneric) a[j] = b[j] = kRowGeneric;
 }
 
 // ------------------------------------------------------------ tile kernels
@@ -416,7 +427,7 @@ __device__ __forceinline__ void process_tile_generic(const ScanArgs& a, int row,
     const uint16_t* ip = a.img + (int64_t)(row - a.row_base) * a.img_row + col0;
     Acc* op = (Acc*)a.out + (int64_t)row * a.nx + col0;
     const int64_t plane = a.out_plane;
-    if (act)
+    if (act && a.pass != 2)  // the second pass adds onto the first pass's output
         for (int b = 0; b < B; ++b)
 #pragma unroll
             for (int q = 0; q < PPL; ++q) op[(int64_t)b * plane + q] = (Acc)0;
@@ -444,15 +455,19 @@ __device__ __forceinline__ void process_tile_generic(const ScanArgs& a, int row,
         }
     }
     if (a.partials) {
+        // partial totals of the final values; a first pass of two leaves them
+        // to the second (a row is generic in both passes or in neither)
         PartialWindow<Acc> pwin;
         pwin.row = (Acc*)a.partials + ((int64_t)(row * a.tiles_per_row + tile) * WAVES + wave) * B;
         pwin.B = B;
-        for (int b = 0; b < B; ++b) {
-            Acc s = (Acc)0;
-            if (act)
+        if (a.pass != 1) {
+            for (int b = 0; b < B; ++b) {
+                Acc s = (Acc)0;
+                if (act)
 #pragma unroll
-                for (int q = 0; q < PPL; ++q) s += op[(int64_t)b * plane + q];
-            pwin.add(b, wave_total(s), lane);
+                    for (int q = 0; q < PPL; ++q) s += op[(int64_t)b * plane + q];
+                pwin.add(b, wave_total(s), lane);
+            }
         }
         pwin.finish(lane);
     }
@@ -496,8 +511,19 @@ __device__ __forceinline__ void process_tile_mono(const ScanArgs& a, int row, in
     for (int q = 0; q < PPL; ++q) acc[q] = (Acc)0;
     int cb = -1;  // open bin (uniform), -1 = none
 
+    const bool add_on = a.pass == 2;  // second pass: add onto the first pass's output
     auto put = [&]() {
-        if (act) store_bins<Acc, PPL>(outp(cb), acc);
+        if (act) {
+            if (add_on) {
+                Acc* o = outp(cb);
+                Acc v[PPL];
+#pragma unroll
+                for (int q = 0; q < PPL; ++q) v[q] = o[q] + acc[q];
+                store_bins<Acc, PPL>(o, v);
+            } else {
+                store_bins<Acc, PPL>(outp(cb), acc);
+            }
+        }
         if (pwin.row) {
             Acc s = (Acc)0;
 #pragma unroll
@@ -574,7 +600,7 @@ __device__ __forceinline__ void process_tile_mono(const ScanArgs& a, int row, in
     if (cb >= 0) put();
     // bins outside the row's touched range are zero; stored after the last load
     const int blo = a.row_lo[row], bhi = a.row_hi[row];
-    if (act) {
+    if (act && !add_on) {
         Acc z[PPL];
 #pragma unroll
         for (int q = 0; q < PPL; ++q) z[q] = (Acc)0;
@@ -674,13 +700,13 @@ __global__ __launch_bounds__(256) void totals_stage2(const double* work, int row
 // ------------------------------------------------------------------- debug
 
 __global__ __launch_bounds__(64) void debug_plan_kernel(GeomArgs g, const int64_t* pix, int n,
-                                                        int32_t* bins, double* upos)
+                                                        int side, int32_t* bins, double* upos)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= n) return;
     double py, pz;
     pixel_key(g, pix[idx], py, pz);
-    const int s = leading_sign(g, py, pz);
+    const int s = side ? -leading_sign(g, py, pz) : leading_sign(g, py, pz);
     const double sr = (double)s * g.radius;
     const double e0 = g.first_center - g.width / 2.0;
     const double invw = 1.0 / g.width;
@@ -734,10 +760,18 @@ int tile_width(const TileCfg& t) { return 64 * t.waves * t.ppl; }
         }                                                            \
     } while (0)
 
-hipError_t launch_build_plans(const GeomArgs& g, const PlanTables& t, int* d_status,
-                              hipStream_t s)
+hipError_t launch_build_plans(const GeomArgs& g, const PlanTables& t, int side, double scale,
+                              int* d_status, hipStream_t s)
 {
-    hipLaunchKernelGGL(build_plans_kernel, dim3(g.ny), dim3(256), 0, s, g, t, d_status);
+    hipLaunchKernelGGL(build_plans_kernel, dim3(g.ny), dim3(256), 0, s, g, t, side, scale,
+                       d_status);
+    return hipGetLastError();
+}
+
+hipError_t launch_unify_classes(int8_t* a, int8_t* b, int ny, hipStream_t s)
+{
+    hipLaunchKernelGGL(unify_classes_kernel, dim3((unsigned)((ny + 255) / 256)), dim3(256), 0, s,
+                       a, b, ny);
     return hipGetLastError();
 }
 
@@ -797,12 +831,12 @@ hipError_t launch_totals_f64(const double* partials, int64_t slots, int n_bins, 
     return launch_totals<double>(partials, slots, n_bins, work, work_rows, totals, s);
 }
 
-hipError_t launch_debug_plan(const GeomArgs& g, const int64_t* pixels, int n, int32_t* bins,
-                             double* upos, hipStream_t s)
+hipError_t launch_debug_plan(const GeomArgs& g, const int64_t* pixels, int n, int side,
+                             int32_t* bins, double* upos, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(debug_plan_kernel, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, g,
-                       pixels, n, bins, upos);
+                       pixels, n, side, bins, upos);
     return hipGetLastError();
 }
 

@@ -70,10 +70,12 @@ int64_t partial_slots(const dr_geom g, const TileCfg& t)
     return (int64_t)g->ny * tiles_per_row(g, t) * t.waves;
 }
 
-ScanArgs scan_args(const dr_geom g, const TileCfg& t, const uint16_t* img, int64_t img_step,
-                   int row_base, int row_begin, int row_end, float* out, float* partials)
+ScanArgs scan_args(const dr_geom g, const TileCfg& t, int pass, const uint16_t* img,
+                   int64_t img_step, int row_base, int row_begin, int row_end, float* out,
+                   float* partials)
 {
     ScanArgs a{};
+    a.pass = g->passes == 1 ? 0 : pass + 1;
     a.img = img;
     a.img_step = img_step;
     a.img_row = g->nx;
@@ -87,25 +89,28 @@ ScanArgs scan_args(const dr_geom g, const TileCfg& t, const uint16_t* img, int64
     a.n_bins = g->n_bins;
     a.out = out;
     a.out_plane = (int64_t)g->nx * g->ny;
-    a.partials = partials;
-    a.bl = g->t.bl;
-    a.nb = g->t.nb;
-    a.f0 = g->t.f0;
-    a.fm = g->t.fm;
-    a.f1 = g->t.f1;
-    a.d0 = g->t.d0;
-    a.dm = g->t.dm;
-    a.d1 = g->t.d1;
-    a.row_class = g->t.row_class;
-    a.row_lo = g->t.row_lo;
-    a.row_hi = g->t.row_hi;
+    a.partials = partials ? partials + (size_t)pass * partial_slots(g, t) * g->n_bins : nullptr;
+    const PlanTables& pt = g->t[pass];
+    a.bl = pt.bl;
+    a.nb = pt.nb;
+    a.f0 = pt.f0;
+    a.fm = pt.fm;
+    a.f1 = pt.f1;
+    a.d0 = pt.d0;
+    a.dm = pt.dm;
+    a.d1 = pt.d1;
+    a.row_class = pt.row_class;
+    a.row_lo = pt.row_lo;
+    a.row_hi = pt.row_hi;
     return a;
 }
 
 hipError_t enqueue_totals(const dr_geom g, const float* partials, int64_t slots, double* work,
                           float* totals, hipStream_t s)
 {
-    return launch_totals_f32(partials, slots, g->n_bins, work, kTotalsWorkRows, totals, s);
+    // slots: partial rows of one pass; the partial rows of every pass are summed
+    return launch_totals_f32(partials, slots * g->passes, g->n_bins, work, kTotalsWorkRows,
+                             totals, s);
 }
 
 static TileCfg choose_tile(dr_geom g, const void* img, const void* out)
@@ -118,7 +123,7 @@ static TileCfg choose_tile(dr_geom g, const void* img, const void* out)
 static dr_status ensure_scratch(dr_geom g, const TileCfg& t, float** part)
 {
     std::lock_guard<std::mutex> lk(g->mu);
-    const size_t need = (size_t)partial_slots(g, t) * g->n_bins * sizeof(float);
+    const size_t need = (size_t)g->passes * partial_slots(g, t) * g->n_bins * sizeof(float);
     DR_HIP(g->part32.reserve(need));
     DR_HIP(g->work.reserve((size_t)kTotalsWorkRows * g->n_bins * sizeof(double)));
     *part = g->part32.as<float>();
@@ -259,8 +264,9 @@ dr_status dr_geometry_init(dr_ctx c, const dr_detector* det, const dr_wire* wire
         return set_error(DR_E_INVAL, "detector origin/u/v must be finite");
     if (!(wire->axis[0] == 1.0 && wire->axis[1] == 0.0 && wire->axis[2] == 0.0))
         return set_error(DR_E_UNSUPPORTED, "only a wire axis along x (1,0,0) is supported");
-    if (wire->edge != DR_EDGE_LEADING)
-        return set_error(DR_E_UNSUPPORTED, "only DR_EDGE_LEADING is supported");
+    if (wire->edge != DR_EDGE_LEADING && wire->edge != DR_EDGE_TRAILING &&
+        wire->edge != DR_EDGE_BOTH)
+        return set_error(DR_E_INVAL, "wire edge must be DR_EDGE_LEADING, _TRAILING or _BOTH");
     const int nx = det->nx, ny = det->ny, N = wire->n_steps, B = grid->n_bins;
     if ((int64_t)nx * ny > (int64_t)1 << 31)
         return set_error(DR_E_INVAL, "detector larger than 2^31 pixels");
@@ -307,6 +313,8 @@ dr_status dr_geometry_init(dr_ctx c, const dr_detector* det, const dr_wire* wire
     g->first_center = grid->first_center;
     g->width = grid->width;
     g->row_mode = row_mode;
+    g->edge = wire->edge;
+    g->passes = wire->edge == DR_EDGE_BOTH ? 2 : 1;
 
     std::vector<double> wyz((size_t)N * 2);
     for (int k = 0; k < N; ++k) {
@@ -338,7 +346,9 @@ dr_status dr_geometry_init(dr_ctx c, const dr_detector* det, const dr_wire* wire
     ga.uz = det->u[2];
     ga.vz = det->v[2];
 
-    // plan tables: bl, nb (int32), f0, fm, f1 (float), d0, dm, d1 (double), class, sign
+    // plan tables per pass: bl, nb (int32), f0, fm, f1 (float), d0, dm, d1 (double),
+    // class, side, touched-bin range.  Leading: side s_p, fractions as they are;
+    // trailing: side -s_p, fractions negated (I_{k+1} - I_k); both: the two at 1/2.
     const size_t ent = (size_t)ny * (N - 1);
     auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
     const size_t o_bl = 0, o_nb = o_bl + up(ent * 4), o_f0 = o_nb + up(ent * 4),
@@ -346,24 +356,40 @@ dr_status dr_geometry_init(dr_ctx c, const dr_detector* det, const dr_wire* wire
                  o_dm = o_d0 + up(ent * 8), o_d1 = o_dm + up(ent * 8), o_cls = o_d1 + up(ent * 8),
                  o_sgn = o_cls + up(ny), o_lo = o_sgn + up(ny), o_hi = o_lo + up((size_t)ny * 4),
                  o_st = o_hi + up((size_t)ny * 4), total = o_st + 256;
-    DR_HIP(g->plan.reserve(total));
-    char* base = g->plan.as<char>();
-    PlanTables& t = g->t;
-    t.bl = (int32_t*)(base + o_bl);
-    t.nb = (int32_t*)(base + o_nb);
-    t.f0 = (float*)(base + o_f0);
-    t.fm = (float*)(base + o_fm);
-    t.f1 = (float*)(base + o_f1);
-    t.d0 = (double*)(base + o_d0);
-    t.dm = (double*)(base + o_dm);
-    t.d1 = (double*)(base + o_d1);
-    t.row_class = (int8_t*)(base + o_cls);
-    t.row_sign = (int8_t*)(base + o_sgn);
-    t.row_lo = (int32_t*)(base + o_lo);
-    t.row_hi = (int32_t*)(base + o_hi);
-    int* d_status = (int*)(base + o_st);
-    DR_HIP(hipMemsetAsync(d_status, 0, sizeof(int), c->stream));
-    DR_HIP(launch_build_plans(ga, t, d_status, c->stream));
+    int* d_status = nullptr;
+    for (int p = 0; p < g->passes; ++p) {
+        DR_HIP(g->plan[p].reserve(total));
+        char* base = g->plan[p].as<char>();
+        PlanTables& t = g->t[p];
+        t.bl = (int32_t*)(base + o_bl);
+        t.nb = (int32_t*)(base + o_nb);
+        t.f0 = (float*)(base + o_f0);
+        t.fm = (float*)(base + o_fm);
+        t.f1 = (float*)(base + o_f1);
+        t.d0 = (double*)(base + o_d0);
+        t.dm = (double*)(base + o_dm);
+        t.d1 = (double*)(base + o_d1);
+        t.row_class = (int8_t*)(base + o_cls);
+        t.row_sign = (int8_t*)(base + o_sgn);
+        t.row_lo = (int32_t*)(base + o_lo);
+        t.row_hi = (int32_t*)(base + o_hi);
+        if (p == 0) {
+            d_status = (int*)(base + o_st);
+            DR_HIP(hipMemsetAsync(d_status, 0, sizeof(int), c->stream));
+        }
+        int side = 0;
+        double scale = 1.0;
+        if (g->edge == DR_EDGE_TRAILING) {
+            side = 1;
+            scale = -1.0;
+        } else if (g->edge == DR_EDGE_BOTH) {
+            side = p;
+            scale = p == 0 ? 0.5 : -0.5;
+        }
+        DR_HIP(launch_build_plans(ga, t, side, scale, d_status, c->stream));
+    }
+    if (g->passes == 2)
+        DR_HIP(launch_unify_classes(g->t[0].row_class, g->t[1].row_class, ny, c->stream));
     int status = 0;
     DR_HIP(hipMemcpyAsync(&status, d_status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     DR_HIP(hipStreamSynchronize(c->stream));
@@ -424,9 +450,11 @@ static dr_status reconstruct_device(dr_geom g, const TileCfg& t, const uint16_t*
         dr_status st = ensure_scratch(g, t, &part);
         if (st != DR_OK) return st;
     }
-    ScanArgs a = scan_args(g, t, images, (int64_t)g->nx * g->ny, 0, 0, g->ny, out, part);
     if (g->timing) DR_HIP(hipEventRecord(g->ev[0], s));
-    DR_HIP(launch_rows_f32(t, a, s));
+    for (int p = 0; p < g->passes; ++p) {
+        ScanArgs a = scan_args(g, t, p, images, (int64_t)g->nx * g->ny, 0, 0, g->ny, out, part);
+        DR_HIP(launch_rows_f32(t, a, s));
+    }
     if (g->timing) DR_HIP(hipEventRecord(g->ev[1], s));
     if (totals)
         DR_HIP(enqueue_totals(g, part, partial_slots(g, t), g->work.as<double>(), totals, s));
@@ -481,10 +509,12 @@ static dr_status reconstruct_streamed(dr_geom g, const TileCfg& t, const uint16_
                                 hipMemcpyHostToDevice, c->copy));
         DR_HIP(hipEventRecord(c->slab_ready[b], c->copy));
         DR_HIP(hipStreamWaitEvent(s, c->slab_ready[b], 0));
-        ScanArgs a = scan_args(g, t, c->slab[b].as<uint16_t>(), (int64_t)R * g->nx, r0, r0,
-                               r0 + rs, out, part);
         if (g->timing && n == 0) DR_HIP(hipEventRecord(g->ev[0], s));
-        DR_HIP(launch_rows_f32(t, a, s));
+        for (int p = 0; p < g->passes; ++p) {
+            ScanArgs a = scan_args(g, t, p, c->slab[b].as<uint16_t>(), (int64_t)R * g->nx, r0,
+                                   r0, r0 + rs, out, part);
+            DR_HIP(launch_rows_f32(t, a, s));
+        }
         DR_HIP(hipEventRecord(c->slab_free[b], s));
     }
     if (g->timing) DR_HIP(hipEventRecord(g->ev[1], s));
@@ -528,25 +558,32 @@ dr_status dr_reconstruct_f64(dr_geom g, const uint16_t* images, double* out, dou
     double* part = nullptr;
     if (totals) {
         std::lock_guard<std::mutex> lk(g->mu);
-        DR_HIP(g->part64.reserve((size_t)partial_slots(g, t) * g->n_bins * sizeof(double)));
+        DR_HIP(g->part64.reserve((size_t)g->passes * partial_slots(g, t) * g->n_bins *
+                                 sizeof(double)));
         DR_HIP(g->work.reserve((size_t)kTotalsWorkRows * g->n_bins * sizeof(double)));
         part = g->part64.as<double>();
     }
-    ScanArgs a = scan_args(g, t, images, (int64_t)g->nx * g->ny, 0, 0, g->ny, nullptr, nullptr);
-    a.out = out;
-    a.partials = part;
-    DR_HIP(launch_rows_f64(a, s));
+    const int64_t slots = partial_slots(g, t);
+    for (int p = 0; p < g->passes; ++p) {
+        ScanArgs a = scan_args(g, t, p, images, (int64_t)g->nx * g->ny, 0, 0, g->ny, nullptr,
+                               nullptr);
+        a.out = out;
+        a.partials = part ? part + (size_t)p * slots * g->n_bins : nullptr;
+        DR_HIP(launch_rows_f64(a, s));
+    }
     if (totals)
-        DR_HIP(launch_totals_f64(part, partial_slots(g, t), g->n_bins, g->work.as<double>(),
+        DR_HIP(launch_totals_f64(part, slots * g->passes, g->n_bins, g->work.as<double>(),
                                  kTotalsWorkRows, totals, s));
     return ok();
 }
 
-dr_status dr_debug_plan(dr_geom g, const int64_t* pixels, int32_t n, int32_t* bins_out,
-                        double* u_out)
+dr_status dr_debug_plan(dr_geom g, const int64_t* pixels, int32_t n, int32_t edge,
+                        int32_t* bins_out, double* u_out)
 {
     if (!g || (n > 0 && !pixels)) return set_error(DR_E_INVAL, "dr_debug_plan: NULL argument");
     if (n < 0) return set_error(DR_E_INVAL, "dr_debug_plan: n < 0");
+    if (edge != DR_EDGE_LEADING && edge != DR_EDGE_TRAILING)
+        return set_error(DR_E_INVAL, "dr_debug_plan: edge must be leading or trailing");
     if (n == 0) return ok();
     const int64_t np = (int64_t)g->nx * g->ny;
     for (int32_t i = 0; i < n; ++i)
@@ -560,7 +597,8 @@ dr_status dr_debug_plan(dr_geom g, const int64_t* pixels, int32_t n, int32_t* bi
     if (bins_out) DR_HIP(db.reserve(cnt * sizeof(int32_t)));
     if (u_out) DR_HIP(du.reserve(cnt * sizeof(double)));
     DR_HIP(hipMemcpyAsync(dp.p, pixels, (size_t)n * sizeof(int64_t), hipMemcpyHostToDevice, s));
-    DR_HIP(launch_debug_plan(g->g, dp.as<int64_t>(), n, db.as<int32_t>(), du.as<double>(), s));
+    DR_HIP(launch_debug_plan(g->g, dp.as<int64_t>(), n, edge == DR_EDGE_TRAILING ? 1 : 0,
+                             db.as<int32_t>(), du.as<double>(), s));
     if (bins_out)
         DR_HIP(hipMemcpyAsync(bins_out, db.p, cnt * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     if (u_out) DR_HIP(hipMemcpyAsync(u_out, du.p, cnt * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -681,54 +719,78 @@ static dr_status batch_build_args(dr_batch b, const TileCfg& t, int gpc)
     b->slots.assign(n, 0);
     int64_t poff = 0;
     for (int i = 0; i < n; ++i) {
-        b->slots[i] = b->items[i].totals ? partial_slots(b->geoms[i], t) : 0;
+        b->slots[i] = b->items[i].totals ? partial_slots(b->geoms[i], t) : 0;  // per pass
         b->part_off[i] = poff;
-        poff += b->slots[i] * b->geoms[i]->n_bins;
+        poff += b->slots[i] * b->geoms[i]->passes * b->geoms[i]->n_bins;
     }
     DR_HIP(b->parts.reserve(std::max<size_t>(4, (size_t)poff * sizeof(float))));
     int maxB = 1;
     for (int i = 0; i < n; ++i) maxB = std::max(maxB, b->geoms[i]->n_bins);
     b->max_bins = maxB;
     DR_HIP(b->work.reserve((size_t)n * kTotalsWorkRows * maxB * sizeof(double)));
-    std::vector<ScanArgs> args(n);
-    std::vector<int64_t> start(n + 1, 0);
-    for (int w = 0; w < n; ++w) {
-        const int i = order[w];
-        const dr_geom g = b->geoms[i];
-        float* part = b->items[i].totals ? b->parts.as<float>() + b->part_off[i] : nullptr;
-        args[w] = scan_args(g, t, b->items[i].images, (int64_t)g->nx * g->ny, 0, 0, g->ny,
-                            b->items[i].out, part);
-        start[w + 1] = start[w] + (int64_t)g->ny * args[w].tiles_per_row;
+    // first launch: every scan's first (or only) pass; second launch: the
+    // second passes of two-edge scans, which add onto the first launch's output
+    std::vector<ScanArgs> args;
+    std::vector<int64_t> start1(1, 0), start2(1, 0);
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int w = 0; w < n; ++w) {
+            const int i = order[w];
+            const dr_geom g = b->geoms[i];
+            if (pass >= g->passes) continue;
+            float* part = b->items[i].totals ? b->parts.as<float>() + b->part_off[i] : nullptr;
+            ScanArgs a = scan_args(g, t, pass, b->items[i].images, (int64_t)g->nx * g->ny, 0, 0,
+                                   g->ny, b->items[i].out, part);
+            args.push_back(a);
+            std::vector<int64_t>& st = pass == 0 ? start1 : start2;
+            st.push_back(st.back() + (int64_t)g->ny * a.tiles_per_row);
+        }
     }
-    DR_HIP(b->scans.reserve(sizeof(ScanArgs) * n));
-    DR_HIP(b->starts.reserve(sizeof(int64_t) * (n + 1)));
-    DR_HIP(b->counter.reserve(sizeof(unsigned long long)));
-    DR_HIP(hipMemcpy(b->scans.p, args.data(), sizeof(ScanArgs) * n, hipMemcpyHostToDevice));
-    DR_HIP(hipMemcpy(b->starts.p, start.data(), sizeof(int64_t) * (n + 1),
+    b->n_args1 = (int)start1.size() - 1;
+    b->n_args2 = (int)start2.size() - 1;
+    std::vector<int64_t> starts(start1);
+    starts.insert(starts.end(), start2.begin(), start2.end());
+    DR_HIP(b->scans.reserve(sizeof(ScanArgs) * args.size()));
+    DR_HIP(b->starts.reserve(sizeof(int64_t) * starts.size()));
+    DR_HIP(b->counter.reserve(2 * sizeof(unsigned long long)));
+    DR_HIP(hipMemcpy(b->scans.p, args.data(), sizeof(ScanArgs) * args.size(),
                      hipMemcpyHostToDevice));
-    b->total_tiles = start[n];
+    DR_HIP(hipMemcpy(b->starts.p, starts.data(), sizeof(int64_t) * starts.size(),
+                     hipMemcpyHostToDevice));
+    b->total_tiles = start1.back();
+    b->total_tiles2 = start2.back();
     b->tile = t;
     b->gpc = gpc;
-    b->groups = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)c->cus * gpc, b->total_tiles));
+    // gpc == 0: one workgroup per tile (no persistent loop)
+    b->groups = gpc == 0 ? (int)std::min<int64_t>(b->total_tiles, INT32_MAX)
+                         : (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)c->cus * gpc,
+                                                                       b->total_tiles));
     return DR_OK;
 }
 
 static dr_status batch_enqueue(dr_batch b, hipStream_t s)
 {
-    BatchArgs ba{};
-    ba.scans = b->scans.as<ScanArgs>();
-    ba.tile_start = b->starts.as<int64_t>();
-    ba.n_scans = (int)b->items.size();
-    ba.total_tiles = b->total_tiles;
-    ba.counter = b->counter.as<unsigned long long>();
-    DR_HIP(launch_reset_counter(ba.counter, s));
-    DR_HIP(launch_batch_f32(b->tile, ba, b->groups, s));
+    for (int launch = 0; launch < 2; ++launch) {
+        const int na = launch == 0 ? b->n_args1 : b->n_args2;
+        if (na == 0) continue;
+        BatchArgs ba{};
+        ba.scans = b->scans.as<ScanArgs>() + (launch == 0 ? 0 : b->n_args1);
+        ba.tile_start = b->starts.as<int64_t>() + (launch == 0 ? 0 : b->n_args1 + 1);
+        ba.n_scans = na;
+        ba.total_tiles = launch == 0 ? b->total_tiles : b->total_tiles2;
+        ba.counter = b->counter.as<unsigned long long>() + launch;
+        const int64_t groups =
+            b->gpc == 0 ? ba.total_tiles
+                        : std::max<int64_t>(1, std::min<int64_t>((int64_t)b->ctx->cus * b->gpc,
+                                                                 ba.total_tiles));
+        DR_HIP(launch_reset_counter(ba.counter, s));
+        DR_HIP(launch_batch_f32(b->tile, ba, (int)std::min<int64_t>(groups, INT32_MAX), s));
+    }
     for (size_t i = 0; i < b->items.size(); ++i) {
         if (!b->items[i].totals) continue;
         const dr_geom g = b->geoms[i];
         double* work = b->work.as<double>() + i * (size_t)kTotalsWorkRows * b->max_bins;
-        DR_HIP(launch_totals_f32(b->parts.as<float>() + b->part_off[i], b->slots[i], g->n_bins,
-                                 work, kTotalsWorkRows, b->items[i].totals, s));
+        DR_HIP(enqueue_totals(g, b->parts.as<float>() + b->part_off[i], b->slots[i], work,
+                              b->items[i].totals, s));
     }
     return DR_OK;
 }
@@ -773,7 +835,7 @@ dr_status dr_batch_create(dr_ctx c, int32_t n, const dr_batch_item* items, int32
         TileCfg bt = t;
         int bg = gpc;
         for (const TileCfg& x : cands) {
-            for (int g : {1, 2, 4, 8}) {
+            for (int g : {0, 1, 2, 4, 8}) {
                 if (64 * x.waves * g > 2048) continue;  // CU thread limit
                 dr_status st = batch_build_args(b.get(), x, g);
                 if (st != DR_OK) return st;

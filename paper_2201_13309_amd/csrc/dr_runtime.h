@@ -78,9 +78,11 @@ struct dr_geom_s {
     int nx = 0, ny = 0, n_steps = 0, n_bins = 0;
     double radius = 0, first_center = 0, width = 0;
     bool row_mode = true;
+    int edge = DR_EDGE_LEADING;
+    int passes = 1;  // 2 for DR_EDGE_BOTH: leading, then trailing added on
     dr::GeomArgs g{};
-    dr::PlanTables t{};
-    dr::DevBuf wire, pix, plan;  // plan: all plan tables in one allocation
+    dr::PlanTables t[2]{};
+    dr::DevBuf wire, pix, plan[2];  // plan[p]: all plan tables of pass p in one allocation
     dr::DevBuf part32, part64, work;
     std::mutex mu;
     bool forced = false, tuned = false;
@@ -99,8 +101,10 @@ struct dr_batch_s {
     int gpc = 0;
     int max_bins = 1;
     dr::DevBuf scans, starts, counter, parts, work;
+    int64_t total_tiles2 = 0;       // tiles of second passes (launched after the first)
+    int n_args1 = 0, n_args2 = 0;   // ScanArgs entries of each launch
     std::vector<int64_t> part_off;  // per item offset into parts (floats)
-    std::vector<int64_t> slots;     // per item partial slots
+    std::vector<int64_t> slots;     // per item partial slots (all passes)
     int64_t total_tiles = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -111,9 +115,13 @@ namespace dr {
 // Shared helpers (dr_runtime.cpp) used by the scheduler.
 bool tile_fits(const dr_geom g, const TileCfg& t, const void* img, const void* out);
 TileCfg default_tile(const dr_geom g, const void* img, const void* out);
+// partial-total rows of one pass; a geometry with two passes uses twice as many
 int64_t partial_slots(const dr_geom g, const TileCfg& t);
-ScanArgs scan_args(const dr_geom g, const TileCfg& t, const uint16_t* img, int64_t img_step,
-                   int row_base, int row_begin, int row_end, float* out, float* partials);
+// arguments of pass `pass` (0 or 1); partials points at the base of all passes'
+// partial rows, the pass's own rows are selected here
+ScanArgs scan_args(const dr_geom g, const TileCfg& t, int pass, const uint16_t* img,
+                   int64_t img_step, int row_base, int row_begin, int row_end, float* out,
+                   float* partials);
 hipError_t enqueue_totals(const dr_geom g, const float* partials, int64_t slots, double* work,
                           float* totals, hipStream_t s);
 

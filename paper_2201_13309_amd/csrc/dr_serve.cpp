@@ -33,6 +33,7 @@ constexpr int kEpochsInFlight = 2;
 constexpr int kCopiesInFlight = 2;
 constexpr int kMaxActive = 64;     // admitted requests at a time
 constexpr int kMaxSegs = 256;      // request segments per epoch and group
+constexpr int kGroups = 6;         // (pass 1 or 2) x (4, 2 or 1 pixels per lane)
 
 struct Request {
     uint64_t id = 0;
@@ -57,7 +58,7 @@ struct Request {
 };
 
 struct EpochSlot {
-    DevBuf args;   // ScanArgs[3][kMaxSegs] + starts[3][kMaxSegs+1] + counters[3]
+    DevBuf args;   // ScanArgs[kGroups][kMaxSegs] + starts[kGroups][kMaxSegs+1] + counters
     ScanArgs* h_args = nullptr;  // pinned staging
     int64_t* h_starts = nullptr;
     hipEvent_t uploaded = nullptr;
@@ -115,7 +116,8 @@ struct Scheduler {
     }
     static size_t parts_bytes(const Request* r)
     {
-        return r->totals ? (size_t)partial_slots(r->g, r->tile) * r->g->n_bins * sizeof(float) +
+        return r->totals ? (size_t)r->g->passes * partial_slots(r->g, r->tile) * r->g->n_bins *
+                                   sizeof(float) +
                                (size_t)kTotalsWorkRows * r->g->n_bins * sizeof(double)
                          : 0;
     }
@@ -131,7 +133,8 @@ struct Scheduler {
             hipError_t e = hipSuccess;
             if (sb) e = hipMallocAsync((void**)&r->staged, sb, ctx->copy);
             if (e == hipSuccess && r->totals) {
-                const size_t pb = (size_t)partial_slots(r->g, r->tile) * r->g->n_bins * sizeof(float);
+                const size_t pb =
+                    (size_t)r->g->passes * partial_slots(r->g, r->tile) * r->g->n_bins * sizeof(float);
                 e = hipMallocAsync((void**)&r->parts, pb, ctx->copy);
                 if (e == hipSuccess)
                     e = hipMallocAsync((void**)&r->work,
@@ -237,47 +240,56 @@ struct Scheduler {
         }
         if (!es) return false;
         // segments: resident, unprocessed rows of every admitted request,
-        // grouped by pixels per lane (one launch per group)
+        // grouped by pass and pixels per lane (one launch per group; every
+        // second-pass launch follows every first-pass launch of the epoch)
         static const int kPpl[3] = {4, 2, 1};
-        int nseg[3] = {0, 0, 0};
-        int64_t tiles[3] = {0, 0, 0};
+        int nseg[kGroups] = {0, 0, 0, 0, 0, 0};
+        int64_t tiles[kGroups] = {0, 0, 0, 0, 0, 0};
         std::vector<Request*> finishing;
         for (Request* r : active) {
             if (r->state != 1 || r->finishing) continue;
-            const int gi = r->tile.ppl == 4 ? 0 : (r->tile.ppl == 2 ? 1 : 2);
-            if (r->rows_ready > r->rows_next && nseg[gi] < kMaxSegs) {
+            const int pi = r->tile.ppl == 4 ? 0 : (r->tile.ppl == 2 ? 1 : 2);
+            const int passes = r->g->passes;
+            bool room = true;
+            for (int p = 0; p < passes; ++p) room = room && nseg[p * 3 + pi] < kMaxSegs;
+            if (r->rows_ready > r->rows_next && room) {
                 const uint16_t* img = r->on_device ? r->images : r->staged;
-                ScanArgs a = scan_args(r->g, r->tile, img, (int64_t)r->g->nx * r->g->ny, 0,
-                                       r->rows_next, r->rows_ready, r->out, r->parts);
-                const int s = nseg[gi]++;
-                es->h_args[gi * kMaxSegs + s] = a;
-                int64_t* st = es->h_starts + gi * (kMaxSegs + 1);
-                if (s == 0) st[0] = 0;
-                st[s + 1] = st[s] + (int64_t)(r->rows_ready - r->rows_next) * a.tiles_per_row;
-                tiles[gi] = st[s + 1];
+                for (int p = 0; p < passes; ++p) {
+                    const int gi = p * 3 + pi;
+                    ScanArgs a = scan_args(r->g, r->tile, p, img, (int64_t)r->g->nx * r->g->ny,
+                                           0, r->rows_next, r->rows_ready, r->out, r->parts);
+                    const int sg = nseg[gi]++;
+                    es->h_args[gi * kMaxSegs + sg] = a;
+                    int64_t* st = es->h_starts + gi * (kMaxSegs + 1);
+                    if (sg == 0) st[0] = 0;
+                    st[sg + 1] = st[sg] + (int64_t)(r->rows_ready - r->rows_next) * a.tiles_per_row;
+                    tiles[gi] = st[sg + 1];
+                }
                 r->rows_next = r->rows_ready;
             }
             if (r->rows_next == r->g->ny) finishing.push_back(r);
         }
-        if (nseg[0] + nseg[1] + nseg[2] == 0 && finishing.empty()) return false;
+        int nall = 0;
+        for (int gi = 0; gi < kGroups; ++gi) nall += nseg[gi];
+        if (nall == 0 && finishing.empty()) return false;
         hipStream_t s = ctx->stream;
         char* dbase = es->args.as<char>();
         ScanArgs* d_args = (ScanArgs*)dbase;
-        int64_t* d_starts = (int64_t*)(dbase + sizeof(ScanArgs) * 3 * kMaxSegs);
+        int64_t* d_starts = (int64_t*)(dbase + sizeof(ScanArgs) * kGroups * kMaxSegs);
         unsigned long long* d_cnt =
-            (unsigned long long*)(dbase + sizeof(ScanArgs) * 3 * kMaxSegs +
-                                  sizeof(int64_t) * 3 * (kMaxSegs + 1));
+            (unsigned long long*)(dbase + sizeof(ScanArgs) * kGroups * kMaxSegs +
+                                  sizeof(int64_t) * kGroups * (kMaxSegs + 1));
         hipError_t e = hipSuccess;
         // the pinned staging of this slot was last read by an upload that has
         // completed (the slot is not busy), so it can be rewritten and sent
-        e = hipMemcpyAsync(d_args, es->h_args, sizeof(ScanArgs) * 3 * kMaxSegs,
+        e = hipMemcpyAsync(d_args, es->h_args, sizeof(ScanArgs) * kGroups * kMaxSegs,
                            hipMemcpyHostToDevice, s);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(d_starts, es->h_starts, sizeof(int64_t) * 3 * (kMaxSegs + 1),
+            e = hipMemcpyAsync(d_starts, es->h_starts, sizeof(int64_t) * kGroups * (kMaxSegs + 1),
                                hipMemcpyHostToDevice, s);
         // rows are handed out only after the host has seen their copy event
         // complete, so the kernels below read finished copies
-        for (int gi = 0; gi < 3 && e == hipSuccess; ++gi) {
+        for (int gi = 0; gi < kGroups && e == hipSuccess; ++gi) {
             if (!nseg[gi]) continue;
             BatchArgs ba{};
             ba.scans = d_args + gi * kMaxSegs;
@@ -285,7 +297,7 @@ struct Scheduler {
             ba.n_scans = nseg[gi];
             ba.total_tiles = tiles[gi];
             ba.counter = d_cnt + gi;
-            const TileCfg t{kPpl[gi], 4, 16};
+            const TileCfg t{kPpl[gi % 3], 4, 16};
             const int groups = (int)std::max<int64_t>(1, std::min<int64_t>(ctx->cus * 2, tiles[gi]));
             e = launch_reset_counter(ba.counter, s);
             if (e == hipSuccess) e = launch_batch_f32(t, ba, groups, s);
@@ -389,11 +401,12 @@ Scheduler* make_scheduler(dr_ctx ctx)
     auto* s = new Scheduler();
     s->ctx = ctx;
     for (auto& es : s->slots) {
-        const size_t bytes = sizeof(ScanArgs) * 3 * kMaxSegs + sizeof(int64_t) * 3 * (kMaxSegs + 1) +
-                             sizeof(unsigned long long) * 3;
+        const size_t bytes = sizeof(ScanArgs) * kGroups * kMaxSegs +
+                             sizeof(int64_t) * kGroups * (kMaxSegs + 1) +
+                             sizeof(unsigned long long) * kGroups;
         if (es.args.reserve(bytes) != hipSuccess ||
-            hipHostMalloc((void**)&es.h_args, sizeof(ScanArgs) * 3 * kMaxSegs, 0) != hipSuccess ||
-            hipHostMalloc((void**)&es.h_starts, sizeof(int64_t) * 3 * (kMaxSegs + 1), 0) != hipSuccess ||
+            hipHostMalloc((void**)&es.h_args, sizeof(ScanArgs) * kGroups * kMaxSegs, 0) != hipSuccess ||
+            hipHostMalloc((void**)&es.h_starts, sizeof(int64_t) * kGroups * (kMaxSegs + 1), 0) != hipSuccess ||
             hipEventCreateWithFlags(&es.uploaded, hipEventDisableTiming) != hipSuccess ||
             hipEventCreateWithFlags(&es.finished, hipEventDisableTiming) != hipSuccess) {
             destroy_scheduler(s);

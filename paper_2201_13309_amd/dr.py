@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libdr.so")
 DR_OK, DR_PENDING = 0, 1
 DR_E_INVAL, DR_E_NOMEM, DR_E_UNSUPPORTED, DR_E_DEVICE, DR_E_BUSY, DR_E_NOTFOUND = (
     -1, -2, -3, -4, -5, -6)
-DR_EDGE_LEADING = 0
+DR_EDGE_LEADING, DR_EDGE_TRAILING, DR_EDGE_BOTH = 0, 1, 2
 DR_BATCH_AUTOTUNE, DR_BATCH_GRAPH = 1, 2
 
 # names exported by libdr.so, as declared in include/dr.h
@@ -100,7 +100,7 @@ def load(path: Optional[str] = None):
         "dr_autotune": [vp, vp, vp, P(dr_tile_config)],
         "dr_reconstruct": [vp, vp, ctypes.c_int, vp, vp, vp],
         "dr_reconstruct_f64": [vp, vp, vp, vp, vp],
-        "dr_debug_plan": [vp, vp, i32, vp, vp],
+        "dr_debug_plan": [vp, vp, i32, i32, vp, vp],
         "dr_enable_timing": [vp, ctypes.c_int],
         "dr_last_timing": [vp, P(ctypes.c_double), P(ctypes.c_double)],
         "dr_batch_create": [vp, i32, P(dr_batch_item), i32, P(vp)],
@@ -240,11 +240,13 @@ def dr_reconstruct_f64(geom: int, images_dev, out, totals=None, stream=None):
                                      stream_handle(stream)))
 
 
-def dr_debug_plan(geom: int, pixels, n_steps: int, want_bins: bool = True, want_u: bool = True):
+def dr_debug_plan(geom: int, pixels, n_steps: int, want_bins: bool = True, want_u: bool = True,
+                  edge: int = DR_EDGE_LEADING):
     pix = np.ascontiguousarray(np.asarray(pixels, dtype=np.int64))
     bins = np.empty((pix.shape[0], n_steps), dtype=np.int32) if want_bins else None
     u = np.empty((pix.shape[0], n_steps), dtype=np.float64) if want_u else None
-    _check(load().dr_debug_plan(geom, pix.ctypes.data, int(pix.shape[0]), ptr(bins), ptr(u)))
+    _check(load().dr_debug_plan(geom, pix.ctypes.data, int(pix.shape[0]), int(edge), ptr(bins),
+                                ptr(u)))
     return bins, u
 
 

@@ -47,7 +47,7 @@ def test_null_arguments_rejected_without_device(lib):
     assert lib.dr_submit(None, None, None, 0, None, None, ctypes.byref(t)) == dr.DR_E_INVAL
     assert lib.dr_poll(None, 1) == dr.DR_E_INVAL
     assert lib.dr_ctx_create(0, 0, None) == dr.DR_E_INVAL
-    assert lib.dr_debug_plan(None, None, 0, None, None) == dr.DR_E_INVAL
+    assert lib.dr_debug_plan(None, None, 0, 0, None, None) == dr.DR_E_INVAL
 
 
 def test_ctx_create_without_gpu_fails_cleanly(lib):

@@ -52,6 +52,8 @@ def uneven_scans(seed, odd=False):
         src = synth.draw_sources(rng, max(2, side * side // 800), nx, side, -half, half)
         s = synth.Scan(f"u{n}", det, wire, grid, src, dark=100.0, noise=True, seed=seed * 10 + n)
         synth.render(s)
+        s.wire.edge = (synth.EDGE_LEADING, synth.EDGE_LEADING, synth.EDGE_BOTH,
+                       synth.EDGE_LEADING, synth.EDGE_TRAILING, synth.EDGE_BOTH)[n]
         scans.append(s)
     return scans
 

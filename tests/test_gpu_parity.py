@@ -77,11 +77,20 @@ def make_case(name):
         s.detector = synth.Detector(40, 6, s.detector.origin, s.detector.u, s.detector.v,
                                     pixel_xyz=xyz)
         return s
+    if name.startswith("trailing_") or name.startswith("both_"):
+        edge, base = name.split("_", 1)
+        s = make_case(base)
+        if base == "config1":
+            s.grid = synth.centered_grid(201, 1.0)  # room for the trailing sweep
+        s.wire.edge = synth.EDGE_TRAILING if edge == "trailing" else synth.EDGE_BOTH
+        return s
     raise KeyError(name)
 
 
 CASES = ["config1", "ragged_301x7", "wide_2500x5", "long_1500_steps", "decreasing",
-         "non_monotone", "narrow_grid", "coarse_steps", "degenerate_1x1", "pixel_table"]
+         "non_monotone", "narrow_grid", "coarse_steps", "degenerate_1x1", "pixel_table",
+         "trailing_config1", "trailing_decreasing", "both_config1", "both_ragged_301x7",
+         "both_decreasing", "both_non_monotone", "both_long_1500_steps"]
 
 
 @pytest.mark.parametrize("name", CASES)
@@ -90,14 +99,20 @@ def test_positions_bit_exact(dr, ctx, name):
     nx, ny = s.detector.nx, s.detector.ny
     rng = np.random.default_rng(1)
     pix = np.unique(np.concatenate([[0, nx * ny - 1], rng.integers(0, nx * ny, 64)]))
-    _, bins_ref, u_ref = oracle.reconstruct_pixels(s, pix, want_bins=True, want_u=True)
+    edges = {synth.EDGE_LEADING: [0], synth.EDGE_TRAILING: [1], synth.EDGE_BOTH: [0, 1]}
     g = dr.dr_geometry_init(ctx, s.detector, s.wire, s.grid)
     try:
-        bins, u = dr.dr_debug_plan(g, pix, s.wire.n_steps)
+        for side in edges[s.wire.edge]:
+            ref_scan = synth.Scan(s.name, s.detector, synth.Wire(s.wire.radius, s.wire.centers,
+                                                                  edge=side), s.grid,
+                                  s.sources, s.dark, s.noise, s.seed)
+            _, bins_ref, u_ref = oracle.reconstruct_pixels(ref_scan, pix, want_bins=True,
+                                                           want_u=True)
+            bins, u = dr.dr_debug_plan(g, pix, s.wire.n_steps, edge=side)
+            assert np.array_equal(bins, bins_ref), side
+            assert np.array_equal(u.view(np.int64), u_ref.view(np.int64)), side
     finally:
         dr.dr_geometry_free(g)
-    assert np.array_equal(bins, bins_ref)
-    assert np.array_equal(u.view(np.int64), u_ref.view(np.int64))
 
 
 @pytest.mark.parametrize("name", CASES)
