@@ -47,10 +47,10 @@ def load(path: Optional[str] = None):
         lib.oracle_edge_sign.restype = i32
         lib.oracle_bin_profile.argtypes = [p, p, i32, i32, i32, p, i64]
         lib.oracle_bin_profile.restype = None
-        lib.oracle_reconstruct.argtypes = [i32, i32, p, p, p, p, d, i32, p, i32, d, d, i32, p,
-                                           i32, i32, p, p, p, i32]
+        lib.oracle_reconstruct.argtypes = [i32, i32, p, p, p, p, d, p, i32, p, i32, d, d, i32,
+                                           p, i32, i32, p, p, p, i32]
         lib.oracle_reconstruct.restype = i32
-        lib.oracle_reconstruct_pixels.argtypes = [i32, i32, p, p, p, p, d, i32, p, i32, d, d,
+        lib.oracle_reconstruct_pixels.argtypes = [i32, i32, p, p, p, p, d, p, i32, p, i32, d, d,
                                                   i32, p, p, p, i64, p, p, p, i32]
         lib.oracle_reconstruct_pixels.restype = i32
         _libs[path] = lib
@@ -75,8 +75,11 @@ def tangent_depth(py, pz, cy, cz, r, s, lib=None) -> float:
 
 
 def edge_sign(py, pz, centers, r, lib=None) -> int:
+    """Leading side for a pixel at (y, z) and wire centres [N][3] with the wire
+    axis along x (the projection is then (eta, xi) = (y, z))."""
     c = _f64(centers)
-    return (lib or load()).oracle_edge_sign(float(py), float(pz), c.shape[0], _p(c), float(r))
+    wyz = np.ascontiguousarray(c[:, 1:3])
+    return (lib or load()).oracle_edge_sign(float(py), float(pz), wyz.shape[0], _p(wyz), float(r))
 
 
 EDGE_LEADING, EDGE_TRAILING, EDGE_BOTH = 0, 1, 2
@@ -99,10 +102,11 @@ def _geom_args(scan):
     origin, u, v = _f64(det.origin), _f64(det.u), _f64(det.v)
     pxyz = None if det.pixel_xyz is None else _f64(det.pixel_xyz)
     centers = _f64(wire.centers)
-    keep = (origin, u, v, pxyz, centers)
+    axis = _f64(getattr(wire, "axis", (1.0, 0.0, 0.0)))
+    keep = (origin, u, v, pxyz, centers, axis)
     args = (int(det.nx), int(det.ny), _p(origin), _p(u), _p(v), _p(pxyz), float(wire.radius),
-            int(centers.shape[0]), _p(centers), int(grid.n_bins), float(grid.first_center),
-            float(grid.width), int(getattr(wire, "edge", EDGE_LEADING)))
+            _p(axis), int(centers.shape[0]), _p(centers), int(grid.n_bins),
+            float(grid.first_center), float(grid.width), int(getattr(wire, "edge", EDGE_LEADING)))
     return args, keep
 
 

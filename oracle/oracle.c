@@ -12,15 +12,24 @@
  * geometry to the differential-aperture method it cites, so the geometry below
  * is the reading written down with the tests):
  *
- *   frame      um, beam along +z through x = y = 0, depth = z; the wire axis is
- *              x, so only (y, z) projections matter.
+ *   frame      um, beam along +z through x = y = 0, depth = z.  The wire is a
+ *              cylinder of radius r around an axis of unit direction a (the
+ *              lab x axis in the standard set-up).  Everything is projected
+ *              onto the plane normal to a, with coordinates
+ *                xi  = X . e1,  e1 = (z - (z.a) a) / |z - (z.a) a|
+ *                eta = X . e2,  e2 = e1 x a
+ *              in which the beam is the xi axis (beam point d -> xi = c d,
+ *              c = e1.z) and the wire is a disc; for a = x this is
+ *              (xi, eta) = (z, y) exactly.
  *   pixel      P = (origin + i*u) + j*v for column i and row j, or an explicit
- *              per-pixel table.
- *   depth      for pixel P, wire centre C_k and radius r, the ray from P that is
- *              tangent to the wire on side s (+1: the +z side) meets the beam at
- *                d = Cz - (Cy*tz + s*r*L2) / ty
+ *              per-pixel table, then projected.
+ *   depth      for projected pixel P, wire centre C_k and radius r, the ray
+ *              from P tangent to the disc on side s (+1: the +xi side) meets
+ *              the xi axis at
+ *                xi* = C_xi - (C_eta*t_xi + s*r*L2) / t_eta
  *              with a = C - P, L2 = |a|^2, kk = sqrt(L2 - r^2),
- *              tz = az*kk - ay*s*r, ty = ay*kk + az*s*r.
+ *              t_xi = a_xi*kk - a_eta*s*r, t_eta = a_eta*kk + a_xi*s*r,
+ *              and depth d = xi* / c.
  *   edge       s_p = +1 when that +z-side depth moves toward +z over the scan
  *              (last step vs first step), else -1.  The leading edge uses
  *              side s_p and dI_k = I_k - I_{k+1} (intensity lost as the edge
@@ -58,8 +67,9 @@
 #define EDGE_TRAILING 1
 #define EDGE_BOTH 2
 
-/* Depth at which the ray from (py, pz), tangent to the wire disc centred at
- * (cy, cz) on side s, meets the beam.  Returns NAN when the pixel is inside
+/* In the plane normal to the wire axis: the xi coordinate at which the ray
+ * from (py, pz) = (eta, xi) of the pixel, tangent to the wire disc centred at
+ * (cy, cz) on side s, meets the xi axis.  Returns NAN when the pixel is inside
  * the disc. */
 double oracle_tangent_depth(double py, double pz, double cy, double cz, double r, int s)
 {
@@ -75,28 +85,71 @@ double oracle_tangent_depth(double py, double pz, double cy, double cz, double r
     return cz - (cy * tz + sr * L2) / ty;
 }
 
-/* Leading-edge side for one pixel: +1 when the +z tangent depth grows from the
- * first to the last wire position, else -1. */
-int oracle_edge_sign(double py, double pz, int n_steps, const double* centers, double r)
+/* Projection frame of the plane normal to the wire axis: e1 (projected beam
+ * direction), e2 = e1 x a, and c = e1.z.  Returns ORACLE_EINVAL for a zero
+ * axis or an axis parallel to the beam. */
+typedef struct {
+    double e1[3], e2[3], c;
+} frame_t;
+
+static int axis_frame(const double* axis, frame_t* f)
 {
-    double d0 = oracle_tangent_depth(py, pz, centers[1], centers[2], r, +1);
-    double d1 = oracle_tangent_depth(py, pz, centers[3 * (n_steps - 1) + 1],
-                                     centers[3 * (n_steps - 1) + 2], r, +1);
+    double n = sqrt((axis[0] * axis[0] + axis[1] * axis[1]) + axis[2] * axis[2]);
+    if (!(n > 0.0)) return ORACLE_EINVAL;
+    double a[3] = {axis[0] / n, axis[1] / n, axis[2] / n};
+    double zp[3] = {0.0 - a[2] * a[0], 0.0 - a[2] * a[1], 1.0 - a[2] * a[2]};
+    double m = sqrt((zp[0] * zp[0] + zp[1] * zp[1]) + zp[2] * zp[2]);
+    if (!(m > 1e-6)) return ORACLE_EINVAL;
+    for (int q = 0; q < 3; ++q) f->e1[q] = zp[q] / m;
+    f->e2[0] = f->e1[1] * a[2] - f->e1[2] * a[1];
+    f->e2[1] = f->e1[2] * a[0] - f->e1[0] * a[2];
+    f->e2[2] = f->e1[0] * a[1] - f->e1[1] * a[0];
+    f->c = f->e1[2];
+    return ORACLE_OK;
+}
+
+/* (eta, xi) of a lab point */
+static void project(const frame_t* f, const double* X, double* eta, double* xi)
+{
+    *xi = (X[0] * f->e1[0] + X[1] * f->e1[1]) + X[2] * f->e1[2];
+    *eta = (X[0] * f->e2[0] + X[1] * f->e2[1]) + X[2] * f->e2[2];
+}
+
+/* Leading-edge side for one pixel: +1 when the +xi (downstream) tangent
+ * point of the last wire position lies beyond that of the first, else -1.
+ * wyz: projected wire centres [n_steps][2] as (eta, xi). */
+int oracle_edge_sign(double py, double pz, int n_steps, const double* wyz, double r)
+{
+    double d0 = oracle_tangent_depth(py, pz, wyz[0], wyz[1], r, +1);
+    double d1 = oracle_tangent_depth(py, pz, wyz[2 * (n_steps - 1)],
+                                     wyz[2 * (n_steps - 1) + 1], r, +1);
     return (d1 > d0) ? +1 : -1;
 }
 
-static void pixel_center(int nx, const double* origin, const double* u, const double* v,
-                         const double* pixel_xyz, int64_t p, double* py, double* pz)
+/* Projected (eta, xi) of pixel p. */
+static void pixel_center(const frame_t* f, int nx, const double* origin, const double* u,
+                         const double* v, const double* pixel_xyz, int64_t p, double* py,
+                         double* pz)
 {
+    double X[3];
     if (pixel_xyz) {
-        *py = pixel_xyz[3 * p + 1];
-        *pz = pixel_xyz[3 * p + 2];
-        return;
+        X[0] = pixel_xyz[3 * p];
+        X[1] = pixel_xyz[3 * p + 1];
+        X[2] = pixel_xyz[3 * p + 2];
+    } else {
+        double i = (double)(p % nx);
+        double j = (double)(p / nx);
+        for (int q = 0; q < 3; ++q) X[q] = (origin[q] + i * u[q]) + j * v[q];
     }
-    double i = (double)(p % nx);
-    double j = (double)(p / nx);
-    *py = (origin[1] + i * u[1]) + j * v[1];
-    *pz = (origin[2] + i * u[2]) + j * v[2];
+    project(f, X, py, pz);
+}
+
+/* Projected wire centres [n_steps][2] (eta, xi); caller frees. */
+static double* project_wire(const frame_t* f, int n_steps, const double* centers)
+{
+    double* w = (double*)malloc(sizeof(double) * 2 * (size_t)n_steps);
+    for (int k = 0; k < n_steps; ++k) project(f, centers + 3 * k, &w[2 * k], &w[2 * k + 1]);
+    return w;
 }
 
 static int32_t floor_to_i32(double x)
@@ -110,13 +163,13 @@ static int32_t floor_to_i32(double x)
 /* Positions u_k of one edge (leading, or trailing when `trailing` is set) in
  * bin units for one pixel.  Returns ORACLE_EINVAL if the pixel is inside the
  * wire or a value is not finite. */
-static int pixel_positions(double py, double pz, int n_steps, const double* centers, double r,
-                           double e0, double invw, int trailing, double* u)
+static int pixel_positions(double py, double pz, int n_steps, const double* wyz, double r,
+                           double c, double e0, double invw, int trailing, double* u)
 {
-    int s = oracle_edge_sign(py, pz, n_steps, centers, r);
+    int s = oracle_edge_sign(py, pz, n_steps, wyz, r);
     if (trailing) s = -s;
     for (int k = 0; k < n_steps; ++k) {
-        double d = oracle_tangent_depth(py, pz, centers[3 * k + 1], centers[3 * k + 2], r, s);
+        double d = oracle_tangent_depth(py, pz, wyz[2 * k], wyz[2 * k + 1], r, s) / c;
         u[k] = (d - e0) * invw;
         if (!isfinite(u[k])) return ORACLE_EINVAL;
     }
@@ -159,22 +212,23 @@ void oracle_bin_profile(const double* u, const double* I, int n_steps, int n_bin
  * scratch; the positions of the reported edge (trailing for TRAILING, else
  * leading) are left in uk. */
 static int pixel_profile(double py, double pz, const double* Ik, int n_steps,
-                         const double* centers, double r, double e0, double invw, int n_bins,
-                         int edge, double* o, int64_t stride, double* uk, double* tmp)
+                         const double* wyz, double r, double c, double e0, double invw,
+                         int n_bins, int edge, double* o, int64_t stride, double* uk,
+                         double* tmp)
 {
     if (edge == EDGE_BOTH) {
-        if (pixel_positions(py, pz, n_steps, centers, r, e0, invw, 1, uk) != ORACLE_OK)
+        if (pixel_positions(py, pz, n_steps, wyz, r, c, e0, invw, 1, uk) != ORACLE_OK)
             return ORACLE_EINVAL;
         for (int b = 0; b < n_bins; ++b) tmp[b] = 0.0;
         oracle_bin_profile(uk, Ik, n_steps, n_bins, 1, tmp, 1);
-        if (pixel_positions(py, pz, n_steps, centers, r, e0, invw, 0, uk) != ORACLE_OK)
+        if (pixel_positions(py, pz, n_steps, wyz, r, c, e0, invw, 0, uk) != ORACLE_OK)
             return ORACLE_EINVAL;
         oracle_bin_profile(uk, Ik, n_steps, n_bins, 0, o, stride);
         for (int b = 0; b < n_bins; ++b) o[(int64_t)b * stride] = 0.5 * (o[(int64_t)b * stride] + tmp[b]);
         return ORACLE_OK;
     }
     const int trailing = edge == EDGE_TRAILING;
-    if (pixel_positions(py, pz, n_steps, centers, r, e0, invw, trailing, uk) != ORACLE_OK)
+    if (pixel_positions(py, pz, n_steps, wyz, r, c, e0, invw, trailing, uk) != ORACLE_OK)
         return ORACLE_EINVAL;
     oracle_bin_profile(uk, Ik, n_steps, n_bins, trailing, o, stride);
     return ORACLE_OK;
@@ -190,8 +244,9 @@ static int pixel_profile(double py, double pz, const double* Ik, int n_steps,
  * Returns ORACLE_OK or ORACLE_EINVAL.
  */
 int oracle_reconstruct(int nx, int ny, const double* origin, const double* u, const double* v,
-                       const double* pixel_xyz, double radius, int n_steps, const double* centers,
-                       int n_bins, double first_center, double width, int edge,
+                       const double* pixel_xyz, double radius, const double* axis, int n_steps,
+                       const double* centers, int n_bins, double first_center, double width,
+                       int edge,
                        const uint16_t* images, int row0, int nrows, double* out, double* totals,
                        int32_t* bins, int nthreads)
 {
@@ -199,11 +254,14 @@ int oracle_reconstruct(int nx, int ny, const double* origin, const double* u, co
         return ORACLE_EINVAL;
     if (edge < EDGE_LEADING || edge > EDGE_BOTH) return ORACLE_EINVAL;
     if (row0 < 0 || nrows < 0 || row0 + nrows > ny) return ORACLE_EINVAL;
+    frame_t fr;
+    if (axis_frame(axis, &fr) != ORACLE_OK) return ORACLE_EINVAL;
     const double e0 = first_center - width / 2.0;
     const double invw = 1.0 / width;
     const int64_t plane_in = (int64_t)nx * ny;
     const int64_t plane_out = (int64_t)nx * nrows;
     memset(out, 0, sizeof(double) * (size_t)plane_out * (size_t)n_bins);
+    double* wyz = project_wire(&fr, n_steps, centers);
     int status = ORACLE_OK;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -222,9 +280,9 @@ int oracle_reconstruct(int nx, int ny, const double* origin, const double* u, co
                 int64_t p = (int64_t)(row0 + jr) * nx + i;
                 int64_t q = (int64_t)jr * nx + i;
                 double py, pz;
-                pixel_center(nx, origin, u, v, pixel_xyz, p, &py, &pz);
+                pixel_center(&fr, nx, origin, u, v, pixel_xyz, p, &py, &pz);
                 for (int k = 0; k < n_steps; ++k) Ik[k] = (double)images[(int64_t)k * plane_in + p];
-                if (pixel_profile(py, pz, Ik, n_steps, centers, radius, e0, invw, n_bins, edge,
+                if (pixel_profile(py, pz, Ik, n_steps, wyz, radius, fr.c, e0, invw, n_bins, edge,
                                   out + q, plane_out, uk, tmp) != ORACLE_OK) {
 #pragma omp atomic write
                     status = ORACLE_EINVAL;
@@ -238,6 +296,7 @@ int oracle_reconstruct(int nx, int ny, const double* origin, const double* u, co
         free(Ik);
         free(tmp);
     }
+    free(wyz);
     if (status != ORACLE_OK) return status;
     if (totals) {
         for (int b = 0; b < n_bins; ++b) {
@@ -260,7 +319,7 @@ int oracle_reconstruct(int nx, int ny, const double* origin, const double* u, co
  */
 int oracle_reconstruct_pixels(int nx, int ny, const double* origin, const double* u,
                               const double* v, const double* pixel_xyz, double radius,
-                              int n_steps, const double* centers, int n_bins,
+                              const double* axis, int n_steps, const double* centers, int n_bins,
                               double first_center, double width, int edge,
                               const uint16_t* images, const uint16_t* series,
                               const int64_t* pixels, int64_t npix, double* out, int32_t* bins,
@@ -269,9 +328,12 @@ int oracle_reconstruct_pixels(int nx, int ny, const double* origin, const double
     if (nx <= 0 || ny <= 0 || n_steps < 2 || n_bins <= 0 || !(width > 0.0) || !(radius > 0.0))
         return ORACLE_EINVAL;
     if (edge < EDGE_LEADING || edge > EDGE_BOTH) return ORACLE_EINVAL;
+    frame_t fr;
+    if (axis_frame(axis, &fr) != ORACLE_OK) return ORACLE_EINVAL;
     const double e0 = first_center - width / 2.0;
     const double invw = 1.0 / width;
     const int64_t plane_in = (int64_t)nx * ny;
+    double* wyz = project_wire(&fr, n_steps, centers);
     int status = ORACLE_OK;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -294,12 +356,12 @@ int oracle_reconstruct_pixels(int nx, int ny, const double* origin, const double
                 continue;
             }
             double py, pz;
-            pixel_center(nx, origin, u, v, pixel_xyz, p, &py, &pz);
+            pixel_center(&fr, nx, origin, u, v, pixel_xyz, p, &py, &pz);
             for (int k = 0; k < n_steps; ++k)
                 Ik[k] = series ? (double)series[n * n_steps + k]
                                : (images ? (double)images[(int64_t)k * plane_in + p] : 0.0);
-            if (pixel_profile(py, pz, Ik, n_steps, centers, radius, e0, invw, n_bins, edge, o, 1,
-                              uk, tmp) != ORACLE_OK) {
+            if (pixel_profile(py, pz, Ik, n_steps, wyz, radius, fr.c, e0, invw, n_bins, edge, o,
+                              1, uk, tmp) != ORACLE_OK) {
 #pragma omp atomic write
                 status = ORACLE_EINVAL;
                 continue;
@@ -315,5 +377,6 @@ int oracle_reconstruct_pixels(int nx, int ny, const double* origin, const double
         free(Ik);
         free(tmp);
     }
+    free(wyz);
     return status;
 }

@@ -339,8 +339,141 @@ def pin_poisson_recovery(lib):
     assert tot >= 30 and ok >= math.ceil(0.99 * tot), (ok, tot)
 
 
+# ------------------------------------------------- tilted wire axis (3D pins)
+
+
+def line_segment_dist3(C, a, S, P):
+    """Distance between the line C + t*a (a unit) and the segment S->P in 3D,
+    from the closest points of the two lines, the segment parameter clamped."""
+    C, a, S, P = (np.asarray(x, dtype=np.float64) for x in (C, a, S, P))
+    d = P - S
+    w = S - C
+    A, Bq, Cq = float(a @ a), float(a @ d), float(d @ d)
+    D, E = float(a @ w), float(d @ w)
+    den = A * Cq - Bq * Bq
+    sp = (A * E * -1.0 + Bq * D) / den if den > 0 else 0.0
+    sp = min(1.0, max(0.0, sp))
+    t = (float(a @ (S + sp * d - C))) / A
+    return float(np.linalg.norm(C + t * a - (S + sp * d)))
+
+
+def random_tilted(n, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        ax = np.array([1.0, rng.uniform(-0.4, 0.4), rng.uniform(-0.5, 0.5)])
+        ax /= np.linalg.norm(ax)
+        P = np.array([rng.uniform(-2e4, 2e4), rng.uniform(3e5, 6e5), rng.uniform(-2e5, 2e5)])
+        C = np.array([rng.uniform(-500, 500), rng.uniform(100, 1500), rng.uniform(-300, 300)])
+        r = rng.uniform(5.0, 60.0)
+        out.append((ax, P, C, r))
+    return out
+
+
+def _oracle_positions(ax, P, centers, r, edge, lib):
+    """u_k of one pixel at P (grid e0 = 0, width 1: u = depth)."""
+    det = synth.Detector(1, 1, np.zeros(3), np.array([1.0, 0, 0]), np.array([0, 0, 1.0]),
+                         pixel_xyz=P.reshape(1, 1, 3))
+    wire = synth.Wire(radius=r, centers=np.asarray(centers, dtype=np.float64), axis=ax, edge=edge)
+    scan = synth.Scan("p", det, wire, synth.DepthGrid(4, 0.5, 1.0), None, 0.0, False, 0)
+    _, _, u = oracle.reconstruct_pixels(scan, [0], want_bins=False, want_u=True, lib=lib)
+    return u[0]
+
+
+def pin_tilted_axis_bisection(lib):
+    """A wire axis tilted out of x: the depth of each edge equals the beam point
+    where the 3D distance between the axis line and the source-pixel segment
+    reaches r, found by bisection (leading: downstream side for a wire moving
+    downstream; trailing: upstream side)."""
+    for ax, P, C, r in random_tilted(60, 16):
+        step = np.array([0.0, 0.7, 0.7])
+        centers = np.stack([C, C + step])
+        dist = lambda z: line_segment_dist3(C, ax, np.array([0.0, 0.0, z]), P)
+        # beam point whose ray meets the axis: minimise the distance
+        lo, hi = -1e5, 1e5
+        for _ in range(300):
+            m1, m2 = lo + (hi - lo) / 3, hi - (hi - lo) / 3
+            if dist(m1) < dist(m2):
+                hi = m2
+            else:
+                lo = m1
+        zc = 0.5 * (lo + hi)
+        assert dist(zc) < r
+        for edge, sgn in ((0, +1.0), (1, -1.0)):
+            a_, b_ = zc, zc + sgn * 1e5
+            for _ in range(200):
+                m = 0.5 * (a_ + b_)
+                if dist(m) < r:
+                    a_ = m
+                else:
+                    b_ = m
+            u = _oracle_positions(ax, P, centers, r, edge, lib)
+            assert abs(u[0] - 0.5 * (a_ + b_)) < 1e-6 * (1 + abs(u[0])), (edge, u[0], a_, ax)
+
+
+def pin_tilted_axis_brute_force(lib):
+    """Tilted axis: whole-profile check against brute-force sub-sampling of the
+    beam with the 3D occlusion predicate, arbitrary intensities."""
+    rng = np.random.default_rng(17)
+    for ax, P, C, r in random_tilted(4, 18):
+        N = 7
+        step = np.array([0.0, 0.8, 0.8])
+        centers = np.stack([C + (k - N // 2) * step for k in range(N)])
+        # grid around the leading sweep
+        u0 = _oracle_positions(ax, P, centers, r, 0, lib)
+        width = 0.5
+        B = 40
+        first = np.floor(u0.min()) - 8.0
+        det = synth.Detector(1, 1, np.zeros(3), np.array([1.0, 0, 0]), np.array([0, 0, 1.0]),
+                             pixel_xyz=P.reshape(1, 1, 3))
+        I = rng.integers(0, 60000, N).astype(np.uint16)
+        for edge in (0, 1, 2):
+            wire = synth.Wire(radius=r, centers=centers, axis=ax, edge=edge)
+            grid = synth.DepthGrid(B, first + 0.5 * width, width)
+            scan = synth.Scan("bf", det, wire, grid, None, 0.0, False, 0,
+                              images=I.reshape(N, 1, 1))
+            out, _, _ = oracle.reconstruct(scan, lib=lib)
+            e0 = first
+            h = width / 2500.0
+            z = e0 - 40.0 * width + h * (np.arange(int((B + 80) * width / h)) + 0.5)
+            # vectorised 3D distance: closest points between the axis line and each segment
+            dvec = P[None, :] - np.stack([np.zeros_like(z), np.zeros_like(z), z], 1)
+            prof = {0: np.zeros(B), 1: np.zeros(B)}
+            err = {0: np.zeros(B), 1: np.zeros(B)}
+            occ = []
+            for c in centers:
+                S = np.stack([np.zeros_like(z), np.zeros_like(z), z], 1)
+                w = S - c[None, :]
+                A = 1.0
+                Bq = dvec @ ax
+                Cq = np.einsum("ij,ij->i", dvec, dvec)
+                D = w @ ax
+                E = np.einsum("ij,ij->i", dvec, w)
+                sp = np.clip((Bq * D - A * E) / (A * Cq - Bq * Bq), 0.0, 1.0)
+                Q = S + sp[:, None] * dvec
+                t = (Q - c[None, :]) @ ax
+                occ.append(np.linalg.norm(c[None, :] + t[:, None] * ax[None, :] - Q, axis=1) < r)
+            occ = np.stack(occ)
+            binidx = np.floor((z - e0) / width).astype(np.int64)
+            inside = (binidx >= 0) & (binidx < B)
+            for side in (0, 1):
+                for k in range(N - 1):
+                    newly = (occ[k + 1] & ~occ[k]) if side == 0 else (occ[k] & ~occ[k + 1])
+                    dI = (float(I[k]) - float(I[k + 1])) * (1 if side == 0 else -1)
+                    n = int(newly.sum())
+                    if n == 0:
+                        continue
+                    cnt = np.bincount(binidx[newly & inside], minlength=B)
+                    prof[side] += dI * cnt / n
+                    err[side][cnt > 0] += abs(dI) * 4.0 / n
+            want = prof[0] if edge == 0 else (prof[1] if edge == 1 else 0.5 * (prof[0] + prof[1]))
+            tol = err[0] if edge == 0 else (err[1] if edge == 1 else 0.5 * (err[0] + err[1]))
+            assert np.all(np.abs(out[:, 0, 0] - want) <= tol + 1e-6), (edge, ax)
+
+
 ALL_PINS = [
     pin_closed_form_level, pin_zero_radius, pin_bisection, pin_mirror, pin_edge_sign,
     pin_hand_profiles, pin_conservation_random, pin_conservation_scan, pin_brute_force,
-    pin_planted_sources, pin_poisson_recovery,
+    pin_planted_sources, pin_poisson_recovery, pin_tilted_axis_bisection,
+    pin_tilted_axis_brute_force,
 ]

@@ -41,8 +41,14 @@ MUTANTS = [
      "out[(int64_t)bd * stride] += dI * ov;"),
     ("ceil_first", "double first = floor(lo), last = floor(hi);",
      "double first = ceil(lo), last = floor(hi);"),
-    ("pixel_transposed", "*pz = (origin[2] + i * u[2]) + j * v[2];",
-     "*pz = (origin[2] + j * u[2]) + i * v[2];"),
+    ("pixel_transposed", "for (int q = 0; q < 3; ++q) X[q] = (origin[q] + i * u[q]) + j * v[q];",
+     "for (int q = 0; q < 3; ++q) X[q] = (origin[q] + j * u[q]) + i * v[q];"),
+    ("frame_e2_sign", "f->e2[1] = f->e1[2] * a[0] - f->e1[0] * a[2];",
+     "f->e2[1] = f->e1[0] * a[2] - f->e1[2] * a[0];"),
+    ("depth_not_scaled", "double d = oracle_tangent_depth(py, pz, wyz[2 * k], wyz[2 * k + 1], r, s) / c;",
+     "double d = oracle_tangent_depth(py, pz, wyz[2 * k], wyz[2 * k + 1], r, s);"),
+    ("projection_drops_z", "*xi = (X[0] * f->e1[0] + X[1] * f->e1[1]) + X[2] * f->e1[2];",
+     "*xi = (X[0] * f->e1[0] + X[1] * f->e1[1]);"),
     ("step_reversed", "Ik[k] = (double)images[(int64_t)k * plane_in + p];",
      "Ik[k] = (double)images[(int64_t)(n_steps - 1 - k) * plane_in + p];"),
     ("point_mass_sign", "if (bd >= 0.0 && bd < (double)n_bins) out[(int64_t)bd * stride] += dI;",
@@ -54,7 +60,7 @@ MUTANTS = [
 
 def _ordered_pins():
     pins = list(oracle_pins.ALL_PINS)
-    slow = [oracle_pins.pin_brute_force]
+    slow = [oracle_pins.pin_brute_force, oracle_pins.pin_tilted_axis_brute_force]
     return [p for p in pins if p not in slow] + slow
 
 
