@@ -45,7 +45,7 @@ def load(path: Optional[str] = None):
         lib.oracle_tangent_depth.restype = d
         lib.oracle_edge_sign.argtypes = [d, d, i32, p, d]
         lib.oracle_edge_sign.restype = i32
-        lib.oracle_bin_profile.argtypes = [p, p, i32, i32, i32, p, i64]
+        lib.oracle_bin_profile.argtypes = [p, p, i32, i32, i32, d, p, i64]
         lib.oracle_bin_profile.restype = None
         lib.oracle_reconstruct.argtypes = [i32, i32, p, p, p, p, d, p, i32, p, i32, d, d, i32,
                                            p, i32, i32, p, p, p, i32]
@@ -85,15 +85,16 @@ def edge_sign(py, pz, centers, r, lib=None) -> int:
 EDGE_LEADING, EDGE_TRAILING, EDGE_BOTH = 0, 1, 2
 
 
-def bin_profile(u, intensities, n_bins: int, trailing: bool = False, lib=None) -> np.ndarray:
+def bin_profile(u, intensities, n_bins: int, trailing: bool = False, weight: float = 1.0,
+                lib=None) -> np.ndarray:
     """Binning of one pixel given its positions u_k (bin units) and counts;
-    trailing=True takes dI_k = I_{k+1} - I_k."""
+    trailing=True takes dI_k = I_{k+1} - I_k; weight scales the fractions."""
     u = _f64(u)
     I = _f64(intensities)
     assert u.shape == I.shape and u.ndim == 1
     out = np.zeros(n_bins, dtype=np.float64)
     (lib or load()).oracle_bin_profile(_p(u), _p(I), u.shape[0], int(n_bins), 1 if trailing else 0,
-                                       _p(out), 1)
+                                       float(weight), _p(out), 1)
     return out
 
 

@@ -35,11 +35,14 @@
  *              side s_p and dI_k = I_k - I_{k+1} (intensity lost as the edge
  *              covers the slice); the trailing edge uses side -s_p and
  *              dI_k = I_{k+1} - I_k (intensity regained as it uncovers it);
- *              "both" is the average of the two reconstructions.
+ *              "both" is the average of the two reconstructions, accumulated
+ *              as the leading contributions at weight 1/2 followed by the
+ *              trailing contributions at weight 1/2, each bin in step order.
  *   binning    u_k = (d_k - e0) * (1/width), e0 = first_center - width/2.
- *              For k = 0..N-2 the difference dI_k = I_k - I_{k+1} is spread
- *              over [lo, hi] = [min, max](u_k, u_{k+1}): bin b gets
- *              dI_k * ov/len with ov = min(hi, b+1) - max(lo, b) > 0 and
+ *              For k = 0..N-2 the difference dI_k is spread over
+ *              [lo, hi] = [min, max](u_k, u_{k+1}): bin b gets
+ *              dI_k * (w * (ov/len)) (edge weight w) with
+ *              ov = min(hi, b+1) - max(lo, b) > 0 and
  *              len = hi - lo; parts outside [0, n_bins) are dropped; a
  *              zero-length interval puts dI_k into bin floor(lo).
  *   totals     tot[b] = sum over pixels of out[b][p].
@@ -180,10 +183,11 @@ static int pixel_positions(double py, double pz, int n_steps, const double* wyz,
  *   u        [n_steps] edge positions in bin units
  *   I        [n_steps] intensities (counts), read as doubles
  *   trailing 0: dI_k = I_k - I_{k+1}; 1: dI_k = I_{k+1} - I_k
+ *   w        weight of this edge (1, or 1/2 for each edge of "both")
  *   out      [n_bins] accumulated in place (caller zeroes it)
  *   stride   distance between consecutive bins of out */
 void oracle_bin_profile(const double* u, const double* I, int n_steps, int n_bins, int trailing,
-                        double* out, int64_t stride)
+                        double w, double* out, int64_t stride)
 {
     for (int k = 0; k + 1 < n_steps; ++k) {
         double dI = trailing ? I[k + 1] - I[k] : I[k] - I[k + 1];
@@ -198,39 +202,37 @@ void oracle_bin_profile(const double* u, const double* I, int n_steps, int n_bin
                 double top = hi < bd + 1.0 ? hi : bd + 1.0;
                 double bot = lo > bd ? lo : bd;
                 double ov = top - bot;
-                if (ov > 0.0) out[(int64_t)bd * stride] += dI * (ov / len);
+                if (ov > 0.0) out[(int64_t)bd * stride] += dI * (w * (ov / len));
             }
         } else {
             double bd = floor(lo);
-            if (bd >= 0.0 && bd < (double)n_bins) out[(int64_t)bd * stride] += dI;
+            if (bd >= 0.0 && bd < (double)n_bins) out[(int64_t)bd * stride] += dI * w;
         }
     }
 }
 
 /* Profile of one pixel for edge LEADING, TRAILING or BOTH into o (stride
- * between bins; the caller zeroes it).  uk [n_steps] and tmp [n_bins] are
- * scratch; the positions of the reported edge (trailing for TRAILING, else
- * leading) are left in uk. */
+ * between bins; the caller zeroes it).  uk [n_steps] is scratch; the
+ * positions of the reported edge (trailing for TRAILING, else leading) are
+ * left in uk. */
 static int pixel_profile(double py, double pz, const double* Ik, int n_steps,
                          const double* wyz, double r, double c, double e0, double invw,
-                         int n_bins, int edge, double* o, int64_t stride, double* uk,
-                         double* tmp)
+                         int n_bins, int edge, double* o, int64_t stride, double* uk)
 {
     if (edge == EDGE_BOTH) {
-        if (pixel_positions(py, pz, n_steps, wyz, r, c, e0, invw, 1, uk) != ORACLE_OK)
-            return ORACLE_EINVAL;
-        for (int b = 0; b < n_bins; ++b) tmp[b] = 0.0;
-        oracle_bin_profile(uk, Ik, n_steps, n_bins, 1, tmp, 1);
         if (pixel_positions(py, pz, n_steps, wyz, r, c, e0, invw, 0, uk) != ORACLE_OK)
             return ORACLE_EINVAL;
-        oracle_bin_profile(uk, Ik, n_steps, n_bins, 0, o, stride);
-        for (int b = 0; b < n_bins; ++b) o[(int64_t)b * stride] = 0.5 * (o[(int64_t)b * stride] + tmp[b]);
-        return ORACLE_OK;
+        oracle_bin_profile(uk, Ik, n_steps, n_bins, 0, 0.5, o, stride);
+        if (pixel_positions(py, pz, n_steps, wyz, r, c, e0, invw, 1, uk) != ORACLE_OK)
+            return ORACLE_EINVAL;
+        oracle_bin_profile(uk, Ik, n_steps, n_bins, 1, 0.5, o, stride);
+        /* report the leading positions */
+        return pixel_positions(py, pz, n_steps, wyz, r, c, e0, invw, 0, uk);
     }
     const int trailing = edge == EDGE_TRAILING;
     if (pixel_positions(py, pz, n_steps, wyz, r, c, e0, invw, trailing, uk) != ORACLE_OK)
         return ORACLE_EINVAL;
-    oracle_bin_profile(uk, Ik, n_steps, n_bins, trailing, o, stride);
+    oracle_bin_profile(uk, Ik, n_steps, n_bins, trailing, 1.0, o, stride);
     return ORACLE_OK;
 }
 
@@ -273,7 +275,6 @@ int oracle_reconstruct(int nx, int ny, const double* origin, const double* u, co
     {
         double* uk = (double*)malloc(sizeof(double) * (size_t)n_steps);
         double* Ik = (double*)malloc(sizeof(double) * (size_t)n_steps);
-        double* tmp = (double*)malloc(sizeof(double) * (size_t)n_bins);
 #pragma omp for schedule(dynamic, 1)
         for (int jr = 0; jr < nrows; ++jr) {
             for (int i = 0; i < nx; ++i) {
@@ -283,7 +284,7 @@ int oracle_reconstruct(int nx, int ny, const double* origin, const double* u, co
                 pixel_center(&fr, nx, origin, u, v, pixel_xyz, p, &py, &pz);
                 for (int k = 0; k < n_steps; ++k) Ik[k] = (double)images[(int64_t)k * plane_in + p];
                 if (pixel_profile(py, pz, Ik, n_steps, wyz, radius, fr.c, e0, invw, n_bins, edge,
-                                  out + q, plane_out, uk, tmp) != ORACLE_OK) {
+                                  out + q, plane_out, uk) != ORACLE_OK) {
 #pragma omp atomic write
                     status = ORACLE_EINVAL;
                     continue;
@@ -294,7 +295,6 @@ int oracle_reconstruct(int nx, int ny, const double* origin, const double* u, co
         }
         free(uk);
         free(Ik);
-        free(tmp);
     }
     free(wyz);
     if (status != ORACLE_OK) return status;
@@ -344,7 +344,6 @@ int oracle_reconstruct_pixels(int nx, int ny, const double* origin, const double
     {
         double* uk = (double*)malloc(sizeof(double) * (size_t)n_steps);
         double* Ik = (double*)malloc(sizeof(double) * (size_t)n_steps);
-        double* tmp = (double*)malloc(sizeof(double) * (size_t)n_bins);
 #pragma omp for schedule(dynamic, 16)
         for (int64_t n = 0; n < npix; ++n) {
             int64_t p = pixels[n];
@@ -361,7 +360,7 @@ int oracle_reconstruct_pixels(int nx, int ny, const double* origin, const double
                 Ik[k] = series ? (double)series[n * n_steps + k]
                                : (images ? (double)images[(int64_t)k * plane_in + p] : 0.0);
             if (pixel_profile(py, pz, Ik, n_steps, wyz, radius, fr.c, e0, invw, n_bins, edge, o,
-                              1, uk, tmp) != ORACLE_OK) {
+                              1, uk) != ORACLE_OK) {
 #pragma omp atomic write
                 status = ORACLE_EINVAL;
                 continue;
@@ -375,7 +374,6 @@ int oracle_reconstruct_pixels(int nx, int ny, const double* origin, const double
         }
         free(uk);
         free(Ik);
-        free(tmp);
     }
     free(wyz);
     return status;

@@ -49,7 +49,8 @@ def _load():
         lib = ctypes.CDLL(LIB_PATH)
         d, i32, i64, u64, p = (ctypes.c_double, ctypes.c_int32, ctypes.c_int64,
                                ctypes.c_uint64, ctypes.c_void_p)
-        lib.synth_render.argtypes = [i32, i32, p, p, i32, p, p, d, p, p, p, d, i32, u64, p, i32]
+        lib.synth_render.argtypes = [i32, i32, p, p, p, i32, p, p, p, p, d, p, p, p, d, i32, u64,
+                                     p, i32]
         lib.synth_render.restype = ctypes.c_int
         lib.synth_uniforms.argtypes = [u64, u64, u64, i64, p]
         lib.synth_uniforms.restype = None
@@ -76,17 +77,20 @@ class Detector:
     v: np.ndarray
     pixel_xyz: Optional[np.ndarray] = None  # optional [ny][nx][3] override
 
-    def pixel_yz(self):
-        """Pixel-centre (y, z) arrays [ny][nx] for the forward model."""
+    def pixel_xyz_arrays(self):
+        """Pixel-centre (x, y, z) arrays [ny][nx] for the forward model."""
         if self.pixel_xyz is not None:
-            return (np.ascontiguousarray(self.pixel_xyz[..., 1]),
-                    np.ascontiguousarray(self.pixel_xyz[..., 2]))
+            return tuple(np.ascontiguousarray(self.pixel_xyz[..., q]) for q in range(3))
         i = np.arange(self.nx, dtype=np.float64)[None, :]
         j = np.arange(self.ny, dtype=np.float64)[:, None]
-        y = (self.origin[1] + i * self.u[1]) + j * self.v[1]
-        z = (self.origin[2] + i * self.u[2]) + j * self.v[2]
-        return (np.ascontiguousarray(np.broadcast_to(y, (self.ny, self.nx))),
-                np.ascontiguousarray(np.broadcast_to(z, (self.ny, self.nx))))
+        return tuple(np.ascontiguousarray(np.broadcast_to(
+            (self.origin[q] + i * self.u[q]) + j * self.v[q], (self.ny, self.nx)))
+            for q in range(3))
+
+    def pixel_yz(self):
+        """Pixel-centre (y, z) arrays [ny][nx]."""
+        _, y, z = self.pixel_xyz_arrays()
+        return y, z
 
 
 EDGE_LEADING, EDGE_TRAILING, EDGE_BOTH = 0, 1, 2
@@ -227,18 +231,21 @@ def contributions(src: Sources, nx: int, ny: int):
 def render(scan: Scan, out: Optional[np.ndarray] = None, nthreads: int = 0) -> np.ndarray:
     """Fill scan.images (uint16 [N][ny][nx]) with the forward model."""
     det, wire = scan.detector, scan.wire
-    py, pz = det.pixel_yz()
+    px, py, pz = det.pixel_xyz_arrays()
     ptr, gain, zs = contributions(scan.sources, det.nx, det.ny)
     N = wire.n_steps
     if out is None:
         out = np.empty((N, det.ny, det.nx), dtype=np.uint16)
     assert out.dtype == np.uint16 and out.shape == (N, det.ny, det.nx) and out.flags.c_contiguous
+    cx = np.ascontiguousarray(wire.centers[:, 0])
     cy = np.ascontiguousarray(wire.centers[:, 1])
     cz = np.ascontiguousarray(wire.centers[:, 2])
+    axis = np.asarray(wire.axis, dtype=np.float64)
+    axis = np.ascontiguousarray(axis / np.linalg.norm(axis))
     if nthreads <= 0:
         nthreads = min(16, os.cpu_count() or 1)
-    _load().synth_render(det.nx, det.ny, _ptr(py), _ptr(pz), N, _ptr(cy), _ptr(cz),
-                         float(wire.radius), _ptr(ptr), _ptr(gain), _ptr(zs),
+    _load().synth_render(det.nx, det.ny, _ptr(px), _ptr(py), _ptr(pz), N, _ptr(cx), _ptr(cy),
+                         _ptr(cz), _ptr(axis), float(wire.radius), _ptr(ptr), _ptr(gain), _ptr(zs),
                          float(scan.dark), 1 if scan.noise else 0,
                          int(scan.seed) & 0xFFFFFFFFFFFFFFFF, _ptr(out), int(nthreads))
     scan.images = out
@@ -333,7 +340,8 @@ def config4(seed: int = 4, render_now: bool = True, n_scans: int = 16,
 def tiny(nx: int, ny: int, n_steps: int, n_bins: int, seed: int = 7, pitch: float = 200.0,
          step: float = 1.0, width: float = 1.0, n_src: int = 4, dark: float = 0.0,
          noise: bool = True, sigma: float = 1.5, zlo: Optional[float] = None,
-         zhi: Optional[float] = None, integer_amp: bool = False) -> Scan:
+         zhi: Optional[float] = None, integer_amp: bool = False,
+         render_now: bool = True) -> Scan:
     """Small seeded scan for parity and edge-case tests (ragged sizes allowed)."""
     rng = np.random.default_rng(np.random.SeedSequence(seed))
     det = flat_detector(nx, ny, pitch)
@@ -344,7 +352,8 @@ def tiny(nx: int, ny: int, n_steps: int, n_bins: int, seed: int = 7, pitch: floa
     hi = sweep if zhi is None else zhi
     src = draw_sources(rng, n_src, nx, ny, lo, hi, sigma=sigma, integer_amp=integer_amp)
     s = Scan(f"tiny{nx}x{ny}x{n_steps}", det, wire, grid, src, dark=dark, noise=noise, seed=seed)
-    render(s)
+    if render_now:
+        render(s)
     return s
 
 

@@ -7,11 +7,12 @@
  * fraction.  What it models is the physics the reconstruction inverts
  * (wire-scan depth resolution, Sec. I): point sources on the incident beam
  * send rays to detector pixels; a ray is blocked at wire step k when the wire
- * cross-section (a disc of radius r in the plane normal to the wire axis,
- * which is the lab x axis) overlaps it; every pixel records Poisson counts.
+ * (a cylinder of radius r around an axis line) comes closer than r to it;
+ * every pixel records Poisson counts.
  *
- * Frame: micrometres, beam along +z through x = y = 0, depth = z.  Only the
- * (y, z) projection matters because the wire axis is x.
+ * Frame: micrometres, beam along +z through x = y = 0, depth = z.  For a wire
+ * along the lab x axis only the (y, z) projection matters; other axes use the
+ * 3D distance between the axis line and the ray segment.
  *
  * Random numbers come from Philox4x32-10 (Salmon, Moraes, Dror and Shaw,
  * "Parallel random numbers: as easy as 1, 2, 3", SC 2011), used as a pure
@@ -193,12 +194,41 @@ int synth_occluded(double zs, double py, double pz, double cy, double cz, double
     return occluded(zs, py, pz, cy, cz, r * r);
 }
 
+/* General wire axis: true when the 3D distance between the axis line
+ * C + t*a (a unit) and the segment from the source (0, 0, zs) to the pixel P
+ * is strictly below r (closest points of the two lines, segment parameter
+ * clamped to [0, 1]). */
+static inline int occluded3(double zs, const double* P, const double* C, const double* a,
+                            double rr)
+{
+    const double d[3] = {P[0], P[1], P[2] - zs};
+    const double w[3] = {-C[0], -C[1], zs - C[2]};
+    const double B = a[0] * d[0] + a[1] * d[1] + a[2] * d[2];
+    const double Cq = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    const double D = a[0] * w[0] + a[1] * w[1] + a[2] * w[2];
+    const double E = d[0] * w[0] + d[1] * w[1] + d[2] * w[2];
+    const double den = Cq - B * B;
+    double s = den > 0.0 ? (B * D - E) / den : 0.0;
+    if (s < 0.0) s = 0.0;
+    if (s > 1.0) s = 1.0;
+    double q[3], t = 0.0;
+    for (int i = 0; i < 3; ++i) q[i] = (i == 2 ? zs : 0.0) + s * d[i];
+    for (int i = 0; i < 3; ++i) t += (q[i] - C[i]) * a[i];
+    double dist2 = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        const double e = C[i] + t * a[i] - q[i];
+        dist2 += e * e;
+    }
+    return dist2 < rr;
+}
+
 /* -------------------------------------------------------------- renderer */
 
 /*
  * Render images[k][j][i] (uint16, step slowest) for an ny x nx detector.
- *   py, pz        [ny*nx] pixel-centre y and z in um
- *   cy, cz        [n_steps] wire-centre y and z in um; radius r
+ *   px, py, pz    [ny*nx] pixel-centre x, y and z in um
+ *   cx, cy, cz    [n_steps] wire-centre x, y and z in um; radius r
+ *   axis          unit wire axis; (1,0,0) uses the (y, z) projection
  *   cptr          [ny*nx + 1] CSR offsets into the contribution arrays
  *   cgain, czs    per contribution: expected counts when the ray is clear,
  *                 and the depth of the source it comes from
@@ -207,13 +237,14 @@ int synth_occluded(double zs, double py, double pz, double cy, double cz, double
  *   seed          Philox key for the noise
  * Counts are clipped to [0, 65535].  Returns 0.
  */
-int synth_render(int32_t nx, int32_t ny, const double* py, const double* pz,
-                 int32_t n_steps, const double* cy, const double* cz, double r,
-                 const int64_t* cptr, const double* cgain, const double* czs,
-                 double dark, int32_t noise, uint64_t seed, uint16_t* images,
+int synth_render(int32_t nx, int32_t ny, const double* px, const double* py, const double* pz,
+                 int32_t n_steps, const double* cx, const double* cy, const double* cz,
+                 const double* axis, double r, const int64_t* cptr, const double* cgain,
+                 const double* czs, double dark, int32_t noise, uint64_t seed, uint16_t* images,
                  int32_t nthreads)
 {
     const double rr = r * r;
+    const int xaxis = axis[0] == 1.0 && axis[1] == 0.0 && axis[2] == 0.0;
     const int64_t plane = (int64_t)nx * (int64_t)ny;
     double* cdf = NULL;
     int ncdf = noise ? build_cdf(dark, &cdf) : 0;
@@ -231,7 +262,15 @@ int synth_render(int32_t nx, int32_t ny, const double* py, const double* pz,
                 const int64_t p = (int64_t)j * nx + i;
                 double lam = dark;
                 for (int64_t c = cptr[p]; c < cptr[p + 1]; ++c) {
-                    if (!occluded(czs[c], py[p], pz[p], cy[k], cz[k], rr)) lam += cgain[c];
+                    int occ;
+                    if (xaxis) {
+                        occ = occluded(czs[c], py[p], pz[p], cy[k], cz[k], rr);
+                    } else {
+                        const double P[3] = {px[p], py[p], pz[p]};
+                        const double C[3] = {cx[k], cy[k], cz[k]};
+                        occ = occluded3(czs[c], P, C, axis, rr);
+                    }
+                    if (!occ) lam += cgain[c];
                 }
                 int64_t n;
                 if (!noise) {

@@ -31,14 +31,16 @@ MUTANTS = [
     ("trailing_dI_sign", "double dI = trailing ? I[k + 1] - I[k] : I[k] - I[k + 1];",
      "double dI = trailing ? I[k] - I[k + 1] : I[k] - I[k + 1];"),
     ("trailing_side", "if (trailing) s = -s;", "if (trailing) s = s;"),
-    ("both_not_averaged", "o[(int64_t)b * stride] = 0.5 * (o[(int64_t)b * stride] + tmp[b]);",
-     "o[(int64_t)b * stride] = (o[(int64_t)b * stride] + tmp[b]);"),
-    ("both_drops_trailing", "o[(int64_t)b * stride] = 0.5 * (o[(int64_t)b * stride] + tmp[b]);",
-     "o[(int64_t)b * stride] = 0.5 * (o[(int64_t)b * stride] + o[(int64_t)b * stride]);"),
+    ("both_not_averaged", "oracle_bin_profile(uk, Ik, n_steps, n_bins, 1, 0.5, o, stride);",
+     "oracle_bin_profile(uk, Ik, n_steps, n_bins, 1, 1.0, o, stride);"),
+    ("both_drops_trailing", "oracle_bin_profile(uk, Ik, n_steps, n_bins, 1, 0.5, o, stride);",
+     "oracle_bin_profile(uk, Ik, n_steps, n_bins, 0, 0.5, o, stride);"),
+    ("weight_ignored", "out[(int64_t)bd * stride] += dI * (w * (ov / len));",
+     "out[(int64_t)bd * stride] += dI * (ov / len);"),
     ("top_swap", "double top = hi < bd + 1.0 ? hi : bd + 1.0;",
      "double top = hi < bd + 1.0 ? bd + 1.0 : hi;"),
-    ("no_normalise", "out[(int64_t)bd * stride] += dI * (ov / len);",
-     "out[(int64_t)bd * stride] += dI * ov;"),
+    ("no_normalise", "out[(int64_t)bd * stride] += dI * (w * (ov / len));",
+     "out[(int64_t)bd * stride] += dI * (w * ov);"),
     ("ceil_first", "double first = floor(lo), last = floor(hi);",
      "double first = ceil(lo), last = floor(hi);"),
     ("pixel_transposed", "for (int q = 0; q < 3; ++q) X[q] = (origin[q] + i * u[q]) + j * v[q];",
@@ -51,8 +53,8 @@ MUTANTS = [
      "*xi = (X[0] * f->e1[0] + X[1] * f->e1[1]);"),
     ("step_reversed", "Ik[k] = (double)images[(int64_t)k * plane_in + p];",
      "Ik[k] = (double)images[(int64_t)(n_steps - 1 - k) * plane_in + p];"),
-    ("point_mass_sign", "if (bd >= 0.0 && bd < (double)n_bins) out[(int64_t)bd * stride] += dI;",
-     "if (bd >= 0.0 && bd < (double)n_bins) out[(int64_t)bd * stride] -= dI;"),
+    ("point_mass_sign", "if (bd >= 0.0 && bd < (double)n_bins) out[(int64_t)bd * stride] += dI * w;",
+     "if (bd >= 0.0 && bd < (double)n_bins) out[(int64_t)bd * stride] -= dI * w;"),
     ("lo_hi_swap", "double lo = u[k] < u[k + 1] ? u[k] : u[k + 1];",
      "double lo = u[k];"),
 ]
