@@ -12,7 +12,12 @@
  *
  *   - lengths in micrometres; the beam is the line x = y = 0 travelling +z;
  *     depth is the z coordinate of a point on the beam;
- *   - the wire is a cylinder of radius `radius` whose axis is the lab x axis;
+ *   - the wire is a cylinder of radius `radius` around an axis line of any
+ *     direction not along the beam; positions are projected onto the plane
+ *     normal to the axis, with coordinates (eta, xi): xi along the beam's
+ *     projection, eta = xi x axis (for the lab x axis, (eta, xi) = (y, z)),
+ *     and the tangent construction runs in that plane; the depth is the
+ *     projected beam coordinate divided by the cosine between beam and plane;
  *   - pixel (row j, column i) has centre (origin + i*u) + j*v unless an
  *     explicit per-pixel table is given;
  *   - bin b of the depth grid is centred at first_center + b*width and covers
@@ -67,7 +72,9 @@ typedef int32_t dr_status;
  * covers a depth slice).  Trailing: the opposite side, I_{k+1} - I_k
  * (intensity regained as it uncovers the slice).  Both: the average of the
  * two reconstructions (a true source keeps its amplitude, the mirrored
- * negative ghosts of the two edges are halved). */
+ * negative ghosts of the two edges are halved): half of every leading-edge
+ * contribution is added first, then half of every trailing-edge one, each
+ * bin in step order. */
 #define DR_EDGE_LEADING 0
 #define DR_EDGE_TRAILING 1
 #define DR_EDGE_BOTH 2
@@ -76,18 +83,23 @@ typedef struct dr_ctx_s* dr_ctx;     /* one GPU: streams, slab buffers, schedule
 typedef struct dr_geom_s* dr_geom;   /* device-resident tables of one geometry */
 typedef struct dr_batch_s* dr_batch; /* a captured, tuned launch over many scans */
 
-/* Detector: pixel (j, i) centre = (origin + i*u) + j*v (um).  pixel_xyz, when
- * not NULL, is a host array [ny][nx][3] of explicit centres that overrides the
- * affine map.  Only the y and z coordinates enter the reconstruction. */
+/* Detector: pixel (j, i) centre = (origin + i*u) + j*v (um), any orientation.
+ * pixel_xyz, when not NULL, is a host array [ny][nx][3] of explicit centres
+ * that overrides the affine map.  When every pixel of each row projects to
+ * the row's first (eta, xi) bit for bit (a detector whose rows run along the
+ * wire axis), rows share one set of FP64 bin positions built once; otherwise
+ * each pixel computes its own positions on the fly (the per-pixel path: same
+ * results, ALU-bound instead of HBM-bound). */
 typedef struct {
     int32_t nx, ny;
     double origin[3], u[3], v[3];
     const double* pixel_xyz;
 } dr_detector;
 
-/* Wire: a cylinder of `radius` um with axis `axis` (must be (1,0,0));
- * centers is a host array [n_steps][3] of the axis position at each step (the
- * x coordinate is ignored).  edge: DR_EDGE_LEADING, _TRAILING or _BOTH. */
+/* Wire: a cylinder of `radius` um around the direction `axis` (any length > 0,
+ * not along the beam; normalised inside); centers is a host array
+ * [n_steps][3] of a point of the axis line at each step (only its projection
+ * matters).  edge: DR_EDGE_LEADING, _TRAILING or _BOTH. */
 typedef struct {
     double radius;
     double axis[3];
@@ -132,13 +144,20 @@ dr_status dr_ctx_destroy(dr_ctx ctx);
  * and check it on the device.  Copies every input, so the caller may free its
  * arrays on return; the library owns *out until dr_geometry_free.
  * Errors: DR_E_INVAL for NULL pointers, nx/ny/n_bins < 1, n_steps < 2,
- * radius <= 0, width <= 0, an unknown edge, an axis other than (1,0,0)
- * (DR_E_UNSUPPORTED), a pixel inside the wire,
- * a wire position not strictly between beam and detector in y, or any
+ * radius <= 0, width <= 0, an unknown edge, a zero or non-finite axis or one
+ * along the beam, a pixel inside the wire, a wire position not strictly
+ * between beam and pixel in eta (0 < eta_wire < eta_pixel), or any
  * non-finite depth; DR_E_NOMEM / DR_E_DEVICE for allocation or HIP failures.
  * Synchronous. */
 dr_status dr_geometry_init(dr_ctx ctx, const dr_detector* det, const dr_wire* wire,
                            const dr_depth_grid* grid, dr_geom* out);
+
+/* Which path a geometry takes: DR_PATH_ROWS (per-row FP64 bin tables built
+ * once, HBM-bound kernel) or DR_PATH_PIXELS (positions computed per pixel on
+ * the fly).  Errors: DR_E_INVAL for NULL arguments. */
+#define DR_PATH_ROWS 0
+#define DR_PATH_PIXELS 1
+dr_status dr_geometry_path(dr_geom geom, int32_t* path);
 
 /* Free a geometry.  Waits for the device work already enqueued on it.
  * DR_E_BUSY while serving requests that use it are in flight. */
@@ -147,14 +166,16 @@ dr_status dr_geometry_free(dr_geom geom);
 /* Force a launch shape for this geometry (tile-invariance tests, manual
  * tuning); NULL restores the automatic choice.  DR_E_INVAL for values outside
  * the sets listed at dr_tile_config or a shape that does not fit nx or the
- * buffer alignment at launch time. */
+ * buffer alignment at launch time; DR_E_UNSUPPORTED for a geometry on the
+ * per-pixel path, which has a single launch shape. */
 dr_status dr_set_tile(dr_geom geom, const dr_tile_config* tile);
 
 /* Time the available launch shapes on this geometry with the caller's device
  * buffers and keep the fastest for later calls (autotuner; results are cached
  * per device architecture and size class, and in the JSON file named by the
  * environment variable DR_TUNE_CACHE when set).  `out` is overwritten.
- * Synchronous.  *chosen (if not NULL) receives the winner. */
+ * Synchronous.  *chosen (if not NULL) receives the winner.  On the per-pixel
+ * path nothing is timed and *chosen receives its one shape (1, 4, 8, 0). */
 dr_status dr_autotune(dr_geom geom, const uint16_t* images_dev, float* out_dev,
                       dr_tile_config* chosen);
 
@@ -218,7 +239,8 @@ typedef struct {
  * allocated while the batch exists; their contents may change between runs.
  * With DR_BATCH_AUTOTUNE the outputs are overwritten while tuning.
  * Errors: DR_E_INVAL (n < 1, NULL items, geometries of another context),
- * DR_E_NOMEM, DR_E_DEVICE. */
+ * DR_E_UNSUPPORTED (a geometry on the per-pixel path), DR_E_NOMEM,
+ * DR_E_DEVICE. */
 dr_status dr_batch_create(dr_ctx ctx, int32_t n, const dr_batch_item* items, int32_t flags,
                           dr_batch* out);
 
@@ -244,7 +266,8 @@ dr_status dr_batch_free(dr_batch batch);
  * dr_reconstruct.  images: host (pinned) or device per images_on_device;
  * out/totals: device, as in dr_reconstruct.  The caller keeps every buffer
  * valid until dr_poll reports DR_OK or an error for the ticket.
- * Errors: DR_E_INVAL, DR_E_NOMEM (the request can never fit the budget). */
+ * Errors: DR_E_INVAL, DR_E_NOMEM (the request can never fit the budget),
+ * DR_E_UNSUPPORTED (a geometry on the per-pixel path: use dr_reconstruct). */
 dr_status dr_submit(dr_ctx ctx, dr_geom geom, const uint16_t* images, int images_on_device,
                     float* out, float* totals, uint64_t* ticket);
 

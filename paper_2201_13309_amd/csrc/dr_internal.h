@@ -60,13 +60,17 @@ struct ScanArgs {
     const int32_t* row_hi;
 };
 
-// Geometry as seen by the table builder and the debug kernel.
+// Geometry as seen by the table builder, the per-pixel kernels and the debug
+// kernel.  Coordinates are projected onto the plane normal to the wire axis:
+// (eta, xi), xi along the projected beam (see axis_frame in dr_kernels.hip).
 struct GeomArgs {
     int32_t nx, ny, n_steps, n_bins;
     double radius, first_center, width;
-    const double* wire_yz;  // [n_steps][2]
-    const double* pix_yz;   // [ny][nx][2] or null (affine map below)
-    double oy, uy, vy, oz, uz, vz;
+    double axis[3];         // wire axis as given (normalised on the device)
+    const double* wire_raw; // [n_steps][3] wire centres as given
+    const double* wire_yz;  // [n_steps][2] projected (eta, xi), built on the device
+    const double* pix_xyz;  // [ny][nx][3] explicit pixel centres, or null (affine map)
+    double origin[3], u[3], v[3];
 };
 
 struct BatchArgs {
@@ -104,6 +108,23 @@ hipError_t launch_totals_f64(const double* partials, int64_t slots, int n_bins, 
                              int work_rows, double* totals, hipStream_t s);
 hipError_t launch_debug_plan(const GeomArgs& g, const int64_t* pixels, int n, int side,
                              int32_t* bins, double* upos, hipStream_t s);
+// projected wire table; status bit 4 when the axis is zero or along the beam
+hipError_t launch_project_wire(const GeomArgs& g, double* wire_yz, int* d_status, hipStream_t s);
+// flags[j] = 1 when every pixel of row j has the row's first (eta, xi) bit for
+// bit (flags must be preset to 1)
+hipError_t launch_row_uniform(const GeomArgs& g, int* flags, hipStream_t s);
+// per-pixel geometry checks (status bits as in build_plans_kernel)
+hipError_t launch_validate_pixels(const GeomArgs& g, int* d_status, hipStream_t s);
+// per-pixel path: one lane per pixel, positions and bins computed in FP64 on
+// the fly.  side 0/1 = leading/trailing, scale as for the plan tables.
+hipError_t launch_pixels_f32(const ScanArgs& a, const GeomArgs& g, int side, double scale,
+                             hipStream_t s);
+hipError_t launch_pixels_f64(const ScanArgs& a, const GeomArgs& g, int side, double scale,
+                             hipStream_t s);
+constexpr int kPixelTile = 256;  // pixels per workgroup of the per-pixel path
+// largest partial-total row the per-pixel path sums in LDS (larger rows are
+// summed with device atomics in the partials buffer itself)
+constexpr size_t kPixelLdsBytes = 64 * 1024;
 
 constexpr int kPlanChunk = 1024;  // intervals staged in LDS at a time
 constexpr int kTotalsWorkRows = 64;

@@ -75,21 +75,59 @@ __device__ __forceinline__ double tangent_depth(double py, double pz, double cy,
     return cz - (cy * tz + sr * L2) / ty;
 }
 
-__device__ __forceinline__ void pixel_key(const GeomArgs& g, int64_t p, double& py, double& pz)
+// Frame of the plane normal to the wire axis a: e1 = (z - (z.a)a)/|...| (the
+// projected beam direction), e2 = e1 x a, c = e1.z (depth = xi / c).  For the
+// x axis: e1 = z, e2 = y, c = 1 exactly.
+struct Frame {
+    double e1[3], e2[3], c;
+    bool ok;
+};
+
+__device__ __forceinline__ Frame axis_frame(const GeomArgs& g)
 {
-    if (g.pix_yz) {
-        py = g.pix_yz[2 * p];
-        pz = g.pix_yz[2 * p + 1];
-        return;
-    }
-    const double i = (double)(p % g.nx);
-    const double j = (double)(p / g.nx);
-    py = (g.oy + i * g.uy) + j * g.vy;
-    pz = (g.oz + i * g.uz) + j * g.vz;
+    Frame f;
+    const double n = __builtin_sqrt((g.axis[0] * g.axis[0] + g.axis[1] * g.axis[1]) +
+                                    g.axis[2] * g.axis[2]);
+    const double a0 = g.axis[0] / n, a1 = g.axis[1] / n, a2 = g.axis[2] / n;
+    const double z0 = 0.0 - a2 * a0, z1 = 0.0 - a2 * a1, z2 = 1.0 - a2 * a2;
+    const double m = __builtin_sqrt((z0 * z0 + z1 * z1) + z2 * z2);
+    f.ok = (n > 0.0) && (m > 1e-6);
+    f.e1[0] = z0 / m;
+    f.e1[1] = z1 / m;
+    f.e1[2] = z2 / m;
+    f.e2[0] = f.e1[1] * a2 - f.e1[2] * a1;
+    f.e2[1] = f.e1[2] * a0 - f.e1[0] * a2;
+    f.e2[2] = f.e1[0] * a1 - f.e1[1] * a0;
+    f.c = f.e1[2];
+    return f;
 }
 
-// Leading-edge side: +1 when the +z tangent depth of the last step exceeds
-// that of the first.
+__device__ __forceinline__ void project(const Frame& f, const double* X, double& eta, double& xi)
+{
+    xi = (X[0] * f.e1[0] + X[1] * f.e1[1]) + X[2] * f.e1[2];
+    eta = (X[0] * f.e2[0] + X[1] * f.e2[1]) + X[2] * f.e2[2];
+}
+
+// Projected (eta, xi) of pixel p: centre (origin + i*u) + j*v or the table.
+__device__ __forceinline__ void pixel_key(const GeomArgs& g, const Frame& f, int64_t p,
+                                          double& py, double& pz)
+{
+    double X[3];
+    if (g.pix_xyz) {
+        X[0] = g.pix_xyz[3 * p];
+        X[1] = g.pix_xyz[3 * p + 1];
+        X[2] = g.pix_xyz[3 * p + 2];
+    } else {
+        const double i = (double)(p % g.nx);
+        const double j = (double)(p / g.nx);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) X[q] = (g.origin[q] + i * g.u[q]) + j * g.v[q];
+    }
+    project(f, X, py, pz);
+}
+
+// Leading-edge side: +1 when the +xi tangent point of the last step lies
+// beyond that of the first.
 __device__ __forceinline__ int leading_sign(const GeomArgs& g, double py, double pz)
 {
     const int l = g.n_steps - 1;
@@ -100,9 +138,10 @@ __device__ __forceinline__ int leading_sign(const GeomArgs& g, double py, double
 }
 
 __device__ __forceinline__ double edge_position(const GeomArgs& g, double py, double pz, int k,
-                                                double sr, double e0, double invw)
+                                                double sr, double c, double e0, double invw)
 {
-    const double d = tangent_depth(py, pz, g.wire_yz[2 * k], g.wire_yz[2 * k + 1], g.radius, sr);
+    const double d =
+        tangent_depth(py, pz, g.wire_yz[2 * k], g.wire_yz[2 * k + 1], g.radius, sr) / c;
     return (d - e0) * invw;
 }
 
@@ -173,16 +212,17 @@ __global__ __launch_bounds__(256) void build_plans_kernel(GeomArgs g, PlanTables
 {
     const int row = blockIdx.x;
     const int N = g.n_steps, B = g.n_bins, nint = N - 1;
+    const Frame f = axis_frame(g);
     double py, pz;
-    pixel_key(g, (int64_t)row * g.nx, py, pz);
+    pixel_key(g, f, (int64_t)row * g.nx, py, pz);
     const int s = side ? -leading_sign(g, py, pz) : leading_sign(g, py, pz);
     const double sr = (double)s * g.radius;
     const double e0 = g.first_center - g.width / 2.0;
     const double invw = 1.0 / g.width;
     int inc = 1, dec = 1, bad = 0;
     for (int k = threadIdx.x; k < nint; k += blockDim.x) {
-        const double ua = edge_position(g, py, pz, k, sr, e0, invw);
-        const double ub = edge_position(g, py, pz, k + 1, sr, e0, invw);
+        const double ua = edge_position(g, py, pz, k, sr, f.c, e0, invw);
+        const double ub = edge_position(g, py, pz, k + 1, sr, f.c, e0, invw);
         if (!__builtin_isfinite(ua) || !__builtin_isfinite(ub)) bad |= 1;
         for (int kk = k; kk <= k + 1; ++kk) {
             const double cy = g.wire_yz[2 * kk];
@@ -511,23 +551,19 @@ __device__ __forceinline__ void process_tile_mono(const ScanArgs& a, int row, in
     for (int q = 0; q < PPL; ++q) acc[q] = (Acc)0;
     int cb = -1;  // open bin (uniform), -1 = none
 
-    const bool add_on = a.pass == 2;  // second pass: add onto the first pass's output
-    auto put = [&]() {
-        if (act) {
-            if (add_on) {
-                Acc* o = outp(cb);
-                Acc v[PPL];
+    // second pass of two: an opened bin starts from the first pass's value and
+    // the contributions are added one by one in step order (the oracle's
+    // sequential accumulation); cacc keeps this pass's own sum for the totals
+    const bool add_on = a.pass == 2;
+    Acc cacc[PPL];
 #pragma unroll
-                for (int q = 0; q < PPL; ++q) v[q] = o[q] + acc[q];
-                store_bins<Acc, PPL>(o, v);
-            } else {
-                store_bins<Acc, PPL>(outp(cb), acc);
-            }
-        }
+    for (int q = 0; q < PPL; ++q) cacc[q] = (Acc)0;
+    auto put = [&]() {
+        if (act) store_bins<Acc, PPL>(outp(cb), acc);
         if (pwin.row) {
             Acc s = (Acc)0;
 #pragma unroll
-            for (int q = 0; q < PPL; ++q) s += acc[q];
+            for (int q = 0; q < PPL; ++q) s += add_on ? cacc[q] : acc[q];
             pwin.add(cb, wave_total(act ? s : (Acc)0), lane);
         }
     };
@@ -544,11 +580,23 @@ __device__ __forceinline__ void process_tile_mono(const ScanArgs& a, int row, in
             if (b != cb) {
                 if (cb >= 0) put();
                 cb = b;
+                if (add_on) {
+                    const Acc* o = outp(b);
 #pragma unroll
-                for (int q = 0; q < PPL; ++q) acc[q] = madd(f, dI[q], (Acc)0);
+                    for (int q = 0; q < PPL; ++q) {
+                        acc[q] = madd(f, dI[q], act ? o[q] : (Acc)0);
+                        cacc[q] = madd(f, dI[q], (Acc)0);
+                    }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < PPL; ++q) acc[q] = madd(f, dI[q], (Acc)0);
+                }
             } else {
 #pragma unroll
                 for (int q = 0; q < PPL; ++q) acc[q] = madd(f, dI[q], acc[q]);
+                if (add_on)
+#pragma unroll
+                    for (int q = 0; q < PPL; ++q) cacc[q] = madd(f, dI[q], cacc[q]);
             }
         };
         if constexpr (NB2) {
@@ -704,16 +752,196 @@ __global__ __launch_bounds__(64) void debug_plan_kernel(GeomArgs g, const int64_
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= n) return;
+    const Frame f = axis_frame(g);
     double py, pz;
-    pixel_key(g, pix[idx], py, pz);
+    pixel_key(g, f, pix[idx], py, pz);
     const int s = side ? -leading_sign(g, py, pz) : leading_sign(g, py, pz);
     const double sr = (double)s * g.radius;
     const double e0 = g.first_center - g.width / 2.0;
     const double invw = 1.0 / g.width;
     for (int k = 0; k < g.n_steps; ++k) {
-        const double u = edge_position(g, py, pz, k, sr, e0, invw);
+        const double u = edge_position(g, py, pz, k, sr, f.c, e0, invw);
         if (bins) bins[(int64_t)idx * g.n_steps + k] = floor_to_i32(u);
         if (upos) upos[(int64_t)idx * g.n_steps + k] = u;
+    }
+}
+
+// -------------------------------------------------------- general geometry
+
+__global__ __launch_bounds__(256) void project_wire_kernel(GeomArgs g, double* wyz, int* status)
+{
+    const Frame f = axis_frame(g);
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (!f.ok) {
+        if (k == 0) atomicOr(status, 4);
+        return;
+    }
+    if (k >= g.n_steps) return;
+    double eta, xi;
+    project(f, g.wire_raw + 3 * k, eta, xi);
+    wyz[2 * k] = eta;
+    wyz[2 * k + 1] = xi;
+}
+
+// flags[j] stays 1 when every pixel of row j shares the row's first key bits
+__global__ __launch_bounds__(256) void row_uniform_kernel(GeomArgs g, int* flags)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= (int64_t)g.nx * g.ny) return;
+    const Frame f = axis_frame(g);
+    const int64_t j = p / g.nx;
+    double y, z, y0, z0;
+    pixel_key(g, f, p, y, z);
+    pixel_key(g, f, j * g.nx, y0, z0);
+    if (__double_as_longlong(y) != __double_as_longlong(y0) ||
+        __double_as_longlong(z) != __double_as_longlong(z0))
+        flags[j] = 0;
+}
+
+// every (pixel, step) of a per-pixel geometry: finite positions, wire between
+// beam and pixel (status bits 1 and 2 as in build_plans_kernel)
+__global__ __launch_bounds__(256) void validate_pixels_kernel(GeomArgs g, int* status)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= (int64_t)g.nx * g.ny) return;
+    const Frame f = axis_frame(g);
+    double py, pz;
+    pixel_key(g, f, p, py, pz);
+    const double e0 = g.first_center - g.width / 2.0;
+    const double invw = 1.0 / g.width;
+    int bad = 0;
+    for (int side = 0; side < 2; ++side) {
+        const int s = side ? -leading_sign(g, py, pz) : leading_sign(g, py, pz);
+        const double sr = (double)s * g.radius;
+        for (int k = 0; k < g.n_steps; ++k) {
+            const double u = edge_position(g, py, pz, k, sr, f.c, e0, invw);
+            if (!__builtin_isfinite(u)) bad |= 1;
+        }
+    }
+    for (int k = 0; k < g.n_steps; ++k) {
+        const double cy = g.wire_yz[2 * k];
+        if (!(cy > 0.0 && cy < py)) bad |= 2;
+    }
+    if (bad) atomicOr(status, bad);
+}
+
+// Per-pixel path: one lane per pixel of a row tile of kPixelTile pixels.  Each
+// lane computes its own FP64 positions step by step, plans the interval, and
+// streams its bins in the direction its edge moves (bins are visited in order
+// then; a bin already stored and visited again is read, added to and
+// rewritten, so any sequence of positions is handled).  Partial totals are
+// accumulated per workgroup in LDS and written as one row per workgroup.
+template <typename Acc, int PF>
+__global__ __launch_bounds__(kPixelTile) void pixels_kernel(ScanArgs a, GeomArgs g, int side,
+                                                            double scale)
+{
+    extern __shared__ __align__(16) unsigned char dyn_lds[];
+    const int tid = threadIdx.x;
+    const int row = a.row_begin + (int)(blockIdx.x / (unsigned)a.tiles_per_row);
+    const int tile = (int)(blockIdx.x % (unsigned)a.tiles_per_row);
+    const int col = tile * kPixelTile + tid;
+    const bool act = col < a.nx;
+    const int N = a.n_steps, B = a.n_bins;
+    const bool add_on = a.pass == 2;
+    const bool tot = a.partials != nullptr;
+    // the workgroup's partial-total row: summed in LDS when it fits, else in
+    // place in its own row of the partials buffer
+    Acc* const gp = tot ? (Acc*)a.partials + (int64_t)(row * a.tiles_per_row + tile) * B : nullptr;
+    const bool in_lds = (size_t)B * sizeof(Acc) <= kPixelLdsBytes;
+    Acc* const ltot = in_lds ? reinterpret_cast<Acc*>(dyn_lds) : gp;
+    if (tot)
+        for (int b = tid; b < B; b += kPixelTile) ltot[b] = (Acc)0;
+    __syncthreads();
+
+    const Frame f = axis_frame(g);
+    double py, pz;
+    pixel_key(g, f, (int64_t)row * a.nx + (act ? col : 0), py, pz);
+    const int s = side ? -leading_sign(g, py, pz) : leading_sign(g, py, pz);
+    const double sr = (double)s * g.radius;
+    const double e0 = g.first_center - g.width / 2.0;
+    const double invw = 1.0 / g.width;
+    const double u_first = edge_position(g, py, pz, 0, sr, f.c, e0, invw);
+    const double u_last = edge_position(g, py, pz, N - 1, sr, f.c, e0, invw);
+    const int dir = (u_last >= u_first) ? 1 : -1;
+
+    const uint16_t* ip = a.img + (int64_t)(row - a.row_base) * a.img_row + (act ? col : 0);
+    Acc* op = (Acc*)a.out + (int64_t)row * a.nx + col;
+    const int64_t plane = a.out_plane;
+    auto binp = [&](int bp) { return dir > 0 ? bp : B - 1 - bp; };
+
+    Acc acc = (Acc)0;
+    int cbp = -1;  // open bin in the direction frame (-1: none); when open, cbp == nxt
+    int nxt = 0;   // first bin (direction frame) not yet stored
+    auto store = [&](int bp, Acc v) {
+        if (act) stream_store(v, op + (int64_t)binp(bp) * plane);
+    };
+    auto close_open = [&]() {
+        if (cbp >= 0) {
+            store(cbp, acc);
+            nxt = cbp + 1;
+            cbp = -1;
+        }
+    };
+    auto visit = [&](int b, Acc fr, Acc dI) {
+        const int bp = dir > 0 ? b : B - 1 - b;
+        if (tot && act) atomicAdd(&ltot[b], fr * dI);
+        if (bp == cbp) {
+            acc = madd(fr, dI, acc);
+        } else if (bp >= nxt) {
+            close_open();
+            if (!add_on)
+                for (int z = nxt; z < bp; ++z) store(z, (Acc)0);
+            cbp = bp;
+            nxt = bp;
+            Acc* o = op + (int64_t)b * plane;
+            acc = madd(fr, dI, (add_on && act) ? *o : (Acc)0);
+        } else if (act) {  // stored already: read, add, rewrite
+            Acc* o = op + (int64_t)b * plane;
+            *o = madd(fr, dI, *o);
+        }
+    };
+
+    constexpr int U = PF + 1;
+    unsigned short ring[U];
+#pragma unroll
+    for (int d = 0; d < U; ++d) ring[d] = stream_load(ip + (int64_t)min(d, N - 1) * a.img_step);
+    double u_prev = u_first;
+    int k = 0;
+    for (; k + U <= N - 1; k += U) {
+#pragma unroll
+        for (int d = 0; d < U; ++d) {
+            const double u_next = edge_position(g, py, pz, k + d + 1, sr, f.c, e0, invw);
+            const PlanD e = make_plan(u_prev, u_next, B);
+            const Acc dI = (Acc)((int)ring[d] - (int)ring[(d + 1) % U]);
+            const Acc f0 = (Acc)(e.f0 * scale), fm = (Acc)(e.fm * scale), f1 = (Acc)(e.f1 * scale);
+            const int bh = e.bl + e.nb - 1;
+            int b = dir > 0 ? e.bl : bh;
+            for (int q = 0; q < e.nb; ++q, b += dir)
+                visit(b, (b == e.bl) ? f0 : ((b == bh) ? f1 : fm), dI);
+            u_prev = u_next;
+            ring[d] = stream_load(ip + (int64_t)min(k + d + U, N - 1) * a.img_step);
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < U; ++d) {
+        if (k + d < N - 1) {
+            const double u_next = edge_position(g, py, pz, k + d + 1, sr, f.c, e0, invw);
+            const PlanD e = make_plan(u_prev, u_next, B);
+            const Acc dI = (Acc)((int)ring[d] - (int)ring[(d + 1) % U]);
+            const Acc f0 = (Acc)(e.f0 * scale), fm = (Acc)(e.fm * scale), f1 = (Acc)(e.f1 * scale);
+            const int bh = e.bl + e.nb - 1;
+            int b = dir > 0 ? e.bl : bh;
+            for (int q = 0; q < e.nb; ++q, b += dir)
+                visit(b, (b == e.bl) ? f0 : ((b == bh) ? f1 : fm), dI);
+            u_prev = u_next;
+        }
+    }
+    close_open();
+    if (!add_on)
+        for (int z = nxt; z < B; ++z) store(z, (Acc)0);
+    if (tot && in_lds) {
+        __syncthreads();
+        for (int b = tid; b < B; b += kPixelTile) gp[b] = ltot[b];
     }
 }
 
@@ -829,6 +1057,54 @@ hipError_t launch_totals_f64(const double* partials, int64_t slots, int n_bins, 
                              int work_rows, double* totals, hipStream_t s)
 {
     return launch_totals<double>(partials, slots, n_bins, work, work_rows, totals, s);
+}
+
+hipError_t launch_project_wire(const GeomArgs& g, double* wire_yz, int* d_status, hipStream_t s)
+{
+    hipLaunchKernelGGL(project_wire_kernel, dim3((unsigned)((g.n_steps + 255) / 256)), dim3(256),
+                       0, s, g, wire_yz, d_status);
+    return hipGetLastError();
+}
+
+hipError_t launch_row_uniform(const GeomArgs& g, int* flags, hipStream_t s)
+{
+    const int64_t n = (int64_t)g.nx * g.ny;
+    hipLaunchKernelGGL(row_uniform_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g,
+                       flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate_pixels(const GeomArgs& g, int* d_status, hipStream_t s)
+{
+    const int64_t n = (int64_t)g.nx * g.ny;
+    hipLaunchKernelGGL(validate_pixels_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       g, d_status);
+    return hipGetLastError();
+}
+
+template <typename Acc>
+static hipError_t launch_pixels(const ScanArgs& a, const GeomArgs& g, int side, double scale,
+                                hipStream_t s)
+{
+    const int64_t rows = a.row_end - a.row_begin;
+    if (rows <= 0) return hipSuccess;
+    const size_t need = (size_t)a.n_bins * sizeof(Acc);
+    const size_t lds = (a.partials && need <= kPixelLdsBytes) ? need : 0;
+    hipLaunchKernelGGL((pixels_kernel<Acc, 8>), dim3((unsigned)(rows * a.tiles_per_row)),
+                       dim3(kPixelTile), lds, s, a, g, side, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_pixels_f32(const ScanArgs& a, const GeomArgs& g, int side, double scale,
+                             hipStream_t s)
+{
+    return launch_pixels<float>(a, g, side, scale, s);
+}
+
+hipError_t launch_pixels_f64(const ScanArgs& a, const GeomArgs& g, int side, double scale,
+                             hipStream_t s)
+{
+    return launch_pixels<double>(a, g, side, scale, s);
 }
 
 hipError_t launch_debug_plan(const GeomArgs& g, const int64_t* pixels, int n, int side,

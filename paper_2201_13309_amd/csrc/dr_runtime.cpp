@@ -61,13 +61,14 @@ TileCfg default_tile(const dr_geom g, const void* img, const void* out)
 
 static int tiles_per_row(const dr_geom g, const TileCfg& t)
 {
-    const int tw = tile_width(t);
+    const int tw = g->row_mode ? tile_width(t) : kPixelTile;
     return (g->nx + tw - 1) / tw;
 }
 
 int64_t partial_slots(const dr_geom g, const TileCfg& t)
 {
-    return (int64_t)g->ny * tiles_per_row(g, t) * t.waves;
+    // per-pixel path: one partial row per workgroup
+    return (int64_t)g->ny * tiles_per_row(g, t) * (g->row_mode ? t.waves : 1);
 }
 
 ScanArgs scan_args(const dr_geom g, const TileCfg& t, int pass, const uint16_t* img,
@@ -90,6 +91,7 @@ ScanArgs scan_args(const dr_geom g, const TileCfg& t, int pass, const uint16_t* 
     a.out = out;
     a.out_plane = (int64_t)g->nx * g->ny;
     a.partials = partials ? partials + (size_t)pass * partial_slots(g, t) * g->n_bins : nullptr;
+    if (!g->row_mode) return a;
     const PlanTables& pt = g->t[pass];
     a.bl = pt.bl;
     a.nb = pt.nb;
@@ -262,8 +264,7 @@ dr_status dr_geometry_init(dr_ctx c, const dr_detector* det, const dr_wire* wire
         return set_error(DR_E_INVAL, "depth grid width must be > 0 and finite");
     if (!finite3(det->origin) || !finite3(det->u) || !finite3(det->v))
         return set_error(DR_E_INVAL, "detector origin/u/v must be finite");
-    if (!(wire->axis[0] == 1.0 && wire->axis[1] == 0.0 && wire->axis[2] == 0.0))
-        return set_error(DR_E_UNSUPPORTED, "only a wire axis along x (1,0,0) is supported");
+    if (!finite3(wire->axis)) return set_error(DR_E_INVAL, "wire axis must be finite");
     if (wire->edge != DR_EDGE_LEADING && wire->edge != DR_EDGE_TRAILING &&
         wire->edge != DR_EDGE_BOTH)
         return set_error(DR_E_INVAL, "wire edge must be DR_EDGE_LEADING, _TRAILING or _BOTH");
@@ -273,34 +274,10 @@ dr_status dr_geometry_init(dr_ctx c, const dr_detector* det, const dr_wire* wire
     for (int k = 0; k < N; ++k)
         if (!finite3(wire->centers + 3 * k))
             return set_error(DR_E_INVAL, "wire centers must be finite");
-
-    // Rows share one bit-identical (y, z) centre when u has no y or z part,
-    // or when the explicit table says so row by row.
-    bool row_mode = true;
-    std::vector<double> pyz;
-    if (det->pixel_xyz) {
-        pyz.resize((size_t)nx * ny * 2);
-        for (int64_t p = 0; p < (int64_t)nx * ny; ++p) {
-            const double* q = det->pixel_xyz + 3 * p;
-            if (!finite3(q)) return set_error(DR_E_INVAL, "pixel_xyz must be finite");
-            pyz[2 * p] = q[1];
-            pyz[2 * p + 1] = q[2];
-        }
-        for (int j = 0; j < ny && row_mode; ++j) {
-            const double* r0 = pyz.data() + (size_t)2 * j * nx;
-            for (int i = 1; i < nx; ++i)
-                if (std::memcmp(r0, r0 + 2 * i, 2 * sizeof(double)) != 0) {
-                    row_mode = false;
-                    break;
-                }
-        }
-    } else {
-        row_mode = (det->u[1] == 0.0 && det->u[2] == 0.0);
-    }
-    if (!row_mode)
-        return set_error(DR_E_UNSUPPORTED,
-                         "detector rows must share their (y, z) pixel centre (u with no y or z "
-                         "component); a per-pixel geometry is not supported yet");
+    if (det->pixel_xyz)
+        for (int64_t p = 0; p < (int64_t)nx * ny; ++p)
+            if (!finite3(det->pixel_xyz + 3 * p))
+                return set_error(DR_E_INVAL, "pixel_xyz must be finite");
 
     DR_HIP(hipSetDevice(c->device));
     auto g = std::make_unique<dr_geom_s>();
@@ -312,22 +289,43 @@ dr_status dr_geometry_init(dr_ctx c, const dr_detector* det, const dr_wire* wire
     g->radius = wire->radius;
     g->first_center = grid->first_center;
     g->width = grid->width;
-    g->row_mode = row_mode;
     g->edge = wire->edge;
     g->passes = wire->edge == DR_EDGE_BOTH ? 2 : 1;
+    for (int p = 0; p < g->passes; ++p) {
+        // leading: side s_p, fractions as they are; trailing: side -s_p,
+        // fractions negated (I_{k+1} - I_k); both: leading then trailing at 1/2
+        g->side[p] = 0;
+        g->scale[p] = 1.0;
+        if (g->edge == DR_EDGE_TRAILING) {
+            g->side[p] = 1;
+            g->scale[p] = -1.0;
+        } else if (g->edge == DR_EDGE_BOTH) {
+            g->side[p] = p;
+            g->scale[p] = p == 0 ? 0.5 : -0.5;
+        }
+    }
 
-    std::vector<double> wyz((size_t)N * 2);
-    for (int k = 0; k < N; ++k) {
-        wyz[2 * k] = wire->centers[3 * k + 1];
-        wyz[2 * k + 1] = wire->centers[3 * k + 2];
+    // wire: raw centres [N][3], then the projected (eta, xi) [N][2]; pixel
+    // centres [ny][nx][3] when given explicitly; one status word and one
+    // row-uniformity flag per row
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t w_raw = 0, w_yz = up((size_t)N * 3 * 8), w_st = w_yz + up((size_t)N * 2 * 8),
+                 w_fl = w_st + 256, w_total = w_fl + up((size_t)ny * 4);
+    DR_HIP(g->wire.reserve(w_total));
+    char* wb = g->wire.as<char>();
+    double* d_wraw = (double*)(wb + w_raw);
+    double* d_wyz = (double*)(wb + w_yz);
+    int* d_status = (int*)(wb + w_st);
+    int* d_flags = (int*)(wb + w_fl);
+    DR_HIP(hipMemcpyAsync(d_wraw, wire->centers, (size_t)N * 3 * sizeof(double),
+                          hipMemcpyHostToDevice, c->stream));
+    if (det->pixel_xyz) {
+        DR_HIP(g->pix.reserve((size_t)nx * ny * 3 * sizeof(double)));
+        DR_HIP(hipMemcpyAsync(g->pix.p, det->pixel_xyz, (size_t)nx * ny * 3 * sizeof(double),
+                              hipMemcpyHostToDevice, c->stream));
     }
-    DR_HIP(g->wire.reserve(wyz.size() * sizeof(double)));
-    DR_HIP(hipMemcpy(g->wire.p, wyz.data(), wyz.size() * sizeof(double), hipMemcpyHostToDevice));
-    if (!pyz.empty()) {
-        DR_HIP(g->pix.reserve(pyz.size() * sizeof(double)));
-        DR_HIP(hipMemcpy(g->pix.p, pyz.data(), pyz.size() * sizeof(double),
-                         hipMemcpyHostToDevice));
-    }
+    DR_HIP(hipMemsetAsync(d_status, 0, sizeof(int), c->stream));
+    DR_HIP(hipMemsetAsync(d_flags, 1, (size_t)ny * sizeof(int), c->stream));
 
     GeomArgs& ga = g->g;
     ga.nx = nx;
@@ -337,26 +335,55 @@ dr_status dr_geometry_init(dr_ctx c, const dr_detector* det, const dr_wire* wire
     ga.radius = wire->radius;
     ga.first_center = grid->first_center;
     ga.width = grid->width;
-    ga.wire_yz = g->wire.as<double>();
-    ga.pix_yz = g->pix.as<double>();
-    ga.oy = det->origin[1];
-    ga.uy = det->u[1];
-    ga.vy = det->v[1];
-    ga.oz = det->origin[2];
-    ga.uz = det->u[2];
-    ga.vz = det->v[2];
+    for (int i = 0; i < 3; ++i) {
+        ga.axis[i] = wire->axis[i];
+        ga.origin[i] = det->origin[i];
+        ga.u[i] = det->u[i];
+        ga.v[i] = det->v[i];
+    }
+    ga.wire_raw = d_wraw;
+    ga.wire_yz = d_wyz;
+    ga.pix_xyz = det->pixel_xyz ? g->pix.as<double>() : nullptr;
+    DR_HIP(launch_project_wire(ga, d_wyz, d_status, c->stream));
+    DR_HIP(launch_row_uniform(ga, d_flags, c->stream));
+    int status = 0;
+    std::vector<int> flags(ny);
+    DR_HIP(hipMemcpyAsync(&status, d_status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    DR_HIP(hipMemcpyAsync(flags.data(), d_flags, (size_t)ny * sizeof(int),
+                          hipMemcpyDeviceToHost, c->stream));
+    DR_HIP(hipStreamSynchronize(c->stream));
+    if (status & 4)
+        return set_error(DR_E_INVAL, "wire axis is zero or along the beam");
+    // Rows whose pixels all share one projected (eta, xi), bit for bit, take
+    // the per-row plan tables; any other geometry takes the per-pixel path.
+    bool row_mode = true;
+    for (int j = 0; j < ny; ++j) row_mode = row_mode && flags[j] != 0;
+    g->row_mode = row_mode;
+
+    if (!row_mode) {
+        DR_HIP(launch_validate_pixels(ga, d_status, c->stream));
+        DR_HIP(hipMemcpyAsync(&status, d_status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        DR_HIP(hipStreamSynchronize(c->stream));
+        if (status & 1)
+            return set_error(DR_E_INVAL, "geometry gives a non-finite depth (pixel inside the "
+                                         "wire or a ray parallel to the beam)");
+        if (status & 2)
+            return set_error(DR_E_INVAL,
+                             "wire not strictly between the beam and the detector in y");
+        for (int i = 0; i < 3; ++i) DR_HIP(hipEventCreate(&g->ev[i]));
+        c->live_geoms++;
+        *out = g.release();
+        return ok();
+    }
 
     // plan tables per pass: bl, nb (int32), f0, fm, f1 (float), d0, dm, d1 (double),
-    // class, side, touched-bin range.  Leading: side s_p, fractions as they are;
-    // trailing: side -s_p, fractions negated (I_{k+1} - I_k); both: the two at 1/2.
+    // class, side, touched-bin range
     const size_t ent = (size_t)ny * (N - 1);
-    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
     const size_t o_bl = 0, o_nb = o_bl + up(ent * 4), o_f0 = o_nb + up(ent * 4),
                  o_fm = o_f0 + up(ent * 4), o_f1 = o_fm + up(ent * 4), o_d0 = o_f1 + up(ent * 4),
                  o_dm = o_d0 + up(ent * 8), o_d1 = o_dm + up(ent * 8), o_cls = o_d1 + up(ent * 8),
                  o_sgn = o_cls + up(ny), o_lo = o_sgn + up(ny), o_hi = o_lo + up((size_t)ny * 4),
-                 o_st = o_hi + up((size_t)ny * 4), total = o_st + 256;
-    int* d_status = nullptr;
+                 total = o_hi + up((size_t)ny * 4);
     for (int p = 0; p < g->passes; ++p) {
         DR_HIP(g->plan[p].reserve(total));
         char* base = g->plan[p].as<char>();
@@ -373,24 +400,10 @@ dr_status dr_geometry_init(dr_ctx c, const dr_detector* det, const dr_wire* wire
         t.row_sign = (int8_t*)(base + o_sgn);
         t.row_lo = (int32_t*)(base + o_lo);
         t.row_hi = (int32_t*)(base + o_hi);
-        if (p == 0) {
-            d_status = (int*)(base + o_st);
-            DR_HIP(hipMemsetAsync(d_status, 0, sizeof(int), c->stream));
-        }
-        int side = 0;
-        double scale = 1.0;
-        if (g->edge == DR_EDGE_TRAILING) {
-            side = 1;
-            scale = -1.0;
-        } else if (g->edge == DR_EDGE_BOTH) {
-            side = p;
-            scale = p == 0 ? 0.5 : -0.5;
-        }
-        DR_HIP(launch_build_plans(ga, t, side, scale, d_status, c->stream));
+        DR_HIP(launch_build_plans(ga, t, g->side[p], g->scale[p], d_status, c->stream));
     }
     if (g->passes == 2)
         DR_HIP(launch_unify_classes(g->t[0].row_class, g->t[1].row_class, ny, c->stream));
-    int status = 0;
     DR_HIP(hipMemcpyAsync(&status, d_status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     DR_HIP(hipStreamSynchronize(c->stream));
     if (status & 1)
@@ -412,6 +425,13 @@ dr_status dr_geometry_init(dr_ctx c, const dr_detector* det, const dr_wire* wire
     return ok();
 }
 
+dr_status dr_geometry_path(dr_geom g, int32_t* path)
+{
+    if (!g || !path) return set_error(DR_E_INVAL, "dr_geometry_path: NULL argument");
+    *path = g->row_mode ? DR_PATH_ROWS : DR_PATH_PIXELS;
+    return ok();
+}
+
 dr_status dr_geometry_free(dr_geom g)
 {
     if (!g) return set_error(DR_E_INVAL, "dr_geometry_free: NULL geometry");
@@ -429,6 +449,8 @@ dr_status dr_geometry_free(dr_geom g)
 dr_status dr_set_tile(dr_geom g, const dr_tile_config* tile)
 {
     if (!g) return set_error(DR_E_INVAL, "dr_set_tile: NULL geometry");
+    if (!g->row_mode && tile)
+        return set_error(DR_E_UNSUPPORTED, "dr_set_tile: a per-pixel geometry has one launch shape");
     std::lock_guard<std::mutex> lk(g->mu);
     if (!tile) {
         g->forced = false;
@@ -442,6 +464,14 @@ dr_status dr_set_tile(dr_geom g, const dr_tile_config* tile)
     return ok();
 }
 
+// pass p of either path: the per-row plan kernel or the per-pixel kernel
+static hipError_t launch_f32(const dr_geom g, const TileCfg& t, int p, const ScanArgs& a,
+                             hipStream_t s)
+{
+    if (g->row_mode) return launch_rows_f32(t, a, s);
+    return launch_pixels_f32(a, g->g, g->side[p], g->scale[p], s);
+}
+
 static dr_status reconstruct_device(dr_geom g, const TileCfg& t, const uint16_t* images,
                                     float* out, float* totals, hipStream_t s)
 {
@@ -453,7 +483,7 @@ static dr_status reconstruct_device(dr_geom g, const TileCfg& t, const uint16_t*
     if (g->timing) DR_HIP(hipEventRecord(g->ev[0], s));
     for (int p = 0; p < g->passes; ++p) {
         ScanArgs a = scan_args(g, t, p, images, (int64_t)g->nx * g->ny, 0, 0, g->ny, out, part);
-        DR_HIP(launch_rows_f32(t, a, s));
+        DR_HIP(launch_f32(g, t, p, a, s));
     }
     if (g->timing) DR_HIP(hipEventRecord(g->ev[1], s));
     if (totals)
@@ -513,7 +543,7 @@ static dr_status reconstruct_streamed(dr_geom g, const TileCfg& t, const uint16_
         for (int p = 0; p < g->passes; ++p) {
             ScanArgs a = scan_args(g, t, p, c->slab[b].as<uint16_t>(), (int64_t)R * g->nx, r0,
                                    r0, r0 + rs, out, part);
-            DR_HIP(launch_rows_f32(t, a, s));
+            DR_HIP(launch_f32(g, t, p, a, s));
         }
         DR_HIP(hipEventRecord(c->slab_free[b], s));
     }
@@ -569,7 +599,10 @@ dr_status dr_reconstruct_f64(dr_geom g, const uint16_t* images, double* out, dou
                                nullptr);
         a.out = out;
         a.partials = part ? part + (size_t)p * slots * g->n_bins : nullptr;
-        DR_HIP(launch_rows_f64(a, s));
+        if (g->row_mode)
+            DR_HIP(launch_rows_f64(a, s));
+        else
+            DR_HIP(launch_pixels_f64(a, g->g, g->side[p], g->scale[p], s));
     }
     if (totals)
         DR_HIP(launch_totals_f64(part, slots * g->passes, g->n_bins, g->work.as<double>(),
@@ -630,6 +663,10 @@ dr_status dr_last_timing(dr_geom g, double* kernel_ms, double* totals_ms)
 dr_status dr_autotune(dr_geom g, const uint16_t* images, float* out, dr_tile_config* chosen)
 {
     if (!g || !images || !out) return set_error(DR_E_INVAL, "dr_autotune: NULL argument");
+    if (!g->row_mode) {  // one launch shape: a pixel per lane, four waves, prefetch 8
+        if (chosen) *chosen = dr_tile_config{1, kPixelTile / 64, 8, 0};
+        return ok();
+    }
     dr_ctx c = g->ctx;
     DR_HIP(hipSetDevice(c->device));
     hipStream_t s = c->stream;
@@ -808,6 +845,9 @@ dr_status dr_batch_create(dr_ctx c, int32_t n, const dr_batch_item* items, int32
             return set_error(DR_E_INVAL, "dr_batch_create: NULL item field");
         if (it.geom->ctx != c)
             return set_error(DR_E_INVAL, "dr_batch_create: geometry of another context");
+        if (!items[i].geom->row_mode)
+            return set_error(DR_E_UNSUPPORTED,
+                             "dr_batch_create: per-pixel geometries are reconstructed one by one");
         b->items.push_back(it);
         b->geoms.push_back(it.geom);
     }

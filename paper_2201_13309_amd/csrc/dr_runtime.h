@@ -80,9 +80,13 @@ struct dr_geom_s {
     bool row_mode = true;
     int edge = DR_EDGE_LEADING;
     int passes = 1;  // 2 for DR_EDGE_BOTH: leading, then trailing added on
+    int side[2] = {0, 0};         // per pass: 0 leading side s_p, 1 trailing side -s_p
+    double scale[2] = {1.0, 1.0};  // per pass: factor on every fraction
     dr::GeomArgs g{};
     dr::PlanTables t[2]{};
-    dr::DevBuf wire, pix, plan[2];  // plan[p]: all plan tables of pass p in one allocation
+    // wire: raw and projected centres, status and row flags; pix: explicit
+    // pixel centres; plan[p]: all plan tables of pass p in one allocation
+    dr::DevBuf wire, pix, plan[2];
     dr::DevBuf part32, part64, work;
     std::mutex mu;
     bool forced = false, tuned = false;

@@ -24,10 +24,12 @@ DR_E_INVAL, DR_E_NOMEM, DR_E_UNSUPPORTED, DR_E_DEVICE, DR_E_BUSY, DR_E_NOTFOUND 
     -1, -2, -3, -4, -5, -6)
 DR_EDGE_LEADING, DR_EDGE_TRAILING, DR_EDGE_BOTH = 0, 1, 2
 DR_BATCH_AUTOTUNE, DR_BATCH_GRAPH = 1, 2
+DR_PATH_ROWS, DR_PATH_PIXELS = 0, 1
 
 # names exported by libdr.so, as declared in include/dr.h
 ABI_SYMBOLS = (
-    "dr_ctx_create", "dr_ctx_destroy", "dr_geometry_init", "dr_geometry_free", "dr_set_tile",
+    "dr_ctx_create", "dr_ctx_destroy", "dr_geometry_init", "dr_geometry_path",
+    "dr_geometry_free", "dr_set_tile",
     "dr_autotune", "dr_reconstruct", "dr_reconstruct_f64", "dr_debug_plan", "dr_enable_timing",
     "dr_last_timing", "dr_batch_create", "dr_batch_run", "dr_batch_tile", "dr_batch_free",
     "dr_submit", "dr_poll", "dr_wait", "dr_ctx_stats", "dr_last_error",
@@ -95,6 +97,7 @@ def load(path: Optional[str] = None):
         "dr_ctx_create": [ctypes.c_int, sz, P(vp)],
         "dr_ctx_destroy": [vp],
         "dr_geometry_init": [vp, P(dr_detector), P(dr_wire), P(dr_depth_grid), P(vp)],
+        "dr_geometry_path": [vp, P(i32)],
         "dr_geometry_free": [vp],
         "dr_set_tile": [vp, P(dr_tile_config)],
         "dr_autotune": [vp, vp, vp, P(dr_tile_config)],
@@ -207,6 +210,13 @@ def dr_geometry_init(ctx: int, detector, wire, grid) -> int:
     del keep_d, keep_w
     _check(rc)
     return h.value
+
+
+def dr_geometry_path(geom: int) -> int:
+    """DR_PATH_ROWS or DR_PATH_PIXELS."""
+    v = ctypes.c_int32()
+    _check(load().dr_geometry_path(geom, ctypes.byref(v)))
+    return v.value
 
 
 def dr_geometry_free(geom: int) -> None:

@@ -187,13 +187,19 @@ def test_geometry_errors(dr, ctx):
         dr.dr_geometry_init(ctx, s.detector, inside, s.grid)
     assert e.value.code == dr.DR_E_INVAL
     tilted = synth.Detector(8, 4, s.detector.origin, np.array([200.0, 0.0, 1.0]), s.detector.v)
-    with pytest.raises(dr.DRError) as e:
-        dr.dr_geometry_init(ctx, tilted, s.wire, s.grid)
-    assert e.value.code == dr.DR_E_UNSUPPORTED
+    g = dr.dr_geometry_init(ctx, tilted, s.wire, s.grid)  # per-pixel path, accepted
+    assert dr.dr_geometry_path(g) == dr.DR_PATH_PIXELS
+    dr.dr_geometry_free(g)
+    for axis in ([0.0, 0.0, 1.0], [0.0, 0.0, -2.0], [0.0, 0.0, 0.0]):  # along the beam, zero
+        w_axis = synth.Wire(radius=26.0, centers=s.wire.centers, axis=np.array(axis))
+        with pytest.raises(dr.DRError) as e:
+            dr.dr_geometry_init(ctx, s.detector, w_axis, s.grid)
+        assert e.value.code == dr.DR_E_INVAL, axis
+    # axis along y: eta = -x, negative for half the detector (wire not between)
     w_axis = synth.Wire(radius=26.0, centers=s.wire.centers, axis=np.array([0.0, 1.0, 0.0]))
     with pytest.raises(dr.DRError) as e:
         dr.dr_geometry_init(ctx, s.detector, w_axis, s.grid)
-    assert e.value.code == dr.DR_E_UNSUPPORTED
+    assert e.value.code == dr.DR_E_INVAL
 
 
 def test_all_zero_outside_sweep(dr, ctx):
