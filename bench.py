@@ -33,8 +33,12 @@ def log(*a):
 
 
 def kernel_source_digest() -> str:
-    with open(os.path.join(ROOT, "paper_2201_13309_amd", "csrc", "dr_kernels.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Digest of the sources the row kernel is compiled from."""
+    h = hashlib.sha256()
+    for name in ("dr_internal.h", "dr_device.h", "dr_tiles_rows.hip"):
+        with open(os.path.join(ROOT, "paper_2201_13309_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def algorithmic_bytes(nx, ny, n_steps, n_bins):
@@ -57,7 +61,7 @@ def measured_traffic(digest: str, shape):
         if ":" in line:
             k, v = line.split(":", 1)
             d[k.strip()] = v.strip()
-    want = "rows_f32_kernel<%d, %d, %d>" % tuple(shape[:3])
+    want = "rows_f32_kernel<%d, %d, %d, false>" % tuple(shape[:3])
     if d.get("kernel_source_sha256_16") != digest or want not in d.get("kernel", ""):
         return None
     return float(d["hbm_bytes_per_launch"])
@@ -82,6 +86,40 @@ def cpu_baseline(scan, target_s: float):
     return {"value": work / spent, "unit": UNIT, "cores": cores, "kind": "oracle",
             "sample": f"{what} {det.nx}x{det.ny}x{N}-step scan in 128-row slabs "
                       f"({work:.3e} pixel-wire-steps, FP64, {spent:.1f} s)"}
+
+
+def run_per_pixel(torch, synth, dr, ctx, s, dev, out, tot, stream, steps: int):
+    """The per-pixel path at the same size: the detector's columns tilted 0.3
+    degrees out of the x axis (u gains a z part), so no two pixels of a row
+    share a projected position.  The images are the flat-detector stack,
+    reinterpreted; timing does not depend on their content."""
+    d = s.detector
+    det = synth.Detector(d.nx, d.ny, d.origin, np.array([d.u[0], 0.0, 1.0]), d.v)
+    g = dr.dr_geometry_init(ctx, det, s.wire, s.grid)
+    try:
+        assert dr.dr_geometry_path(g) == dr.DR_PATH_PIXELS
+        dr.dr_reconstruct(g, dev, True, out, tot, stream)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(steps):
+            dr.dr_reconstruct(g, dev, True, out, tot, stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / steps
+        dr.dr_enable_timing(g, True)
+        dr.dr_reconstruct(g, dev, True, out, tot, stream)
+        kms, _ = dr.dr_last_timing(g)
+        dr.dr_enable_timing(g, False)
+    finally:
+        dr.dr_geometry_free(g)
+    work = d.nx * d.ny * s.wire.n_steps
+    log(f"per-pixel path: {ms:.2f} ms/step")
+    return {"value": work / (ms * 1e-3), "unit": UNIT, "ms_per_step": ms, "kernel_ms": kms,
+            "kernel": "pixels_kernel", "steps": steps,
+            "geometry": "detector columns tilted 0.3 deg out of x (u = (200, 0, 1) um): "
+                        "positions computed per pixel in FP64 on the fly"}
 
 
 def run_batched(torch, synth, dr, ctx, steps: int):
@@ -243,6 +281,7 @@ def main():
     ap.add_argument("--no-e2e", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-per-pixel", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-rate", type=float, default=20.0)
@@ -364,6 +403,9 @@ def main():
                                 "note": "pinned host images streamed in row slabs; PCIe-bound"}
         log(f"end-to-end (PCIe) {dt * 1e3:.1f} ms")
     dr.dr_geometry_free(g)
+    if not args.no_per_pixel:
+        result["per_pixel"] = run_per_pixel(torch, synth, dr, ctx, s, dev, out, tot, stream,
+                                            max(2, args.steps // 2))
     del dev, out
     torch.cuda.empty_cache()
     if not args.no_batch and args.workload == "config3":

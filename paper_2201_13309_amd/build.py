@@ -23,7 +23,9 @@ ARCH = os.environ.get("PYTORCH_ROCM_ARCH", "gfx950").split(";")[0] or "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall", f"-I{INCLUDE}", f"-I{CSRC}"]
 DEVICE = ["-x", "hip", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
           "-packed-fp32-ops"]
-SOURCES = [("dr_kernels.hip", True), ("dr_runtime.cpp", False), ("dr_serve.cpp", False)]
+SOURCES = [("dr_tiles_rows.hip", True), ("dr_tiles_rows_add.hip", True),
+           ("dr_tiles_batch.hip", True), ("dr_tiles_batch_add.hip", True),
+           ("dr_kernels.hip", True), ("dr_runtime.cpp", False), ("dr_serve.cpp", False)]
 
 
 def _compile(src: str, device: bool) -> str:

@@ -99,8 +99,15 @@ hipError_t launch_build_plans(const GeomArgs& g, const PlanTables& t, int side, 
 hipError_t launch_unify_classes(int8_t* a, int8_t* b, int ny, hipStream_t s);
 hipError_t launch_rows_f32(const TileCfg& t, const ScanArgs& a, hipStream_t s);
 hipError_t launch_rows_f64(const ScanArgs& a, hipStream_t s);
-hipError_t launch_batch_f32(const TileCfg& t, const BatchArgs& b, int groups, hipStream_t s);
+// add: every scan of the launch is the second pass of two (pass 2)
+hipError_t launch_batch_f32(const TileCfg& t, const BatchArgs& b, bool add, int groups,
+                            hipStream_t s);
 hipError_t launch_reset_counter(unsigned long long* counter, hipStream_t s);
+// the launch-shape dispatch of each template set, one translation unit each
+hipError_t launch_rows_f32_single(const TileCfg& t, const ScanArgs& a, dim3 grid, hipStream_t s);
+hipError_t launch_rows_f32_add(const TileCfg& t, const ScanArgs& a, dim3 grid, hipStream_t s);
+hipError_t launch_batch_f32_single(const TileCfg& t, const BatchArgs& a, dim3 grid, hipStream_t s);
+hipError_t launch_batch_f32_add(const TileCfg& t, const BatchArgs& a, dim3 grid, hipStream_t s);
 // totals[b] = sum over slots of partials[slot][b] (FP64 sum, stored as T)
 hipError_t launch_totals_f32(const float* partials, int64_t slots, int n_bins, double* work,
                              int work_rows, float* totals, hipStream_t s);

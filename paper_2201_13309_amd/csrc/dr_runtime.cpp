@@ -820,7 +820,8 @@ static dr_status batch_enqueue(dr_batch b, hipStream_t s)
                         : std::max<int64_t>(1, std::min<int64_t>((int64_t)b->ctx->cus * b->gpc,
                                                                  ba.total_tiles));
         DR_HIP(launch_reset_counter(ba.counter, s));
-        DR_HIP(launch_batch_f32(b->tile, ba, (int)std::min<int64_t>(groups, INT32_MAX), s));
+        DR_HIP(launch_batch_f32(b->tile, ba, launch == 1,
+                                (int)std::min<int64_t>(groups, INT32_MAX), s));
     }
     for (size_t i = 0; i < b->items.size(); ++i) {
         if (!b->items[i].totals) continue;

@@ -300,7 +300,8 @@ struct Scheduler {
             const TileCfg t{kPpl[gi % 3], 4, 16};
             const int groups = (int)std::max<int64_t>(1, std::min<int64_t>(ctx->cus * 2, tiles[gi]));
             e = launch_reset_counter(ba.counter, s);
-            if (e == hipSuccess) e = launch_batch_f32(t, ba, groups, s);
+            // groups 3..5 hold second passes, which add onto the first
+            if (e == hipSuccess) e = launch_batch_f32(t, ba, gi >= 3, groups, s);
             stats.tiles_launched += (uint64_t)tiles[gi];
         }
         for (Request* r : finishing) {

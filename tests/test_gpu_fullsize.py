@@ -133,3 +133,42 @@ def test_config3_sampled_and_invariants(dr, ctx):
         dr.dr_geometry_free(g)
         del dev, out
         torch.cuda.empty_cache()
+
+
+def test_config3_per_pixel_path_sampled(dr, ctx):
+    """2048^2 px x 1001 steps x 1001 bins with the detector's columns tilted
+    out of the x axis: the per-pixel path, sampled pixels against the oracle
+    (FP32 tolerance, bit-exact positions, bit-exact FP64 instance)."""
+    import torch
+    s = synth.config3(render_now=False)
+    d = s.detector
+    s.detector = synth.Detector(d.nx, d.ny, d.origin, np.array([d.u[0], 0.0, 1.0]), d.v)
+    host = _render_pinned(s)
+    s.images = host.numpy().view(np.uint16)
+    det, grid, N = s.detector, s.grid, s.wire.n_steps
+    nx, ny, B = det.nx, det.ny, grid.n_bins
+    g, dev, out, tot = _run_like_bench(dr, ctx, s, host)
+    try:
+        assert dr.dr_geometry_path(g) == dr.DR_PATH_PIXELS
+        assert not torch.isnan(out).any().item(), "unwritten output elements"
+        pix = _sample_pixels(nx, ny, 2000, 34)
+        ref, bins_ref, u_ref = oracle.reconstruct_pixels(s, pix, want_bins=True, want_u=True)
+        got = out.view(B, -1)[:, torch.from_numpy(pix).to("cuda")].T.cpu().numpy()
+        series = s.images.reshape(N, -1)[:, pix].T
+        scale = np.abs(np.diff(series.astype(np.int64), axis=1)).sum(1).astype(np.float64)
+        assert np.all(np.abs(got.astype(np.float64) - ref) <= REL_TOL * scale[:, None])
+        bins, u = dr.dr_debug_plan(g, pix, N)
+        assert np.array_equal(bins, bins_ref)
+        assert np.array_equal(u.view(np.int64), u_ref.view(np.int64))
+        del out
+        torch.cuda.empty_cache()
+        out64 = torch.empty((B, ny, nx), dtype=torch.float64, device="cuda")
+        dr.dr_reconstruct_f64(g, dev, out64, None, torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        got64 = out64.view(B, -1)[:, torch.from_numpy(pix).to("cuda")].T.cpu().numpy()
+        assert np.array_equal(got64.view(np.int64), ref.view(np.int64))
+        del out64
+    finally:
+        dr.dr_geometry_free(g)
+        del dev
+        torch.cuda.empty_cache()
