@@ -53,6 +53,10 @@ def load(path: Optional[str] = None):
         lib.oracle_reconstruct_pixels.argtypes = [i32, i32, p, p, p, p, d, p, i32, p, i32, d, d,
                                                   i32, p, p, p, i64, p, p, p, i32]
         lib.oracle_reconstruct_pixels.restype = i32
+        lib.oracle_activity.argtypes = [p, i32, i64, p]
+        lib.oracle_activity.restype = None
+        lib.oracle_select_top.argtypes = [p, i64, i64, p]
+        lib.oracle_select_top.restype = i32
         _libs[path] = lib
     return _libs[path]
 
@@ -163,3 +167,25 @@ def reconstruct_pixels(scan, pixels, images: Optional[np.ndarray] = None,
     if rc != 0:
         raise OracleError(f"oracle_reconstruct_pixels failed ({rc})")
     return out, bins, upos
+
+
+def activity(images: np.ndarray, lib=None) -> np.ndarray:
+    """Pixel activity sum_k |I_k - I_{k+1}| of a stack [N][ny][nx] (or
+    [N][npix]), flat over pixels, uint64."""
+    im = np.ascontiguousarray(images, dtype=np.uint16)
+    N = im.shape[0]
+    npix = int(np.prod(im.shape[1:]))
+    out = np.empty(npix, dtype=np.uint64)
+    (lib or load()).oracle_activity(_p(im), N, npix, _p(out))
+    return out
+
+
+def select_top(act: np.ndarray, k: int, lib=None) -> np.ndarray:
+    """The k pixels of largest activity, ties to the lower index, in
+    increasing index order (int64)."""
+    a = np.ascontiguousarray(act, dtype=np.uint64)
+    out = np.empty(max(int(k), 1), dtype=np.int64)
+    rc = (lib or load()).oracle_select_top(_p(a), a.shape[0], int(k), _p(out))
+    if rc != 0:
+        raise OracleError(f"oracle_select_top failed ({rc})")
+    return out[:int(k)].copy()

@@ -46,6 +46,12 @@
  *              len = hi - lo; parts outside [0, n_bins) are dropped; a
  *              zero-length interval puts dI_k into bin floor(lo).
  *   totals     tot[b] = sum over pixels of out[b][p].
+ *   selection  (the paper's second experiment processes a percentage of the
+ *              pixels, Sec. IV, without stating which; the reading used
+ *              here): the activity of pixel p is A_p = sum_k |I_k - I_{k+1}|
+ *              over its N samples, and the top-k selection keeps the k
+ *              pixels of largest A_p, ties going to the lower pixel index,
+ *              listed in increasing pixel index.
  *
  * Every operation is one IEEE binary64 operation in the order written; build
  * with -ffp-contract=off.  Pins (tests/test_oracle_*.py): the tangent depth
@@ -377,4 +383,48 @@ int oracle_reconstruct_pixels(int nx, int ny, const double* origin, const double
     }
     free(wyz);
     return status;
+}
+
+/* Activity of every pixel of a full stack images[N][npix]:
+ * act[p] = sum_k |I_k - I_{k+1}| (exact in 64-bit integers). */
+void oracle_activity(const uint16_t* images, int n_steps, int64_t npix, uint64_t* act)
+{
+    for (int64_t p = 0; p < npix; ++p) {
+        uint64_t a = 0;
+        for (int k = 0; k + 1 < n_steps; ++k) {
+            int64_t d = (int64_t)images[(int64_t)k * npix + p] -
+                        (int64_t)images[(int64_t)(k + 1) * npix + p];
+            a += (uint64_t)(d < 0 ? -d : d);
+        }
+        act[p] = a;
+    }
+}
+
+/* Order of the selection rule: larger activity first, then lower index. */
+static const uint64_t* g_sel_act;
+static int sel_cmp(const void* x, const void* y)
+{
+    int64_t a = *(const int64_t*)x, b = *(const int64_t*)y;
+    if (g_sel_act[a] != g_sel_act[b]) return g_sel_act[a] > g_sel_act[b] ? -1 : 1;
+    return a < b ? -1 : (a > b ? 1 : 0);
+}
+static int idx_cmp(const void* x, const void* y)
+{
+    int64_t a = *(const int64_t*)x, b = *(const int64_t*)y;
+    return a < b ? -1 : (a > b ? 1 : 0);
+}
+
+/* The k pixels of largest activity (ties: lower index), written to list[k]
+ * in increasing pixel index.  Not thread-safe (qsort comparator state). */
+int oracle_select_top(const uint64_t* act, int64_t npix, int64_t k, int64_t* list)
+{
+    if (npix < 0 || k < 0 || k > npix) return ORACLE_EINVAL;
+    int64_t* order = (int64_t*)malloc(sizeof(int64_t) * (size_t)(npix > 0 ? npix : 1));
+    for (int64_t p = 0; p < npix; ++p) order[p] = p;
+    g_sel_act = act;
+    qsort(order, (size_t)npix, sizeof(int64_t), sel_cmp);
+    for (int64_t i = 0; i < k; ++i) list[i] = order[i];
+    qsort(list, (size_t)k, sizeof(int64_t), idx_cmp);
+    free(order);
+    return ORACLE_OK;
 }

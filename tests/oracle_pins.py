@@ -471,9 +471,62 @@ def pin_tilted_axis_brute_force(lib):
             assert np.all(np.abs(out[:, 0, 0] - want) <= tol + 1e-6), (edge, ax)
 
 
+
+def pin_activity(lib):
+    """Pixel activity sum_k |I_k - I_{k+1}|: a monotone series gives
+    |I_last - I_first|; a constant series 0; a sawtooth of height h over N
+    samples (N-1)*h, beyond 32 bits for a long full-range sawtooth; reversing
+    the steps or adding an offset leaves it unchanged."""
+    rng = np.random.default_rng(41)
+    N, npix = 37, 50
+    inc = np.sort(rng.integers(0, 60000, (N, npix)), axis=0).astype(np.uint16)
+    dec = inc[::-1].copy()
+    a_inc = oracle.activity(inc, lib=lib)
+    a_dec = oracle.activity(dec, lib=lib)
+    expect = inc[-1].astype(np.uint64) - inc[0].astype(np.uint64)
+    assert np.array_equal(a_inc, expect) and np.array_equal(a_dec, expect)
+    const = np.full((N, 3), 1234, dtype=np.uint16)
+    assert np.all(oracle.activity(const, lib=lib) == 0)
+    n_long = 70001
+    saw = np.zeros((n_long, 2), dtype=np.uint16)
+    saw[1::2, 0] = 65535
+    saw[1::2, 1] = 7
+    a = oracle.activity(saw, lib=lib)
+    assert int(a[0]) == (n_long - 1) * 65535 and int(a[1]) == (n_long - 1) * 7
+    noisy = rng.integers(0, 30000, (N, npix)).astype(np.uint16)
+    a0 = oracle.activity(noisy, lib=lib)
+    assert np.array_equal(oracle.activity(noisy[::-1].copy(), lib=lib), a0)
+    assert np.array_equal(oracle.activity(noisy + np.uint16(20000), lib=lib), a0)
+
+
+def pin_select_top(lib):
+    """Top-k selection: k entries in increasing index order such that every
+    selected pixel ranks before every unselected one (larger activity, or
+    equal activity and lower index); k = 0 and k = n are the empty and full
+    lists."""
+    rng = np.random.default_rng(42)
+    for n, hi in ((1, 3), (17, 4), (200, 6), (1000, 1000)):
+        act = rng.integers(0, hi, n).astype(np.uint64)
+        for k in sorted({0, 1, n // 3, n // 2, n - 1, n} - {-1}):
+            if k < 0:
+                continue
+            sel = oracle.select_top(act, k, lib=lib)
+            assert sel.shape == (k,)
+            assert np.all(np.diff(sel) > 0)
+            if k in (0, n):
+                assert np.array_equal(sel, np.arange(k))
+            chosen = np.zeros(n, dtype=bool)
+            chosen[sel] = True
+            if 0 < k < n:
+                p = np.nonzero(chosen)[0]
+                q = np.nonzero(~chosen)[0]
+                ap, aq = act[p][:, None], act[q][None, :]
+                ranks_before = (ap > aq) | ((ap == aq) & (p[:, None] < q[None, :]))
+                assert ranks_before.all(), (n, k)
+
 ALL_PINS = [
     pin_closed_form_level, pin_zero_radius, pin_bisection, pin_mirror, pin_edge_sign,
     pin_hand_profiles, pin_conservation_random, pin_conservation_scan, pin_brute_force,
     pin_planted_sources, pin_poisson_recovery, pin_tilted_axis_bisection,
-    pin_tilted_axis_brute_force,
+    pin_tilted_axis_brute_force, pin_activity, pin_select_top,
 ]

@@ -57,6 +57,13 @@ MUTANTS = [
      "if (bd >= 0.0 && bd < (double)n_bins) out[(int64_t)bd * stride] -= dI * w;"),
     ("lo_hi_swap", "double lo = u[k] < u[k + 1] ? u[k] : u[k + 1];",
      "double lo = u[k];"),
+    ("activity_no_abs", "a += (uint64_t)(d < 0 ? -d : d);", "a += (uint64_t)d;"),
+    ("activity_drops_last", "for (int k = 0; k + 1 < n_steps; ++k) {",
+     "for (int k = 0; k + 2 < n_steps; ++k) {"),
+    ("select_ascending", "return g_sel_act[a] > g_sel_act[b] ? -1 : 1;",
+     "return g_sel_act[a] < g_sel_act[b] ? -1 : 1;"),
+    ("select_ties_high", "    return a < b ? -1 : (a > b ? 1 : 0);\n}\nstatic int idx_cmp",
+     "    return a > b ? -1 : (a < b ? 1 : 0);\n}\nstatic int idx_cmp"),
 ]
 
 
