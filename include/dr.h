@@ -45,7 +45,8 @@
  *
  * Threads: a dr_ctx may be used from several host threads; calls that enqueue
  * work on one dr_geom must not overlap in time on different streams, because
- * each geometry owns one scratch area (per-wave partial sums of the totals).
+ * each geometry owns one scratch area (per-wave partial sums of the totals);
+ * the same holds for calls on one pixel list.
  */
 #ifndef DR_H
 #define DR_H
@@ -82,6 +83,7 @@ typedef int32_t dr_status;
 typedef struct dr_ctx_s* dr_ctx;     /* one GPU: streams, slab buffers, scheduler */
 typedef struct dr_geom_s* dr_geom;   /* device-resident tables of one geometry */
 typedef struct dr_batch_s* dr_batch; /* a captured, tuned launch over many scans */
+typedef struct dr_list_s* dr_list;   /* a sorted pixel list of one geometry, tiled by row */
 
 /* Detector: pixel (j, i) centre = (origin + i*u) + j*v (um), any orientation.
  * pixel_xyz, when not NULL, is a host array [ny][nx][3] of explicit centres
@@ -253,6 +255,65 @@ dr_status dr_batch_run(dr_batch batch, void* stream);
 dr_status dr_batch_tile(dr_batch batch, dr_tile_config* tile);
 
 dr_status dr_batch_free(dr_batch batch);
+
+/* ---------------------------------------------------------- pixel lists */
+
+/* Reconstructing a chosen part of the detector (the paper's second
+ * experiment, Sec. IV, processes a percentage of the pixels without saying
+ * which).  Selection rule: the activity of pixel p is
+ * A_p = sum_k |I_k - I_{k+1}| over its samples, and the top-k list keeps the k
+ * pixels of largest A_p, ties going to the lower index.  Every list is held
+ * on the device in increasing pixel index (p = j*nx + i) and cut into tiles of
+ * at most 256 entries inside one detector row.  Results for a listed pixel are
+ * bitwise those of dr_reconstruct / dr_reconstruct_f64 for that pixel. */
+
+/* Image layouts for list reconstruction. */
+#define DR_LAYOUT_FULL 0 /* full frames uint16 [n_steps][ny][nx], gathered by pixel */
+#define DR_LAYOUT_LIST 1 /* compact uint16 [n_steps][n], column e = list entry e */
+
+/* activity_dev[p] = A_p for every pixel of a device stack [n_steps][ny][nx]
+ * (uint64, exact).  Asynchronous on `stream` (NULL = the HIP null stream);
+ * one pass over the stack.  Errors: DR_E_INVAL (NULL or misaligned). */
+dr_status dr_pixel_activity(dr_geom geom, const uint16_t* images_dev, uint64_t* activity_dev,
+                            void* stream);
+
+/* The top-k list from device activities [nx*ny] (0 <= k <= nx*ny), selected
+ * on the device on the context's stream: the activities must be complete
+ * (synchronize the stream that computed them).  Synchronous; the library owns
+ * *out until dr_list_free.
+ * Errors: DR_E_INVAL (NULL, k out of range, misaligned), DR_E_NOMEM. */
+dr_status dr_select_top(dr_geom geom, const uint64_t* activity_dev, int64_t k, dr_list* out);
+
+/* A list from the caller's pixel indices (host or device array of n int64,
+ * strictly increasing, each in [0, nx*ny)), copied and checked on the device.
+ * Synchronous.  Errors: DR_E_INVAL for an index out of range or an order that
+ * is not strictly increasing. */
+dr_status dr_list_create(dr_geom geom, const int64_t* pixels, int64_t n, int pixels_on_device,
+                         dr_list* out);
+
+dr_status dr_list_size(dr_list list, int64_t* n);
+
+/* Copy the list's n pixel indices to a host array (synchronous). */
+dr_status dr_list_pixels(dr_list list, int64_t* pixels_host);
+
+/* Free a list (waits for the device).  Lists must be freed before their
+ * geometry (dr_geometry_free returns DR_E_BUSY while any is alive). */
+dr_status dr_list_free(dr_list list);
+
+/* Reconstruct the listed pixels: out float [n_bins][n] on the device, column
+ * e for list entry e, every element written; totals float [n_bins] (or NULL)
+ * = sum of out over the list.  images: device, either layout; or host
+ * (pinned for overlap) in DR_LAYOUT_LIST only, streamed in runs of whole
+ * tiles through the context's two slab buffers, so the bytes sent over PCIe
+ * are n/(nx*ny) of a full stack.  Edges as set for the geometry.  Errors:
+ * DR_E_INVAL (NULL, misaligned, unknown layout, host images in full layout). */
+dr_status dr_reconstruct_list(dr_list list, const uint16_t* images, int32_t layout,
+                              int images_on_device, float* out, float* totals, void* stream);
+
+/* FP64 instance of dr_reconstruct_list (device images): out double
+ * [n_bins][n], in the oracle's operation order, bit for bit. */
+dr_status dr_reconstruct_list_f64(dr_list list, const uint16_t* images_dev, int32_t layout,
+                                  double* out, double* totals, void* stream);
 
 /* ---------------------------------------------------------------- serving */
 

@@ -366,19 +366,83 @@ struct PartialWindow {
     }
 };
 
+// Where the lanes of one tile read and write: uniform bases plus 32-bit lane
+// offsets.  A lane's PPL pixels hold step k at ibase[k*istep + ioff + q] and
+// bin b at obase[b*plane + ooff + q]; `part` is the wave's partial-total row.
+template <typename Acc>
+struct TileAddr {
+    const uint16_t* ibase;
+    int64_t istep;
+    uint32_t ioff;
+    Acc* obase;
+    int64_t plane;
+    uint32_t ooff;
+    bool act;   // the lane holds pixels (lanes past the end read valid data, never store)
+    Acc* part;  // null: no totals
+};
+
+// Tile `tile` of detector row `row`: PPL adjacent pixels per lane.
+template <typename Acc, int PPL, int WAVES>
+__device__ __forceinline__ TileAddr<Acc> row_tile_addr(const ScanArgs& a, int row, int tile)
+{
+    constexpr int TW = 64 * WAVES * PPL;
+    const int tid = threadIdx.x, wave = tid >> 6;
+    const int col0 = tile * TW + tid * PPL;
+    TileAddr<Acc> t;
+    t.act = col0 < a.nx;
+    t.ibase = a.img + (int64_t)(row - a.row_base) * a.img_row;
+    t.istep = a.img_step;
+    t.ioff = t.act ? (uint32_t)col0 : 0u;
+    t.obase = (Acc*)a.out + (int64_t)row * a.nx;
+    t.plane = a.out_plane;
+    t.ooff = (uint32_t)col0;
+    t.part = a.partials ? (Acc*)a.partials +
+                              ((int64_t)(row * a.tiles_per_row + tile) * WAVES + wave) * a.n_bins
+                        : nullptr;
+    return t;
+}
+
+// Tile t of a pixel list: entries [tile_start, tile_start + tile_count), all
+// in one detector row, one pixel per lane; the output is [n_bins][n] in list
+// order.  Images are full frames (gathered by pixel) or compact [N][entries]
+// in list order, the buffer holding entries from entry_base on.
+template <typename Acc, int WAVES>
+__device__ __forceinline__ TileAddr<Acc> list_tile_addr(const ScanArgs& a, const ListArgs& l,
+                                                        int64_t t, int row)
+{
+    const int tid = threadIdx.x, wave = tid >> 6;
+    const int64_t e0 = l.tile_start[t];
+    TileAddr<Acc> ta;
+    ta.act = tid < l.tile_count[t];
+    const int64_t e = ta.act ? e0 + tid : e0;
+    if (l.compact) {
+        ta.ibase = a.img;
+        ta.ioff = (uint32_t)(e - l.entry_base);
+    } else {
+        ta.ibase = a.img + (int64_t)(row - a.row_base) * a.img_row;
+        ta.ioff = (uint32_t)(l.pixels[e] - (int64_t)row * a.nx);
+    }
+    ta.istep = a.img_step;
+    ta.obase = (Acc*)a.out;
+    ta.plane = a.out_plane;
+    ta.ooff = (uint32_t)(e0 + tid);
+    ta.part = a.partials ? (Acc*)a.partials + (t * WAVES + wave) * a.n_bins : nullptr;
+    return ta;
+}
+
 // Non-monotone rows: zero the tile's bins, then read-modify-write every
 // contribution in step order (each lane touches only its own pixels).
 template <typename Acc, int PPL, int WAVES>
-__device__ __forceinline__ void process_tile_generic(const ScanArgs& a, int row, int tile, PlanLds<Acc>& L)
+__device__ __forceinline__ void process_tile_generic(const ScanArgs& a, int row,
+                                                     const TileAddr<Acc>& ta, PlanLds<Acc>& L)
 {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    constexpr int TW = 64 * WAVES * PPL;
-    const int col0 = tile * TW + tid * PPL;
-    const bool act = col0 < a.nx;
+    const int tid = threadIdx.x, lane = tid & 63;
+    (void)tid;
+    const bool act = ta.act;
     const int N = a.n_steps, B = a.n_bins, nint = N - 1;
-    const uint16_t* ip = a.img + (int64_t)(row - a.row_base) * a.img_row + col0;
-    Acc* op = (Acc*)a.out + (int64_t)row * a.nx + col0;
-    const int64_t plane = a.out_plane;
+    const uint16_t* ip = ta.ibase + ta.ioff;
+    Acc* op = ta.obase + ta.ooff;
+    const int64_t plane = ta.plane;
     if (act && a.pass != 2)  // the second pass adds onto the first pass's output
         for (int b = 0; b < B; ++b)
 #pragma unroll
@@ -396,8 +460,8 @@ __device__ __forceinline__ void process_tile_generic(const ScanArgs& a, int row,
             const int bh = bl + nb - 1;
 #pragma unroll
             for (int q = 0; q < PPL; ++q) {
-                const Acc dI = (Acc)((int)ip[(int64_t)k * a.img_step + q] -
-                                     (int)ip[(int64_t)(k + 1) * a.img_step + q]);
+                const Acc dI = (Acc)((int)ip[(int64_t)k * ta.istep + q] -
+                                     (int)ip[(int64_t)(k + 1) * ta.istep + q]);
                 for (int b = bl; b <= bh; ++b) {
                     const Acc f = (b == bl) ? f0 : ((b == bh) ? f1 : fm);
                     Acc* o = op + (int64_t)b * plane + q;
@@ -406,11 +470,11 @@ __device__ __forceinline__ void process_tile_generic(const ScanArgs& a, int row,
             }
         }
     }
-    if (a.partials) {
+    if (ta.part) {
         // partial totals of the final values; a first pass of two leaves them
         // to the second (a row is generic in both passes or in neither)
         PartialWindow<Acc> pwin;
-        pwin.row = (Acc*)a.partials + ((int64_t)(row * a.tiles_per_row + tile) * WAVES + wave) * B;
+        pwin.row = ta.part;
         pwin.B = B;
         if (a.pass != 1) {
             for (int b = 0; b < B; ++b) {
@@ -431,27 +495,26 @@ __device__ __forceinline__ void process_tile_generic(const ScanArgs& a, int row,
 // registers, each touched bin stored once as soon as the edge has passed it,
 // untouched bins zeroed after the last load.
 template <typename Acc, int PPL, int WAVES, int PF, bool NB2, bool ADD>
-__device__ __forceinline__ void process_tile_mono(const ScanArgs& a, int row, int tile,
-                                                  PlanLds<Acc>& L, int cls)
+__device__ __forceinline__ void process_tile_mono(const ScanArgs& a, int row,
+                                                  const TileAddr<Acc>& ta, PlanLds<Acc>& L,
+                                                  int cls)
 {
     using V = typename U16V<PPL>::T;
-    constexpr int TW = 64 * WAVES * PPL;
     const int dir = ((cls & 3) == kRowIncreasing) ? 1 : -1;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int col0 = tile * TW + tid * PPL;
-    const bool act = col0 < a.nx;
+    const int tid = threadIdx.x, lane = tid & 63;
+    (void)tid;
+    const bool act = ta.act;
     const int N = a.n_steps, B = a.n_bins, nint = N - 1;
-    // uniform 64-bit row bases plus 32-bit lane offsets; lanes past the row end
-    // read the row's first pixels and never store
-    const uint16_t* irow = a.img + (int64_t)(row - a.row_base) * a.img_row;
-    const uint32_t ioff = act ? (uint32_t)col0 : 0u;
-    Acc* orow = (Acc*)a.out + (int64_t)row * a.nx;
-    const uint32_t ooff = (uint32_t)col0;
-    const int64_t plane = a.out_plane;
-    const int64_t istep = a.img_step;
+    // uniform 64-bit bases plus 32-bit lane offsets; lanes past the end read
+    // valid pixels and never store
+    const uint16_t* irow = ta.ibase;
+    const uint32_t ioff = ta.ioff;
+    Acc* orow = ta.obase;
+    const uint32_t ooff = ta.ooff;
+    const int64_t plane = ta.plane;
+    const int64_t istep = ta.istep;
     PartialWindow<Acc> pwin;
-    if (a.partials)
-        pwin.row = (Acc*)a.partials + ((int64_t)(row * a.tiles_per_row + tile) * WAVES + wave) * B;
+    pwin.row = ta.part;
     pwin.B = B;
 
     auto load = [&](int k) -> V {
@@ -581,16 +644,16 @@ __device__ __forceinline__ void process_tile_mono(const ScanArgs& a, int row, in
 // ADD: the scan's pass is 2 (compile-time, so that a single pass carries no
 // code for adding onto an earlier output)
 template <typename Acc, int PPL, int WAVES, int PF, bool ADD>
-__device__ __forceinline__ void process_tile(const ScanArgs& a, int row, int tile,
+__device__ __forceinline__ void process_tile(const ScanArgs& a, int row, const TileAddr<Acc>& ta,
                                              PlanLds<Acc>& L)
 {
     const int cls = a.row_class[row];
     if (cls == kRowGeneric)
-        process_tile_generic<Acc, PPL, WAVES>(a, row, tile, L);
+        process_tile_generic<Acc, PPL, WAVES>(a, row, ta, L);
     else if (cls & kRowNarrow)
-        process_tile_mono<Acc, PPL, WAVES, PF, true, ADD>(a, row, tile, L, cls);
+        process_tile_mono<Acc, PPL, WAVES, PF, true, ADD>(a, row, ta, L, cls);
     else  // intervals wider than two bins: rare, a short prefetch suffices
-        process_tile_mono<Acc, PPL, WAVES, (PF < 4 ? PF : 4), false, ADD>(a, row, tile, L, cls);
+        process_tile_mono<Acc, PPL, WAVES, (PF < 4 ? PF : 4), false, ADD>(a, row, ta, L, cls);
 }
 
 template <int PPL, int WAVES, int PF, bool ADD>
@@ -599,7 +662,8 @@ __global__ __launch_bounds__(64 * WAVES) void rows_f32_kernel(ScanArgs a)
     __shared__ PlanLds<float> L;
     const int row = a.row_begin + (int)(blockIdx.x / (unsigned)a.tiles_per_row);
     const int tile = (int)(blockIdx.x % (unsigned)a.tiles_per_row);
-    process_tile<float, PPL, WAVES, PF, ADD>(a, row, tile, L);
+    process_tile<float, PPL, WAVES, PF, ADD>(a, row, row_tile_addr<float, PPL, WAVES>(a, row, tile),
+                                             L);
 }
 
 template <bool ADD>
@@ -608,7 +672,27 @@ __global__ __launch_bounds__(256) void rows_f64_kernel(ScanArgs a)
     __shared__ PlanLds<double> L;
     const int row = a.row_begin + (int)(blockIdx.x / (unsigned)a.tiles_per_row);
     const int tile = (int)(blockIdx.x % (unsigned)a.tiles_per_row);
-    process_tile<double, 1, 4, 4, ADD>(a, row, tile, L);
+    process_tile<double, 1, 4, 4, ADD>(a, row, row_tile_addr<double, 1, 4>(a, row, tile), L);
+}
+
+// Pixel lists: one workgroup per list tile (tiles [tile_first, tile_first +
+// gridDim.x) of the list's table).
+template <int PF, bool ADD>
+__global__ __launch_bounds__(256) void list_f32_kernel(ScanArgs a, ListArgs l)
+{
+    __shared__ PlanLds<float> L;
+    const int64_t t = l.tile_first + blockIdx.x;
+    const int row = l.tile_row[t];
+    process_tile<float, 1, 4, PF, ADD>(a, row, list_tile_addr<float, 4>(a, l, t, row), L);
+}
+
+template <bool ADD>
+__global__ __launch_bounds__(256) void list_f64_kernel(ScanArgs a, ListArgs l)
+{
+    __shared__ PlanLds<double> L;
+    const int64_t t = l.tile_first + blockIdx.x;
+    const int row = l.tile_row[t];
+    process_tile<double, 1, 4, 4, ADD>(a, row, list_tile_addr<double, 4>(a, l, t, row), L);
 }
 
 // Persistent grid: workgroups pull (scan, tile) items until the queue is dry.
@@ -630,7 +714,8 @@ __global__ __launch_bounds__(64 * WAVES) void batch_f32_kernel(BatchArgs b)
         const long long t = item - b.tile_start[si];
         const int row = a.row_begin + (int)(t / a.tiles_per_row);
         const int tile = (int)(t % a.tiles_per_row);
-        process_tile<float, PPL, WAVES, PF, ADD>(a, row, tile, L);
+        process_tile<float, PPL, WAVES, PF, ADD>(a, row,
+                                                 row_tile_addr<float, PPL, WAVES>(a, row, tile), L);
     }
 }
 

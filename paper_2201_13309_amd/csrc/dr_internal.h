@@ -73,6 +73,20 @@ struct GeomArgs {
     double origin[3], u[3], v[3];
 };
 
+// A pixel list as seen by the list kernels: entries sorted by pixel index and
+// cut into tiles of at most 256 entries that lie in one detector row (the
+// per-pixel path ignores the row).
+struct ListArgs {
+    const int64_t* pixels;      // [n] flat pixel indices j*nx + i, increasing
+    const int32_t* tile_row;    // [n_tiles]
+    const int64_t* tile_start;  // [n_tiles] first entry of the tile
+    const int32_t* tile_count;  // [n_tiles] entries in the tile
+    int64_t n;
+    int64_t tile_first;         // first tile of this launch
+    int32_t compact;            // images are [N][entries] in list order, else full frames
+    int64_t entry_base;         // first entry held by a compact image buffer
+};
+
 struct BatchArgs {
     const ScanArgs* scans;     // [n_scans] in work order
     const int64_t* tile_start; // [n_scans + 1] prefix sums of tile counts
@@ -132,6 +146,40 @@ constexpr int kPixelTile = 256;  // pixels per workgroup of the per-pixel path
 // largest partial-total row the per-pixel path sums in LDS (larger rows are
 // summed with device atomics in the partials buffer itself)
 constexpr size_t kPixelLdsBytes = 64 * 1024;
+
+// Top-k selection state, kept on the device between the radix passes:
+// after the last pass `prefix` is the k-th largest activity T, `above` the
+// number of activities above T and `need` how many equal to T are taken.
+struct SelectState {
+    uint64_t prefix, mask;
+    int64_t need, above;
+    unsigned long long hist[256];
+};
+constexpr int64_t kSelectBlock = 4096;  // keys per workgroup of the selection scan
+
+// pixel activity sum_k |I_k - I_{k+1}| of a full stack [N][npix]; vec8: 16-byte
+// loads (img 16-byte aligned and npix % 8 == 0)
+hipError_t launch_activity(const uint16_t* img, int64_t npix, int n_steps, uint64_t* act,
+                           bool vec8, hipStream_t s);
+// the k (1 <= k <= npix) largest activities, ties to the lower index, as an
+// increasing index list; bsum holds ceil(npix / kSelectBlock) entries
+hipError_t launch_select_top(const uint64_t* act, int64_t npix, int64_t k, SelectState* st,
+                             uint64_t* bsum, int64_t* list, hipStream_t s);
+// status bit 1: an entry outside [0, npix); bit 2: not strictly increasing
+hipError_t launch_list_check(const int64_t* list, int64_t n, int64_t npix, int* status,
+                             hipStream_t s);
+// starts[j] = number of entries below j*nx, j = 0..ny
+hipError_t launch_list_rows(const int64_t* list, int64_t n, int nx, int ny, int64_t* starts,
+                            hipStream_t s);
+// pixel-list reconstruction, one workgroup per list tile (tiles l.tile_first
+// .. l.tile_first + n_tiles - 1): per-row plan path and per-pixel path
+hipError_t launch_list_f32(const ScanArgs& a, const ListArgs& l, int64_t n_tiles, hipStream_t s);
+hipError_t launch_list_f64(const ScanArgs& a, const ListArgs& l, int64_t n_tiles, hipStream_t s);
+hipError_t launch_list_pixels_f32(const ScanArgs& a, const GeomArgs& g, int side, double scale,
+                                  const ListArgs& l, int64_t n_tiles, hipStream_t s);
+hipError_t launch_list_pixels_f64(const ScanArgs& a, const GeomArgs& g, int side, double scale,
+                                  const ListArgs& l, int64_t n_tiles, hipStream_t s);
+constexpr int kListTile = 256;  // entries per list tile
 
 constexpr int kPlanChunk = 1024;  // intervals staged in LDS at a time
 constexpr int kTotalsWorkRows = 64;

@@ -220,22 +220,45 @@ __global__ __launch_bounds__(256) void validate_pixels_kernel(GeomArgs g, int* s
 // then; a bin already stored and visited again is read, added to and
 // rewritten, so any sequence of positions is handled).  Partial totals are
 // accumulated per workgroup in LDS and written as one row per workgroup.
+// With a pixel list (l.pixels set) workgroup w takes list tile
+// l.tile_first + w: lane i holds entry tile_start + i, its output goes to
+// column `entry` of [n_bins][n], and its images are gathered from full frames
+// (pixel index) or read from a compact [N][entries] buffer.
 template <typename Acc, int PF>
 __global__ __launch_bounds__(kPixelTile) void pixels_kernel(ScanArgs a, GeomArgs g, int side,
-                                                            double scale)
+                                                            double scale, ListArgs l)
 {
     extern __shared__ __align__(16) unsigned char dyn_lds[];
     const int tid = threadIdx.x;
-    const int row = a.row_begin + (int)(blockIdx.x / (unsigned)a.tiles_per_row);
-    const int tile = (int)(blockIdx.x % (unsigned)a.tiles_per_row);
-    const int col = tile * kPixelTile + tid;
-    const bool act = col < a.nx;
     const int N = a.n_steps, B = a.n_bins;
     const bool add_on = a.pass == 2;
     const bool tot = a.partials != nullptr;
+    bool act;
+    int64_t pixel, slot;              // pixel index; partial-total row of the workgroup
+    const uint16_t* ip;               // the lane's step-0 sample
+    Acc* op;                          // the lane's bin 0
+    if (l.pixels) {
+        const int64_t t = l.tile_first + blockIdx.x;
+        const int64_t e0 = l.tile_start[t];
+        act = tid < l.tile_count[t];
+        const int64_t e = act ? e0 + tid : e0;
+        pixel = l.pixels[e];
+        ip = l.compact ? a.img + (e - l.entry_base) : a.img + pixel;
+        op = (Acc*)a.out + e0 + tid;
+        slot = t;
+    } else {
+        const int row = a.row_begin + (int)(blockIdx.x / (unsigned)a.tiles_per_row);
+        const int tile = (int)(blockIdx.x % (unsigned)a.tiles_per_row);
+        const int col = tile * kPixelTile + tid;
+        act = col < a.nx;
+        pixel = (int64_t)row * a.nx + (act ? col : 0);
+        ip = a.img + (int64_t)(row - a.row_base) * a.img_row + (act ? col : 0);
+        op = (Acc*)a.out + (int64_t)row * a.nx + col;
+        slot = (int64_t)row * a.tiles_per_row + tile;
+    }
     // the workgroup's partial-total row: summed in LDS when it fits, else in
     // place in its own row of the partials buffer
-    Acc* const gp = tot ? (Acc*)a.partials + (int64_t)(row * a.tiles_per_row + tile) * B : nullptr;
+    Acc* const gp = tot ? (Acc*)a.partials + slot * B : nullptr;
     const bool in_lds = (size_t)B * sizeof(Acc) <= kPixelLdsBytes;
     Acc* const ltot = in_lds ? reinterpret_cast<Acc*>(dyn_lds) : gp;
     if (tot)
@@ -244,7 +267,7 @@ __global__ __launch_bounds__(kPixelTile) void pixels_kernel(ScanArgs a, GeomArgs
 
     const Frame f = axis_frame(g);
     double py, pz;
-    pixel_key(g, f, (int64_t)row * a.nx + (act ? col : 0), py, pz);
+    pixel_key(g, f, pixel, py, pz);
     const int s = side ? -leading_sign(g, py, pz) : leading_sign(g, py, pz);
     const double sr = (double)s * g.radius;
     const double e0 = g.first_center - g.width / 2.0;
@@ -253,8 +276,6 @@ __global__ __launch_bounds__(kPixelTile) void pixels_kernel(ScanArgs a, GeomArgs
     const double u_last = edge_position(g, py, pz, N - 1, sr, f.c, e0, invw);
     const int dir = (u_last >= u_first) ? 1 : -1;
 
-    const uint16_t* ip = a.img + (int64_t)(row - a.row_base) * a.img_row + (act ? col : 0);
-    Acc* op = (Acc*)a.out + (int64_t)row * a.nx + col;
     const int64_t plane = a.out_plane;
     auto binp = [&](int bp) { return dir > 0 ? bp : B - 1 - bp; };
 
@@ -455,27 +476,62 @@ hipError_t launch_validate_pixels(const GeomArgs& g, int* d_status, hipStream_t 
 
 template <typename Acc>
 static hipError_t launch_pixels(const ScanArgs& a, const GeomArgs& g, int side, double scale,
-                                hipStream_t s)
+                                const ListArgs* l, int64_t n_tiles, hipStream_t s)
 {
-    const int64_t rows = a.row_end - a.row_begin;
-    if (rows <= 0) return hipSuccess;
+    const int64_t groups = l ? n_tiles : (int64_t)(a.row_end - a.row_begin) * a.tiles_per_row;
+    if (groups <= 0) return hipSuccess;
     const size_t need = (size_t)a.n_bins * sizeof(Acc);
     const size_t lds = (a.partials && need <= kPixelLdsBytes) ? need : 0;
-    hipLaunchKernelGGL((pixels_kernel<Acc, 8>), dim3((unsigned)(rows * a.tiles_per_row)),
-                       dim3(kPixelTile), lds, s, a, g, side, scale);
+    const ListArgs none{};
+    hipLaunchKernelGGL((pixels_kernel<Acc, 8>), dim3((unsigned)groups), dim3(kPixelTile), lds, s,
+                       a, g, side, scale, l ? *l : none);
     return hipGetLastError();
 }
 
 hipError_t launch_pixels_f32(const ScanArgs& a, const GeomArgs& g, int side, double scale,
                              hipStream_t s)
 {
-    return launch_pixels<float>(a, g, side, scale, s);
+    return launch_pixels<float>(a, g, side, scale, nullptr, 0, s);
 }
 
 hipError_t launch_pixels_f64(const ScanArgs& a, const GeomArgs& g, int side, double scale,
                              hipStream_t s)
 {
-    return launch_pixels<double>(a, g, side, scale, s);
+    return launch_pixels<double>(a, g, side, scale, nullptr, 0, s);
+}
+
+hipError_t launch_list_pixels_f32(const ScanArgs& a, const GeomArgs& g, int side, double scale,
+                                  const ListArgs& l, int64_t n_tiles, hipStream_t s)
+{
+    return launch_pixels<float>(a, g, side, scale, &l, n_tiles, s);
+}
+
+hipError_t launch_list_pixels_f64(const ScanArgs& a, const GeomArgs& g, int side, double scale,
+                                  const ListArgs& l, int64_t n_tiles, hipStream_t s)
+{
+    return launch_pixels<double>(a, g, side, scale, &l, n_tiles, s);
+}
+
+hipError_t launch_list_f32(const ScanArgs& a, const ListArgs& l, int64_t n_tiles, hipStream_t s)
+{
+    if (n_tiles <= 0) return hipSuccess;
+    const dim3 grid((unsigned)n_tiles);
+    if (a.pass == 2)
+        hipLaunchKernelGGL((list_f32_kernel<16, true>), grid, dim3(256), 0, s, a, l);
+    else
+        hipLaunchKernelGGL((list_f32_kernel<16, false>), grid, dim3(256), 0, s, a, l);
+    return hipGetLastError();
+}
+
+hipError_t launch_list_f64(const ScanArgs& a, const ListArgs& l, int64_t n_tiles, hipStream_t s)
+{
+    if (n_tiles <= 0) return hipSuccess;
+    const dim3 grid((unsigned)n_tiles);
+    if (a.pass == 2)
+        hipLaunchKernelGGL(list_f64_kernel<true>, grid, dim3(256), 0, s, a, l);
+    else
+        hipLaunchKernelGGL(list_f64_kernel<false>, grid, dim3(256), 0, s, a, l);
+    return hipGetLastError();
 }
 
 hipError_t launch_debug_plan(const GeomArgs& g, const int64_t* pixels, int n, int side,

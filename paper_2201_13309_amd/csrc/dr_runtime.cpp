@@ -437,6 +437,8 @@ dr_status dr_geometry_free(dr_geom g)
     if (!g) return set_error(DR_E_INVAL, "dr_geometry_free: NULL geometry");
     if (g->inflight.load() != 0)
         return set_error(DR_E_BUSY, "dr_geometry_free: serving requests still use it");
+    if (g->lists.load() != 0)
+        return set_error(DR_E_BUSY, "dr_geometry_free: pixel lists still use it");
     DR_HIP(hipSetDevice(g->ctx->device));
     DR_HIP(hipDeviceSynchronize());
     for (int i = 0; i < 3; ++i)

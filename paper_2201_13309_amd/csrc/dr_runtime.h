@@ -94,6 +94,7 @@ struct dr_geom_s {
     bool timing = false, timed = false;
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     std::atomic<int> inflight{0};  // serving requests using this geometry
+    std::atomic<int> lists{0};     // pixel lists built on this geometry
 };
 
 struct dr_batch_s {

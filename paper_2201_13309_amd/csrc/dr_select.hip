@@ -1,0 +1,252 @@
+// Pixel activity and top-k pixel selection (gfx950), for reconstructing a
+// chosen fraction of the detector (the paper's second experiment, Sec. IV,
+// processes a percentage of the pixels without stating which).
+//
+// Rule: the activity of a pixel is A = sum_k |I_k - I_{k+1}| over its samples
+// (exact, 64-bit integers); the top-k selection keeps the k pixels of largest
+// A, ties going to the lower pixel index, listed in increasing pixel index.
+//
+//   activity_kernel    one pass over the stack, 8 pixels per lane (16-byte
+//                      loads) when aligned; HBM-bound.
+//   select_hist/pick   radix select of the k-th largest activity, 8 bits per
+//                      pass from the top, with the state kept on the device.
+//   select_reduce /    two-level scan of the packed counts (greater, equal)
+//   scan / scatter     and a scatter of the selected indices in index order.
+#include "dr_device.h"
+
+namespace dr {
+
+template <int PPL>
+__global__ __launch_bounds__(256) void activity_kernel(const uint16_t* img, int64_t npix,
+                                                       int n_steps, uint64_t* act)
+{
+    using V = typename U16V<PPL>::T;
+    const int64_t p0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * PPL;
+    if (p0 >= npix) return;
+    uint64_t acc[PPL];
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) acc[q] = 0;
+    V prev = stream_load((const V*)(img + p0));
+#pragma unroll 8
+    for (int k = 1; k < n_steps; ++k) {
+        const V cur = stream_load((const V*)(img + (int64_t)k * npix + p0));
+#pragma unroll
+        for (int q = 0; q < PPL; ++q) {
+            const int d = pix<PPL>(prev, q) - pix<PPL>(cur, q);
+            acc[q] += (uint64_t)(uint32_t)(d < 0 ? -d : d);
+        }
+        prev = cur;
+    }
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) act[p0 + q] = acc[q];
+}
+
+__global__ void select_init_kernel(SelectState* st, int64_t k)
+{
+    const int t = threadIdx.x;
+    st->hist[t] = 0;
+    if (t == 0) {
+        st->prefix = 0;
+        st->mask = 0;
+        st->need = k;
+        st->above = 0;
+    }
+}
+
+// histogram of digit `shift` over the keys that match the selected prefix
+__global__ __launch_bounds__(256) void select_hist_kernel(const uint64_t* act, int64_t npix,
+                                                          int shift, SelectState* st)
+{
+    __shared__ unsigned int h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t prefix = st->prefix, mask = st->mask;
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < npix;
+         p += (int64_t)gridDim.x * 256) {
+        const uint64_t a = act[p];
+        if ((a & mask) == prefix) atomicAdd(&h[(a >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    if (h[threadIdx.x]) atomicAdd(&st->hist[threadIdx.x], (unsigned long long)h[threadIdx.x]);
+}
+
+// the digit bucket, from the top, that holds the need-th largest key
+__global__ void select_pick_kernel(int shift, SelectState* st)
+{
+    __shared__ unsigned long long h[256];
+    const int t = threadIdx.x;
+    h[t] = st->hist[t];
+    __syncthreads();
+    st->hist[t] = 0;
+    if (t == 0) {
+        unsigned long long cum = 0;
+        for (int b = 255; b >= 0; --b) {
+            if (cum + h[b] >= (unsigned long long)st->need) {
+                st->prefix |= (uint64_t)b << shift;
+                st->mask |= (uint64_t)255 << shift;
+                st->above += (int64_t)cum;
+                st->need -= (int64_t)cum;
+                break;
+            }
+            cum += h[b];
+        }
+    }
+}
+
+// counts packed as (greater << 32) | equal; block b covers 4096 keys
+__device__ __forceinline__ uint64_t sel_flag(uint64_t a, uint64_t thr)
+{
+    return (a > thr ? (uint64_t)1 << 32 : 0) | (a == thr ? 1u : 0u);
+}
+
+__global__ __launch_bounds__(256) void select_reduce_kernel(const uint64_t* act, int64_t npix,
+                                                            const SelectState* st, uint64_t* bsum)
+{
+    __shared__ uint64_t s[256];
+    const uint64_t thr = st->prefix;
+    const int64_t base = (int64_t)blockIdx.x * kSelectBlock + threadIdx.x * 16;
+    uint64_t c = 0;
+    for (int i = 0; i < 16; ++i)
+        if (base + i < npix) c += sel_flag(act[base + i], thr);
+    s[threadIdx.x] = c;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bsum[blockIdx.x] = s[0];
+}
+
+// exclusive scan of the block sums in place (one workgroup, chunks of 256)
+__global__ __launch_bounds__(256) void select_scan_kernel(uint64_t* bsum, int64_t nblocks)
+{
+    __shared__ uint64_t s[256];
+    uint64_t carry = 0;
+    for (int64_t c0 = 0; c0 < nblocks; c0 += 256) {
+        const int64_t i = c0 + threadIdx.x;
+        const uint64_t v = i < nblocks ? bsum[i] : 0;
+        s[threadIdx.x] = v;
+        __syncthreads();
+        for (int w = 1; w < 256; w <<= 1) {  // inclusive Hillis-Steele scan
+            const uint64_t x = threadIdx.x >= w ? s[threadIdx.x - w] : 0;
+            __syncthreads();
+            s[threadIdx.x] += x;
+            __syncthreads();
+        }
+        if (i < nblocks) bsum[i] = carry + s[threadIdx.x] - v;
+        carry += s[255];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void select_scatter_kernel(const uint64_t* act, int64_t npix,
+                                                             const SelectState* st,
+                                                             const uint64_t* bsum, int64_t* list)
+{
+    __shared__ uint64_t s[256];
+    const uint64_t thr = st->prefix;
+    const int64_t need = st->need;
+    const int64_t base = (int64_t)blockIdx.x * kSelectBlock + threadIdx.x * 16;
+    uint64_t c = 0;
+    for (int i = 0; i < 16; ++i)
+        if (base + i < npix) c += sel_flag(act[base + i], thr);
+    s[threadIdx.x] = c;
+    __syncthreads();
+    for (int w = 1; w < 256; w <<= 1) {
+        const uint64_t x = threadIdx.x >= w ? s[threadIdx.x - w] : 0;
+        __syncthreads();
+        s[threadIdx.x] += x;
+        __syncthreads();
+    }
+    uint64_t run = bsum[blockIdx.x] + s[threadIdx.x] - c;  // exclusive prefix at `base`
+    for (int i = 0; i < 16; ++i) {
+        const int64_t p = base + i;
+        if (p >= npix) break;
+        const uint64_t f = sel_flag(act[p], thr);
+        const int64_t gt = (int64_t)(run >> 32), eq = (int64_t)(run & 0xffffffffu);
+        if ((f >> 32) || ((f & 1) && eq < need)) list[gt + (eq < need ? eq : need)] = p;
+        run += f;
+    }
+}
+
+// caller's list: every entry in [0, npix), strictly increasing (bit 1, bit 2)
+__global__ __launch_bounds__(256) void list_check_kernel(const int64_t* list, int64_t n,
+                                                         int64_t npix, int* status)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int64_t p = list[i];
+    int bad = 0;
+    if (p < 0 || p >= npix) bad |= 1;
+    if (i > 0 && !(list[i - 1] < p)) bad |= 2;
+    if (bad) atomicOr(status, bad);
+}
+
+// first entry of every row: starts[j] = #entries below j*nx, j = 0..ny
+__global__ __launch_bounds__(256) void list_rows_kernel(const int64_t* list, int64_t n, int nx,
+                                                        int ny, int64_t* starts)
+{
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j > ny) return;
+    const int64_t key = (int64_t)j * nx;
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (list[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    starts[j] = lo;
+}
+
+hipError_t launch_activity(const uint16_t* img, int64_t npix, int n_steps, uint64_t* act,
+                           bool vec8, hipStream_t s)
+{
+    if (npix <= 0) return hipSuccess;
+    if (vec8) {
+        const int64_t lanes = npix / 8;
+        hipLaunchKernelGGL(activity_kernel<8>, dim3((unsigned)((lanes + 255) / 256)), dim3(256),
+                           0, s, img, npix, n_steps, act);
+    } else {
+        hipLaunchKernelGGL(activity_kernel<1>, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0,
+                           s, img, npix, n_steps, act);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_select_top(const uint64_t* act, int64_t npix, int64_t k, SelectState* st,
+                             uint64_t* bsum, int64_t* list, hipStream_t s)
+{
+    hipLaunchKernelGGL(select_init_kernel, dim3(1), dim3(256), 0, s, st, k);
+    const unsigned hist_groups = (unsigned)std::min<int64_t>(1024, (npix + 255) / 256);
+    for (int shift = 56; shift >= 0; shift -= 8) {
+        hipLaunchKernelGGL(select_hist_kernel, dim3(hist_groups), dim3(256), 0, s, act, npix,
+                           shift, st);
+        hipLaunchKernelGGL(select_pick_kernel, dim3(1), dim3(256), 0, s, shift, st);
+    }
+    const int64_t nb = (npix + kSelectBlock - 1) / kSelectBlock;
+    hipLaunchKernelGGL(select_reduce_kernel, dim3((unsigned)nb), dim3(256), 0, s, act, npix,
+                       (const SelectState*)st, bsum);
+    hipLaunchKernelGGL(select_scan_kernel, dim3(1), dim3(256), 0, s, bsum, nb);
+    hipLaunchKernelGGL(select_scatter_kernel, dim3((unsigned)nb), dim3(256), 0, s, act, npix,
+                       (const SelectState*)st, (const uint64_t*)bsum, list);
+    return hipGetLastError();
+}
+
+hipError_t launch_list_check(const int64_t* list, int64_t n, int64_t npix, int* status,
+                             hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(list_check_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, list,
+                       n, npix, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_list_rows(const int64_t* list, int64_t n, int nx, int ny, int64_t* starts,
+                            hipStream_t s)
+{
+    hipLaunchKernelGGL(list_rows_kernel, dim3((unsigned)((ny + 1 + 255) / 256)), dim3(256), 0, s,
+                       list, n, nx, ny, starts);
+    return hipGetLastError();
+}
+
+}  // namespace dr

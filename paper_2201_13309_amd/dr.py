@@ -25,6 +25,7 @@ DR_E_INVAL, DR_E_NOMEM, DR_E_UNSUPPORTED, DR_E_DEVICE, DR_E_BUSY, DR_E_NOTFOUND 
 DR_EDGE_LEADING, DR_EDGE_TRAILING, DR_EDGE_BOTH = 0, 1, 2
 DR_BATCH_AUTOTUNE, DR_BATCH_GRAPH = 1, 2
 DR_PATH_ROWS, DR_PATH_PIXELS = 0, 1
+DR_LAYOUT_FULL, DR_LAYOUT_LIST = 0, 1
 
 # names exported by libdr.so, as declared in include/dr.h
 ABI_SYMBOLS = (
@@ -32,7 +33,9 @@ ABI_SYMBOLS = (
     "dr_geometry_free", "dr_set_tile",
     "dr_autotune", "dr_reconstruct", "dr_reconstruct_f64", "dr_debug_plan", "dr_enable_timing",
     "dr_last_timing", "dr_batch_create", "dr_batch_run", "dr_batch_tile", "dr_batch_free",
-    "dr_submit", "dr_poll", "dr_wait", "dr_ctx_stats", "dr_last_error",
+    "dr_submit", "dr_poll", "dr_wait", "dr_ctx_stats", "dr_last_error", "dr_pixel_activity",
+    "dr_select_top", "dr_list_create", "dr_list_size", "dr_list_pixels", "dr_list_free",
+    "dr_reconstruct_list", "dr_reconstruct_list_f64",
 )
 
 
@@ -114,6 +117,14 @@ def load(path: Optional[str] = None):
         "dr_poll": [vp, u64],
         "dr_wait": [vp, u64],
         "dr_ctx_stats": [vp, P(dr_stats)],
+        "dr_pixel_activity": [vp, vp, vp, vp],
+        "dr_select_top": [vp, vp, ctypes.c_int64, P(vp)],
+        "dr_list_create": [vp, vp, ctypes.c_int64, ctypes.c_int, P(vp)],
+        "dr_list_size": [vp, P(ctypes.c_int64)],
+        "dr_list_pixels": [vp, vp],
+        "dr_list_free": [vp],
+        "dr_reconstruct_list": [vp, vp, i32, ctypes.c_int, vp, vp, vp],
+        "dr_reconstruct_list_f64": [vp, vp, i32, vp, vp, vp],
     }
     for name, argt in sigs.items():
         f = getattr(lib, name)
@@ -320,3 +331,58 @@ def dr_ctx_stats(ctx: int) -> dict:
     s = dr_stats()
     _check(load().dr_ctx_stats(ctx, ctypes.byref(s)))
     return {f: getattr(s, f) for f, _ in dr_stats._fields_}
+
+
+# ------------------------------------------------------------- pixel lists
+
+
+def dr_pixel_activity(geom: int, images_dev, activity_dev, stream=None) -> None:
+    _check(load().dr_pixel_activity(geom, ptr(images_dev), ptr(activity_dev),
+                                    stream_handle(stream)))
+
+
+def dr_select_top(geom: int, activity_dev, k: int) -> int:
+    h = ctypes.c_void_p()
+    _check(load().dr_select_top(geom, ptr(activity_dev), int(k), ctypes.byref(h)))
+    return h.value
+
+
+def dr_list_create(geom: int, pixels, on_device: bool = False) -> int:
+    """pixels: int64 array (host numpy or device tensor), strictly increasing."""
+    if isinstance(pixels, np.ndarray):
+        pixels = np.ascontiguousarray(pixels, dtype=np.int64)
+        n = pixels.shape[0]
+    else:
+        n = int(pixels.numel())
+    h = ctypes.c_void_p()
+    _check(load().dr_list_create(geom, ptr(pixels) if n else None, n, 1 if on_device else 0,
+                                 ctypes.byref(h)))
+    return h.value
+
+
+def dr_list_size(lst: int) -> int:
+    n = ctypes.c_int64()
+    _check(load().dr_list_size(lst, ctypes.byref(n)))
+    return n.value
+
+
+def dr_list_pixels(lst: int) -> np.ndarray:
+    out = np.empty(max(dr_list_size(lst), 1), dtype=np.int64)
+    _check(load().dr_list_pixels(lst, ptr(out)))
+    return out[:dr_list_size(lst)]
+
+
+def dr_list_free(lst: int) -> None:
+    _check(load().dr_list_free(lst))
+
+
+def dr_reconstruct_list(lst: int, images, layout: int, images_on_device: bool, out, totals=None,
+                        stream=None) -> None:
+    _check(load().dr_reconstruct_list(lst, ptr(images), int(layout), 1 if images_on_device else 0,
+                                      ptr(out), ptr(totals), stream_handle(stream)))
+
+
+def dr_reconstruct_list_f64(lst: int, images_dev, layout: int, out, totals=None,
+                            stream=None) -> None:
+    _check(load().dr_reconstruct_list_f64(lst, ptr(images_dev), int(layout), ptr(out),
+                                          ptr(totals), stream_handle(stream)))

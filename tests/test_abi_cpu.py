@@ -48,6 +48,13 @@ def test_null_arguments_rejected_without_device(lib):
     assert lib.dr_poll(None, 1) == dr.DR_E_INVAL
     assert lib.dr_ctx_create(0, 0, None) == dr.DR_E_INVAL
     assert lib.dr_debug_plan(None, None, 0, 0, None, None) == dr.DR_E_INVAL
+    assert lib.dr_pixel_activity(None, None, None, None) == dr.DR_E_INVAL
+    assert lib.dr_select_top(None, None, 0, None) == dr.DR_E_INVAL
+    assert lib.dr_list_create(None, None, 0, 0, None) == dr.DR_E_INVAL
+    assert lib.dr_list_free(None) == dr.DR_E_INVAL
+    assert lib.dr_reconstruct_list(None, None, 0, 1, None, None, None) == dr.DR_E_INVAL
+    assert lib.dr_reconstruct_list_f64(None, None, 0, None, None, None) == dr.DR_E_INVAL
+    assert lib.dr_geometry_path(None, None) == dr.DR_E_INVAL
 
 
 def test_ctx_create_without_gpu_fails_cleanly(lib):
