@@ -122,6 +122,84 @@ def run_per_pixel(torch, synth, dr, ctx, s, dev, out, tot, stream, steps: int):
                         "positions computed per pixel in FP64 on the fly"}
 
 
+def run_pixel_fraction(torch, dr, ctx, s, host, dev, stream, steps: int):
+    """The paper's second experiment on the same scan: reconstruct the 25, 50
+    and 100% most active pixels (activity sum_k |I_k - I_{k+1}|, ties to the
+    lower index).  Per fraction: device time of the list reconstruction from
+    full frames resident in HBM, and the PCIe-inclusive time from a compact
+    pinned host stack of the selected pixels (gathered before the timed
+    region), whose bytes scale with the fraction; also the device time from
+    that compact stack resident in HBM."""
+    d, N, B = s.detector, s.wire.n_steps, s.grid.n_bins
+    npix = d.nx * d.ny
+    g = dr.dr_geometry_init(ctx, d, s.wire, s.grid)
+    res = {"rule": "top-k pixels by sum_k |I_k - I_{k+1}|, ties to the lower index",
+           "fractions": []}
+    try:
+        act = torch.empty(npix, dtype=torch.int64, device="cuda")
+        dr.dr_pixel_activity(g, dev, act, stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            dr.dr_pixel_activity(g, dev, act, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        res["activity_ms"] = e0.elapsed_time(e1) / steps
+        for pct in (25, 50, 100):
+            k = npix * pct // 100
+            t0 = time.perf_counter()
+            lst = dr.dr_select_top(g, act, k)
+            sel_ms = (time.perf_counter() - t0) * 1e3
+            try:
+                out = torch.empty((B, k), dtype=torch.float32, device="cuda")
+                tot = torch.empty((B,), dtype=torch.float32, device="cuda")
+                dr.dr_reconstruct_list(lst, dev, dr.DR_LAYOUT_FULL, True, out, tot, stream)
+                torch.cuda.synchronize()
+                e0.record(stream)
+                for _ in range(steps):
+                    dr.dr_reconstruct_list(lst, dev, dr.DR_LAYOUT_FULL, True, out, tot, stream)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                dev_ms = e0.elapsed_time(e1) / steps
+                pix = dr.dr_list_pixels(lst)
+                compact = torch.empty((N, k), dtype=torch.int16, pin_memory=True)
+                np.take(host.numpy().reshape(N, npix), pix, axis=1, out=compact.numpy())
+                cdev = compact.to("cuda")
+                dr.dr_reconstruct_list(lst, cdev, dr.DR_LAYOUT_LIST, True, out, tot, stream)
+                torch.cuda.synchronize()
+                e0.record(stream)
+                for _ in range(steps):
+                    dr.dr_reconstruct_list(lst, cdev, dr.DR_LAYOUT_LIST, True, out, tot, stream)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                dev_compact_ms = e0.elapsed_time(e1) / steps
+                del cdev
+                dr.dr_reconstruct_list(lst, compact, dr.DR_LAYOUT_LIST, False, out, tot, stream)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                dr.dr_reconstruct_list(lst, compact, dr.DR_LAYOUT_LIST, False, out, tot, stream)
+                torch.cuda.synchronize()
+                host_ms = (time.perf_counter() - t0) * 1e3
+                del compact, out
+            finally:
+                dr.dr_list_free(lst)
+            work = k * N
+            res["fractions"].append({
+                "percent": pct, "pixels": k, "select_ms": sel_ms,
+                "device_ms": dev_ms, "device_value": work / (dev_ms * 1e-3),
+                "device_compact_ms": dev_compact_ms,
+                "device_compact_value": work / (dev_compact_ms * 1e-3),
+                "host_compact_ms": host_ms, "host_value": work / (host_ms * 1e-3),
+                "h2d_GB": 2 * work / 1e9})
+            log(f"top {pct}%: select {sel_ms:.1f} ms, device full frames {dev_ms:.2f} ms, "
+                f"device compact {dev_compact_ms:.2f} ms, host compact {host_ms:.1f} ms")
+    finally:
+        dr.dr_geometry_free(g)
+    res["unit"] = UNIT
+    return res
+
+
 def run_batched(torch, synth, dr, ctx, steps: int):
     """16 scans of uneven size in one persistent launch (autotuned, graph
     captured) against the same scans run one after another with the
@@ -282,6 +360,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-per-pixel", action="store_true")
+    ap.add_argument("--no-fraction", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-rate", type=float, default=20.0)
@@ -406,7 +485,12 @@ def main():
     if not args.no_per_pixel:
         result["per_pixel"] = run_per_pixel(torch, synth, dr, ctx, s, dev, out, tot, stream,
                                             max(2, args.steps // 2))
-    del dev, out
+    del out
+    torch.cuda.empty_cache()
+    if not args.no_fraction:
+        result["pixel_fraction"] = run_pixel_fraction(torch, dr, ctx, s, host, dev, stream,
+                                                      max(2, args.steps // 2))
+    del dev
     torch.cuda.empty_cache()
     if not args.no_batch and args.workload == "config3":
         result["batched"] = run_batched(torch, synth, dr, ctx, max(3, args.steps // 2))

@@ -403,8 +403,9 @@ __device__ __forceinline__ TileAddr<Acc> row_tile_addr(const ScanArgs& a, int ro
 }
 
 // Tile t of a pixel list: entries [tile_start, tile_start + tile_count), all
-// in one detector row, one pixel per lane; the output is [n_bins][n] in list
-// order.  Images are full frames (gathered by pixel) or compact [N][entries]
+// in one detector row, one pixel per lane, lane i holding entry
+// (tile_start rounded down to kListAlign) + i so that every wave reads and
+// writes whole aligned lines; the output is [n_bins][n] in list order.  Images are full frames (gathered by pixel) or compact [N][entries]
 // in list order, the buffer holding entries from entry_base on.
 template <typename Acc, int WAVES>
 __device__ __forceinline__ TileAddr<Acc> list_tile_addr(const ScanArgs& a, const ListArgs& l,
@@ -412,9 +413,10 @@ __device__ __forceinline__ TileAddr<Acc> list_tile_addr(const ScanArgs& a, const
 {
     const int tid = threadIdx.x, wave = tid >> 6;
     const int64_t e0 = l.tile_start[t];
+    const int64_t base = e0 & ~(int64_t)(kListAlign - 1);  // lane 0's entry
     TileAddr<Acc> ta;
-    ta.act = tid < l.tile_count[t];
-    const int64_t e = ta.act ? e0 + tid : e0;
+    ta.act = base + tid >= e0 && base + tid < e0 + l.tile_count[t];
+    const int64_t e = ta.act ? base + tid : e0;
     if (l.compact) {
         ta.ibase = a.img;
         ta.ioff = (uint32_t)(e - l.entry_base);
@@ -425,7 +427,7 @@ __device__ __forceinline__ TileAddr<Acc> list_tile_addr(const ScanArgs& a, const
     ta.istep = a.img_step;
     ta.obase = (Acc*)a.out;
     ta.plane = a.out_plane;
-    ta.ooff = (uint32_t)(e0 + tid);
+    ta.ooff = (uint32_t)(base + tid);
     ta.part = a.partials ? (Acc*)a.partials + (t * WAVES + wave) * a.n_bins : nullptr;
     return ta;
 }

@@ -179,7 +179,10 @@ hipError_t launch_list_pixels_f32(const ScanArgs& a, const GeomArgs& g, int side
                                   const ListArgs& l, int64_t n_tiles, hipStream_t s);
 hipError_t launch_list_pixels_f64(const ScanArgs& a, const GeomArgs& g, int side, double scale,
                                   const ListArgs& l, int64_t n_tiles, hipStream_t s);
-constexpr int kListTile = 256;  // entries per list tile
+constexpr int kListTile = 256;  // lanes per list tile
+// list tiles map lane i to entry (start rounded down to kListAlign) + i; a tile
+// spans at most kListTile entries from that base
+constexpr int64_t kListAlign = 64;
 
 constexpr int kPlanChunk = 1024;  // intervals staged in LDS at a time
 constexpr int kTotalsWorkRows = 64;

@@ -240,11 +240,12 @@ __global__ __launch_bounds__(kPixelTile) void pixels_kernel(ScanArgs a, GeomArgs
     if (l.pixels) {
         const int64_t t = l.tile_first + blockIdx.x;
         const int64_t e0 = l.tile_start[t];
-        act = tid < l.tile_count[t];
-        const int64_t e = act ? e0 + tid : e0;
+        const int64_t base = e0 & ~(int64_t)(kListAlign - 1);
+        act = base + tid >= e0 && base + tid < e0 + l.tile_count[t];
+        const int64_t e = act ? base + tid : e0;
         pixel = l.pixels[e];
         ip = l.compact ? a.img + (e - l.entry_base) : a.img + pixel;
-        op = (Acc*)a.out + e0 + tid;
+        op = (Acc*)a.out + base + tid;
         slot = t;
     } else {
         const int row = a.row_begin + (int)(blockIdx.x / (unsigned)a.tiles_per_row);

@@ -30,9 +30,14 @@ static bool aligned_to(const void* p, size_t a) { return (reinterpret_cast<uintp
 
 static size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// host runs of a compact stack start and end on multiples of this many
+// entries (128 bytes), the last one at the end of the list
+constexpr int64_t kRunAlign = kListAlign;
+
 // Tile table of a validated list held in l->pixels: per-row plan path, tiles
-// of at most kListTile entries inside one detector row; per-pixel path, runs
-// of kListTile consecutive entries.  Synchronous (reads the row starts back).
+// inside one detector row, each ending at most kListTile entries after its
+// start rounded down to kListAlign; per-pixel path, aligned runs of kListTile
+// consecutive entries.  Synchronous (reads the row starts back).
 static dr_status build_tiles(dr_list l, hipStream_t s)
 {
     const dr_geom g = l->g;
@@ -48,11 +53,15 @@ static dr_status build_tiles(dr_list l, hipStream_t s)
         DR_HIP(hipMemcpyAsync(h.data(), starts.p, h.size() * sizeof(int64_t),
                               hipMemcpyDeviceToHost, s));
         DR_HIP(hipStreamSynchronize(s));
+        // a tile ends kListTile entries after its start rounded down to
+        // kListAlign, so the tiles after a row's first start aligned
         for (int j = 0; j < g->ny; ++j)
-            for (int64_t e = h[j]; e < h[j + 1]; e += kListTile) {
+            for (int64_t e = h[j]; e < h[j + 1];) {
+                const int64_t end = std::min<int64_t>(h[j + 1], e - e % kListAlign + kListTile);
                 rows.push_back(j);
                 l->h_start.push_back(e);
-                l->h_count.push_back((int32_t)std::min<int64_t>(kListTile, h[j + 1] - e));
+                l->h_count.push_back((int32_t)(end - e));
+                e = end;
             }
     } else {
         for (int64_t e = 0; e < l->n; e += kListTile) {
@@ -92,13 +101,14 @@ static ListArgs list_args(const dr_list l, int32_t compact)
     return la;
 }
 
-// partial-total rows of one pass
+// workgroups of one pass, and partial-total rows of one pass
+static int64_t list_groups(const dr_list l) { return l->n_tiles; }
 static int64_t list_slots(const dr_list l) { return l->n_tiles * (l->g->row_mode ? 4 : 1); }
 
 // Scan arguments of pass p over a list: images img (full frames: step stride
 // nx*ny; compact: step stride `img_step` entries), output [n_bins][n].
 static ScanArgs list_scan_args(const dr_list l, int p, const uint16_t* img, int64_t img_step,
-                               void* out, void* partials, size_t elem)
+                               void* out, void* partials, size_t elem, int64_t slots)
 {
     const dr_geom g = l->g;
     ScanArgs a{};
@@ -116,8 +126,7 @@ static ScanArgs list_scan_args(const dr_list l, int p, const uint16_t* img, int6
     a.n_bins = g->n_bins;
     a.out = out;
     a.out_plane = l->n;
-    a.partials = partials ? (char*)partials + (size_t)p * list_slots(l) * g->n_bins * elem
-                          : nullptr;
+    a.partials = partials ? (char*)partials + (size_t)p * slots * g->n_bins * elem : nullptr;
     if (g->row_mode) {
         const PlanTables& pt = g->t[p];
         a.bl = pt.bl;
@@ -283,25 +292,26 @@ dr_status dr_reconstruct_list(dr_list l, const uint16_t* images, int32_t layout,
     DR_HIP(hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
     float* part = nullptr;
-    const int64_t slots = list_slots(l);
+    const int32_t compact = layout == DR_LAYOUT_LIST;
+    const int64_t slots = list_slots(l), groups = list_groups(l);
     if (totals) {
         std::lock_guard<std::mutex> lk(l->mu);
         DR_HIP(l->part32.reserve(std::max<size_t>(4, (size_t)g->passes * slots * g->n_bins * 4)));
         DR_HIP(l->work.reserve((size_t)kTotalsWorkRows * g->n_bins * sizeof(double)));
         part = l->part32.as<float>();
     }
-    const int32_t compact = layout == DR_LAYOUT_LIST;
     if (images_on_device) {
         const int64_t step = compact ? l->n : (int64_t)g->nx * g->ny;
         const ListArgs la = list_args(l, compact);
         for (int p = 0; p < g->passes; ++p) {
-            const ScanArgs a = list_scan_args(l, p, images, step, out, part, 4);
-            DR_HIP(launch_list_pass(l, p, a, la, l->n_tiles, false, s));
+            const ScanArgs a = list_scan_args(l, p, images, step, out, part, 4, slots);
+            DR_HIP(launch_list_pass(l, p, a, la, groups, false, s));
         }
     } else {
         // compact host stack: runs of whole tiles copied into the context's
         // two slab buffers on its copy stream, each run's kernels overlapping
-        // the next run's copy
+        // the next run's copy.  A run's window is widened to multiples of
+        // kRunAlign entries so that every copied line starts aligned.
         size_t target = (size_t)256 << 20;
         if (const char* e = std::getenv("DR_SLAB_MB")) target = (size_t)std::max(1, atoi(e)) << 20;
         const size_t per_entry = (size_t)g->n_steps * sizeof(uint16_t);
@@ -309,7 +319,7 @@ dr_status dr_reconstruct_list(dr_list l, const uint16_t* images, int32_t layout,
         if (const char* e = std::getenv("DR_LIST_RUN_ENTRIES"))  // smaller runs (tests)
             cap = std::max<int64_t>(kListTile, atoll(e));
         std::lock_guard<std::mutex> lk(c->mu);
-        const size_t slab_bytes = (size_t)cap * per_entry;
+        const size_t slab_bytes = (size_t)(cap + 2 * kRunAlign) * per_entry;
         for (int i = 0; i < 2; ++i)
             if (c->slab[i].bytes < slab_bytes) {
                 DR_HIP(hipStreamSynchronize(c->copy));
@@ -323,20 +333,22 @@ dr_status dr_reconstruct_list(dr_list l, const uint16_t* images, int32_t layout,
             int64_t t1 = t0 + 1;
             while (t1 < l->n_tiles && l->h_start[t1] + l->h_count[t1] - e0 <= cap) ++t1;
             const int64_t e1 = l->h_start[t1 - 1] + l->h_count[t1 - 1];
+            const int64_t a0 = e0 - e0 % kRunAlign;
+            const int64_t a1 = std::min<int64_t>(l->n, (e1 + kRunAlign - 1) / kRunAlign * kRunAlign);
             const int b = run & 1;
             DR_HIP(hipStreamWaitEvent(c->copy, c->slab_free[b], 0));
-            DR_HIP(hipMemcpy2DAsync(c->slab[b].p, (size_t)(e1 - e0) * sizeof(uint16_t),
-                                    images + e0, (size_t)l->n * sizeof(uint16_t),
-                                    (size_t)(e1 - e0) * sizeof(uint16_t), (size_t)g->n_steps,
+            DR_HIP(hipMemcpy2DAsync(c->slab[b].p, (size_t)(a1 - a0) * sizeof(uint16_t),
+                                    images + a0, (size_t)l->n * sizeof(uint16_t),
+                                    (size_t)(a1 - a0) * sizeof(uint16_t), (size_t)g->n_steps,
                                     hipMemcpyHostToDevice, c->copy));
             DR_HIP(hipEventRecord(c->slab_ready[b], c->copy));
             DR_HIP(hipStreamWaitEvent(s, c->slab_ready[b], 0));
             ListArgs la = list_args(l, 1);
             la.tile_first = t0;
-            la.entry_base = e0;
+            la.entry_base = a0;
             for (int p = 0; p < g->passes; ++p) {
-                const ScanArgs a = list_scan_args(l, p, c->slab[b].as<uint16_t>(), e1 - e0, out,
-                                                  part, 4);
+                const ScanArgs a = list_scan_args(l, p, c->slab[b].as<uint16_t>(), a1 - a0, out,
+                                                  part, 4, slots);
                 DR_HIP(launch_list_pass(l, p, a, la, t1 - t0, false, s));
             }
             DR_HIP(hipEventRecord(c->slab_free[b], s));
@@ -344,7 +356,7 @@ dr_status dr_reconstruct_list(dr_list l, const uint16_t* images, int32_t layout,
         }
     }
     if (totals) {
-        if (l->n_tiles == 0) {
+        if (groups == 0) {
             DR_HIP(hipMemsetAsync(totals, 0, (size_t)g->n_bins * sizeof(float), s));
         } else {
             DR_HIP(launch_totals_f32(part, slots * g->passes, g->n_bins, l->work.as<double>(),
@@ -368,22 +380,22 @@ dr_status dr_reconstruct_list_f64(dr_list l, const uint16_t* images_dev, int32_t
     DR_HIP(hipSetDevice(g->ctx->device));
     hipStream_t s = (hipStream_t)stream;
     double* part = nullptr;
-    const int64_t slots = list_slots(l);
+    const int32_t compact = layout == DR_LAYOUT_LIST;
+    const int64_t slots = list_slots(l), groups = list_groups(l);
     if (totals) {
         std::lock_guard<std::mutex> lk(l->mu);
         DR_HIP(l->part64.reserve(std::max<size_t>(8, (size_t)g->passes * slots * g->n_bins * 8)));
         DR_HIP(l->work.reserve((size_t)kTotalsWorkRows * g->n_bins * sizeof(double)));
         part = l->part64.as<double>();
     }
-    const int32_t compact = layout == DR_LAYOUT_LIST;
     const int64_t step = compact ? l->n : (int64_t)g->nx * g->ny;
     const ListArgs la = list_args(l, compact);
     for (int p = 0; p < g->passes; ++p) {
-        const ScanArgs a = list_scan_args(l, p, images_dev, step, out, part, 8);
-        DR_HIP(launch_list_pass(l, p, a, la, l->n_tiles, true, s));
+        const ScanArgs a = list_scan_args(l, p, images_dev, step, out, part, 8, slots);
+        DR_HIP(launch_list_pass(l, p, a, la, groups, true, s));
     }
     if (totals) {
-        if (l->n_tiles == 0) {
+        if (groups == 0) {
             DR_HIP(hipMemsetAsync(totals, 0, (size_t)g->n_bins * sizeof(double), s));
         } else {
             DR_HIP(launch_totals_f64(part, slots * g->passes, g->n_bins, l->work.as<double>(),

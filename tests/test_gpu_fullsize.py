@@ -129,6 +129,36 @@ def test_config3_sampled_and_invariants(dr, ctx):
                 d = (sums[rows] - first_minus_last[rows]).abs()
                 assert bool((d <= REL_TOL * sc[rows] + 1e-6).all())
         assert float((tot.to(torch.float64) - tot64).abs().max()) <= REL_TOL * total_scale
+        # pixel selection at full size: activities of the sample against the
+        # oracle, the top-25% list obeys the rule, and its reconstruction from
+        # full frames equals the dense output at the listed pixels bit for bit
+        act = torch.empty(nx * ny, dtype=torch.int64, device="cuda")
+        dr.dr_pixel_activity(g, dev, act, torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        got_act = act[torch.from_numpy(pix).to("cuda")].cpu().numpy().view(np.uint64)
+        assert np.array_equal(got_act, oracle.activity(np.ascontiguousarray(series.T)))
+        k = nx * ny // 4
+        lst = dr.dr_select_top(g, act, k)
+        try:
+            sel = torch.from_numpy(dr.dr_list_pixels(lst)).to("cuda")
+            assert sel.numel() == k and bool((sel[1:] > sel[:-1]).all())
+            chosen = torch.zeros(nx * ny, dtype=torch.bool, device="cuda")
+            chosen[sel] = True
+            thr = act[sel].min()
+            assert bool((act[~chosen] <= thr).all()) and bool(chosen[act > thr].all())
+            ties = torch.nonzero((act == thr) & ~chosen).flatten()
+            if ties.numel():
+                assert int(ties.min()) > int(sel[act[sel] == thr].max())
+            outl = torch.empty((B, k), device="cuda")
+            dr.dr_reconstruct_list(lst, dev, dr.DR_LAYOUT_FULL, True, outl, None,
+                                   torch.cuda.current_stream())
+            torch.cuda.synchronize()
+            for c0 in range(0, k, 1 << 18):  # compare in column blocks
+                cols = sel[c0:c0 + (1 << 18)]
+                assert torch.equal(outl[:, c0:c0 + cols.numel()], out.view(B, -1)[:, cols])
+            del outl, chosen
+        finally:
+            dr.dr_list_free(lst)
     finally:
         dr.dr_geometry_free(g)
         del dev, out
