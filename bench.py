@@ -200,6 +200,65 @@ def run_pixel_fraction(torch, dr, ctx, s, host, dev, stream, steps: int):
     return res
 
 
+def run_h5_files(torch, synth, dr, ctx, stream):
+    """Files in, depth images out, on the 1024x1024 px, 401-step, 501-bin scan:
+    one HDF5 file per wire step (written first, so read from the page cache),
+    read into pinned memory, reconstructed from host memory (row slabs over
+    PCIe), and the depth images written to one HDF5 file."""
+    import shutil
+    import tempfile
+    from paper_2201_13309_amd import dr_h5, build as pkg_build
+    if not pkg_build.hdf5_available() or not os.path.exists(dr_h5.LIB_PATH):
+        return None
+    s = synth.config2(render_now=False)
+    d, N, B = s.detector, s.wire.n_steps, s.grid.n_bins
+    host = torch.empty((N, d.ny, d.nx), dtype=torch.int16, pin_memory=True)
+    synth.render(s, out=host.numpy().view(np.uint16))
+    tmp = tempfile.mkdtemp(prefix="dr_h5_", dir=os.environ.get("TMPDIR", "/tmp"))
+    try:
+        paths = [os.path.join(tmp, f"scan_{k:04d}.h5") for k in range(N)]
+        t0 = time.perf_counter()
+        dr_h5.write_stack(paths, "/entry1/data/data", host.numpy())
+        write_in_s = time.perf_counter() - t0
+        buf = torch.empty((N, d.ny, d.nx), dtype=torch.int16, pin_memory=True)
+        out = torch.empty((B, d.ny, d.nx), dtype=torch.float32, device="cuda")
+        out_h = torch.empty((B, d.ny, d.nx), dtype=torch.float32, pin_memory=True)
+        g = dr.dr_geometry_init(ctx, d, s.wire, s.grid)
+        try:
+            t0 = time.perf_counter()
+            st = dr_h5.open_stack(paths, "/entry1/data/data")
+            direct = dr_h5.stack_shape(st)[3]
+            dr_h5.read_rows(st, 0, d.ny, buf)
+            dr_h5.close_stack(st)
+            t1 = time.perf_counter()
+            dr.dr_reconstruct(g, buf, False, out, None, stream)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            out_h.copy_(out)
+            t3 = time.perf_counter()
+            dr_h5.write_depth_images(os.path.join(tmp, "depth.h5"), "/depth_images",
+                                     out_h, s.grid.first_center, s.grid.width)
+            t4 = time.perf_counter()
+        finally:
+            dr.dr_geometry_free(g)
+        del out
+        res = {"workload": f"config2: {d.nx}x{d.ny} px, {N} files of one uint16 image, "
+                           f"{B} depth bins out",
+               "files": N, "direct_read_files": direct,
+               "read_ms": (t1 - t0) * 1e3, "read_GBps": host.numel() * 2 / (t1 - t0) / 1e9,
+               "reconstruct_from_host_ms": (t2 - t1) * 1e3, "d2h_ms": (t3 - t2) * 1e3,
+               "depth_write_ms": (t4 - t3) * 1e3,
+               "depth_write_GBps": out_h.numel() * 4 / (t4 - t3) / 1e9,
+               "end_to_end_ms": (t4 - t0) * 1e3, "input_write_s": write_in_s,
+               "note": "input files read from the page cache (written just before)"}
+        log(f"files: read {res['read_ms']:.0f} ms ({res['read_GBps']:.1f} GB/s), reconstruct "
+            f"{res['reconstruct_from_host_ms']:.0f} ms, depth images written in "
+            f"{res['depth_write_ms']:.0f} ms")
+        return res
+    finally:
+        shutil.rmtree(tmp, ignore_errors=True)
+
+
 def run_batched(torch, synth, dr, ctx, steps: int):
     """16 scans of uneven size in one persistent launch (autotuned, graph
     captured) against the same scans run one after another with the
@@ -361,6 +420,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-per-pixel", action="store_true")
     ap.add_argument("--no-fraction", action="store_true")
+    ap.add_argument("--no-files", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-rate", type=float, default=20.0)
@@ -497,6 +557,10 @@ def main():
     if not args.no_serve and args.workload == "config3":
         result["serving"] = run_served(torch, synth, dr, s, host, args.serve_seconds,
                                        args.serve_rate)
+    if not args.no_files and args.workload == "config3":
+        res = run_h5_files(torch, synth, dr, ctx, stream)
+        if res is not None:
+            result["files"] = res
     if not args.no_cpu_baseline:
         log("timing the oracle on a CPU sample")
         s.images = host.numpy().view(np.uint16)

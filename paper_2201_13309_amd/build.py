@@ -36,6 +36,36 @@ def _compile(src: str, device: bool) -> str:
     return obj
 
 
+# HDF5 file layer (libdr_h5.so): built when an HDF5 installation is found
+HDF5_ROOT = os.environ.get("DR_HDF5_ROOT", "/opt/conda")
+H5_LIB_PATH = os.path.join(PKG, "libdr_h5.so")
+
+
+def hdf5_available() -> bool:
+    return os.path.exists(os.path.join(HDF5_ROOT, "include", "hdf5.h")) and \
+        os.path.exists(os.path.join(HDF5_ROOT, "lib", "libhdf5.so"))
+
+
+def build_h5(verbose: bool = False) -> str:
+    """g++ build of the HDF5 layer against HDF5_ROOT (rpath to its lib/)."""
+    if not hdf5_available():
+        if verbose:
+            print("HDF5 not found under", HDF5_ROOT, "- libdr_h5.so not built")
+        return ""
+    lib = os.path.join(HDF5_ROOT, "lib")
+    tmp = H5_LIB_PATH + ".tmp"
+    cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-Wall", f"-I{INCLUDE}",
+           f"-I{os.path.join(HDF5_ROOT, 'include')}", os.path.join(CSRC, "dr_h5.cpp"), "-o", tmp,
+           f"-L{lib}", "-lhdf5", f"-Wl,-rpath,{lib}", "-lpthread"]
+    r = subprocess.run(cmd, stderr=subprocess.PIPE, stdout=subprocess.PIPE)
+    if r.returncode != 0:
+        raise RuntimeError("g++ failed for dr_h5.cpp:\n" + r.stderr.decode(errors="replace"))
+    os.replace(tmp, H5_LIB_PATH)
+    if verbose:
+        print("built", H5_LIB_PATH)
+    return H5_LIB_PATH
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     with ThreadPoolExecutor(len(SOURCES)) as ex:
@@ -54,6 +84,7 @@ def build(verbose: bool = False) -> str:
     os.replace(tmp, LIB_PATH)
     if verbose:
         print("built", LIB_PATH)
+    build_h5(verbose)
     return LIB_PATH
 
 
