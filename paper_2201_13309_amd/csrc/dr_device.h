@@ -147,8 +147,8 @@ __device__ __forceinline__ int leading_sign(const GeomArgs& g, double py, double
 __device__ __forceinline__ double edge_position(const GeomArgs& g, double py, double pz, int k,
                                                 double sr, double c, double e0, double invw)
 {
-    const double d =
-        tangent_depth(py, pz, g.wire_yz[2 * k], g.wire_yz[2 * k + 1], g.radius, sr) / c;
+    const double t = tangent_depth(py, pz, g.wire_yz[2 * k], g.wire_yz[2 * k + 1], g.radius, sr);
+    const double d = c == 1.0 ? t : t / c;  // t / 1 == t: the division only for tilted axes
     return (d - e0) * invw;
 }
 
@@ -168,6 +168,9 @@ struct PlanD {
 // Bins of the interval between positions ua and ub (bin units) that overlap it
 // by a positive length, and their fractions overlap/length.  A zero-length
 // interval is a point mass in bin floor(ua).  Parts outside [0, B) drop out.
+// EXACT divides each overlap by the length (the FP64 order); otherwise the
+// overlaps are multiplied by one reciprocal (for fractions rounded to FP32).
+template <bool EXACT = true>
 __device__ __forceinline__ PlanD make_plan(double ua, double ub, int B)
 {
     PlanD e{0, 0, 0.0, 0.0, 0.0};
@@ -196,9 +199,16 @@ __device__ __forceinline__ PlanD make_plan(double ua, double ub, int B)
         if (first <= last) {
             e.bl = (int)first;
             e.nb = (int)(last - first) + 1;
-            e.f0 = ovf / len;
-            e.f1 = ovl / len;
-            e.fm = 1.0 / len;  // interior bins overlap by exactly one bin
+            if constexpr (EXACT) {
+                e.f0 = ovf / len;
+                e.f1 = ovl / len;
+                e.fm = 1.0 / len;  // interior bins overlap by exactly one bin
+            } else {
+                const double rl = 1.0 / len;
+                e.f0 = ovf * rl;
+                e.f1 = ovl * rl;
+                e.fm = rl;
+            }
         }
     } else {
         const double bd = __builtin_floor(lo);

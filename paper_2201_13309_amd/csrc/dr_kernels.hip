@@ -281,6 +281,7 @@ __global__ __launch_bounds__(kPixelTile) void pixels_kernel(ScanArgs a, GeomArgs
     auto binp = [&](int bp) { return dir > 0 ? bp : B - 1 - bp; };
 
     Acc acc = (Acc)0;
+    Acc tacc = (Acc)0;  // this pass's contributions to the open bin, for the totals
     int cbp = -1;  // open bin in the direction frame (-1: none); when open, cbp == nxt
     int nxt = 0;   // first bin (direction frame) not yet stored
     auto store = [&](int bp, Acc v) {
@@ -289,15 +290,16 @@ __global__ __launch_bounds__(kPixelTile) void pixels_kernel(ScanArgs a, GeomArgs
     auto close_open = [&]() {
         if (cbp >= 0) {
             store(cbp, acc);
+            if (tot && act) atomicAdd(&ltot[binp(cbp)], tacc);
             nxt = cbp + 1;
             cbp = -1;
         }
     };
     auto visit = [&](int b, Acc fr, Acc dI) {
         const int bp = dir > 0 ? b : B - 1 - b;
-        if (tot && act) atomicAdd(&ltot[b], fr * dI);
         if (bp == cbp) {
             acc = madd(fr, dI, acc);
+            tacc = madd(fr, dI, tacc);
         } else if (bp >= nxt) {
             close_open();
             if (!add_on)
@@ -306,9 +308,11 @@ __global__ __launch_bounds__(kPixelTile) void pixels_kernel(ScanArgs a, GeomArgs
             nxt = bp;
             Acc* o = op + (int64_t)b * plane;
             acc = madd(fr, dI, (add_on && act) ? *o : (Acc)0);
+            tacc = madd(fr, dI, (Acc)0);
         } else if (act) {  // stored already: read, add, rewrite
             Acc* o = op + (int64_t)b * plane;
             *o = madd(fr, dI, *o);
+            if (tot) atomicAdd(&ltot[b], fr * dI);
         }
     };
 
@@ -322,7 +326,7 @@ __global__ __launch_bounds__(kPixelTile) void pixels_kernel(ScanArgs a, GeomArgs
 #pragma unroll
         for (int d = 0; d < U; ++d) {
             const double u_next = edge_position(g, py, pz, k + d + 1, sr, f.c, e0, invw);
-            const PlanD e = make_plan(u_prev, u_next, B);
+            const PlanD e = make_plan<(sizeof(Acc) == 8)>(u_prev, u_next, B);
             const Acc dI = (Acc)((int)ring[d] - (int)ring[(d + 1) % U]);
             const Acc f0 = (Acc)(e.f0 * scale), fm = (Acc)(e.fm * scale), f1 = (Acc)(e.f1 * scale);
             const int bh = e.bl + e.nb - 1;
@@ -337,7 +341,7 @@ __global__ __launch_bounds__(kPixelTile) void pixels_kernel(ScanArgs a, GeomArgs
     for (int d = 0; d < U; ++d) {
         if (k + d < N - 1) {
             const double u_next = edge_position(g, py, pz, k + d + 1, sr, f.c, e0, invw);
-            const PlanD e = make_plan(u_prev, u_next, B);
+            const PlanD e = make_plan<(sizeof(Acc) == 8)>(u_prev, u_next, B);
             const Acc dI = (Acc)((int)ring[d] - (int)ring[(d + 1) % U]);
             const Acc f0 = (Acc)(e.f0 * scale), fm = (Acc)(e.fm * scale), f1 = (Acc)(e.f1 * scale);
             const int bh = e.bl + e.nb - 1;
