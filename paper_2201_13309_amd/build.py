@@ -66,6 +66,26 @@ def build_h5(verbose: bool = False) -> str:
     return H5_LIB_PATH
 
 
+C_CONSUMER_SRC = os.path.join(ROOT, "tests", "c", "abi_consumer.c")
+C_CONSUMER = os.path.join(ROOT, "tests", "c", "abi_consumer")
+
+
+def build_c_consumer(verbose: bool = False) -> str:
+    """gcc build of the plain-C test caller of the ABI (links libdr.so by rpath)."""
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    cmd = ["gcc", "-std=c11", "-O2", "-Wall", f"-I{INCLUDE}", f"-I{os.path.join(rocm, 'include')}",
+           "-D__HIP_PLATFORM_AMD__", C_CONSUMER_SRC, "-o", C_CONSUMER + ".tmp", f"-L{PKG}", "-ldr",
+           "-Wl,-rpath,$ORIGIN/../../paper_2201_13309_amd", f"-L{os.path.join(rocm, 'lib')}",
+           "-lamdhip64", f"-Wl,-rpath,{os.path.join(rocm, 'lib')}", "-lm"]
+    r = subprocess.run(cmd, stderr=subprocess.PIPE, stdout=subprocess.PIPE)
+    if r.returncode != 0:
+        raise RuntimeError("gcc failed for abi_consumer.c:\n" + r.stderr.decode(errors="replace"))
+    os.replace(C_CONSUMER + ".tmp", C_CONSUMER)
+    if verbose:
+        print("built", C_CONSUMER)
+    return C_CONSUMER
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     with ThreadPoolExecutor(len(SOURCES)) as ex:
@@ -85,6 +105,7 @@ def build(verbose: bool = False) -> str:
     if verbose:
         print("built", LIB_PATH)
     build_h5(verbose)
+    build_c_consumer(verbose)
     return LIB_PATH
 
 
