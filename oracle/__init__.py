@@ -48,10 +48,10 @@ def load(path: Optional[str] = None):
         lib.oracle_bin_profile.argtypes = [p, p, i32, i32, i32, d, p, i64]
         lib.oracle_bin_profile.restype = None
         lib.oracle_reconstruct.argtypes = [i32, i32, p, p, p, p, d, p, i32, p, i32, d, d, i32,
-                                           p, i32, i32, p, p, p, i32]
+                                           p, p, i32, i32, p, p, p, i32]
         lib.oracle_reconstruct.restype = i32
         lib.oracle_reconstruct_pixels.argtypes = [i32, i32, p, p, p, p, d, p, i32, p, i32, d, d,
-                                                  i32, p, p, p, i64, p, p, p, i32]
+                                                  i32, p, p, p, p, i64, p, p, p, i32]
         lib.oracle_reconstruct_pixels.restype = i32
         lib.oracle_activity.argtypes = [p, i32, i64, p]
         lib.oracle_activity.restype = None
@@ -108,10 +108,14 @@ def _geom_args(scan):
     pxyz = None if det.pixel_xyz is None else _f64(det.pixel_xyz)
     centers = _f64(wire.centers)
     axis = _f64(getattr(wire, "axis", (1.0, 0.0, 0.0)))
-    keep = (origin, u, v, pxyz, centers, axis)
+    w = getattr(wire, "weights", None)
+    w = None if w is None else _f64(w)
+    assert w is None or w.shape == (centers.shape[0],)
+    keep = (origin, u, v, pxyz, centers, axis, w)
     args = (int(det.nx), int(det.ny), _p(origin), _p(u), _p(v), _p(pxyz), float(wire.radius),
             _p(axis), int(centers.shape[0]), _p(centers), int(grid.n_bins),
-            float(grid.first_center), float(grid.width), int(getattr(wire, "edge", EDGE_LEADING)))
+            float(grid.first_center), float(grid.width), int(getattr(wire, "edge", EDGE_LEADING)),
+            _p(w))
     return args, keep
 
 

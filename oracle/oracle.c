@@ -45,6 +45,9 @@
  *              ov = min(hi, b+1) - max(lo, b) > 0 and
  *              len = hi - lo; parts outside [0, n_bins) are dropped; a
  *              zero-length interval puts dI_k into bin floor(lo).
+ *   weights    optional per-step weights w_k (beam-monitor normalisation, a
+ *              reading: the paper has none): every sample becomes I_k * w_k
+ *              (one FP64 rounding) before the differences are taken.
  *   totals     tot[b] = sum over pixels of out[b][p].
  *   selection  (the paper's second experiment processes a percentage of the
  *              pixels, Sec. IV, without stating which; the reading used
@@ -245,6 +248,7 @@ static int pixel_profile(double py, double pz, const double* Ik, int n_steps,
 /*
  * Full reconstruction of detector rows [row0, row0 + nrows).
  *   edge    EDGE_LEADING, EDGE_TRAILING or EDGE_BOTH
+ *   step_weight  [n_steps] per-step sample weights, or NULL (all 1)
  *   images  [n_steps][ny][nx] uint16, step slowest
  *   out     [n_bins][nrows][nx] FP64, overwritten
  *   totals  [n_bins] FP64 sums over the processed pixels, or NULL
@@ -254,7 +258,7 @@ static int pixel_profile(double py, double pz, const double* Ik, int n_steps,
 int oracle_reconstruct(int nx, int ny, const double* origin, const double* u, const double* v,
                        const double* pixel_xyz, double radius, const double* axis, int n_steps,
                        const double* centers, int n_bins, double first_center, double width,
-                       int edge,
+                       int edge, const double* step_weight,
                        const uint16_t* images, int row0, int nrows, double* out, double* totals,
                        int32_t* bins, int nthreads)
 {
@@ -288,7 +292,10 @@ int oracle_reconstruct(int nx, int ny, const double* origin, const double* u, co
                 int64_t q = (int64_t)jr * nx + i;
                 double py, pz;
                 pixel_center(&fr, nx, origin, u, v, pixel_xyz, p, &py, &pz);
-                for (int k = 0; k < n_steps; ++k) Ik[k] = (double)images[(int64_t)k * plane_in + p];
+                for (int k = 0; k < n_steps; ++k) {
+                    Ik[k] = (double)images[(int64_t)k * plane_in + p];
+                    if (step_weight) Ik[k] = Ik[k] * step_weight[k];
+                }
                 if (pixel_profile(py, pz, Ik, n_steps, wyz, radius, fr.c, e0, invw, n_bins, edge,
                                   out + q, plane_out, uk) != ORACLE_OK) {
 #pragma omp atomic write
@@ -327,6 +334,7 @@ int oracle_reconstruct_pixels(int nx, int ny, const double* origin, const double
                               const double* v, const double* pixel_xyz, double radius,
                               const double* axis, int n_steps, const double* centers, int n_bins,
                               double first_center, double width, int edge,
+                              const double* step_weight,
                               const uint16_t* images, const uint16_t* series,
                               const int64_t* pixels, int64_t npix, double* out, int32_t* bins,
                               double* upos, int nthreads)
@@ -362,9 +370,11 @@ int oracle_reconstruct_pixels(int nx, int ny, const double* origin, const double
             }
             double py, pz;
             pixel_center(&fr, nx, origin, u, v, pixel_xyz, p, &py, &pz);
-            for (int k = 0; k < n_steps; ++k)
+            for (int k = 0; k < n_steps; ++k) {
                 Ik[k] = series ? (double)series[n * n_steps + k]
                                : (images ? (double)images[(int64_t)k * plane_in + p] : 0.0);
+                if (step_weight) Ik[k] = Ik[k] * step_weight[k];
+            }
             if (pixel_profile(py, pz, Ik, n_steps, wyz, radius, fr.c, e0, invw, n_bins, edge, o,
                               1, uk) != ORACLE_OK) {
 #pragma omp atomic write

@@ -102,6 +102,7 @@ class Wire:
     centers: np.ndarray  # [n_steps][3] um
     axis: np.ndarray = field(default_factory=lambda: np.array([1.0, 0.0, 0.0]))
     edge: int = EDGE_LEADING  # which wire edge the reconstruction uses
+    weights: Optional[np.ndarray] = None  # per-step sample weights (monitor normalisation)
 
     @property
     def n_steps(self) -> int:

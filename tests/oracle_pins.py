@@ -524,9 +524,56 @@ def pin_select_top(lib):
                 ranks_before = (ap > aq) | ((ap == aq) & (p[:, None] < q[None, :]))
                 assert ranks_before.all(), (n, k)
 
+
+def pin_step_weights(lib):
+    """Per-step weights (monitor normalisation): a stack whose images were
+    multiplied by monitor factors m_k in {1, 2}, weighted by 1/m_k, gives the
+    unmodulated reconstruction bit for bit (and the unweighted modulated one
+    differs); weights of 4 scale the output by exactly 4; with arbitrary
+    weights each pixel whose sweep lies inside the grid conserves
+    I_0 w_0 - I_{N-1} w_{N-1}."""
+    base = synth.tiny(24, 3, 21, 61, seed=61, n_src=5, dark=50.0, noise=False)
+    base.images = (base.images // 2).astype(np.uint16)
+    base.grid = synth.DepthGrid(100, -74.5, 1.0)  # holds the sweeps of both edges
+    rng = np.random.default_rng(61)
+    m = rng.integers(1, 3, base.wire.n_steps).astype(np.float64)
+    modulated = (base.images.astype(np.int64) * m[:, None, None].astype(np.int64)).astype(np.uint16)
+    for edge in (0, 1, 2):
+        w0 = synth.Wire(base.wire.radius, base.wire.centers, edge=edge)
+        plain = synth.Scan("p", base.detector, w0, base.grid, None, 0.0, False, 0,
+                           images=base.images)
+        ref, _, _ = oracle.reconstruct(plain, lib=lib)
+        ww = synth.Wire(base.wire.radius, base.wire.centers, edge=edge, weights=1.0 / m)
+        norm = synth.Scan("n", base.detector, ww, base.grid, None, 0.0, False, 0,
+                          images=modulated)
+        got, _, _ = oracle.reconstruct(norm, lib=lib)
+        assert np.array_equal(got, ref), edge
+        raw, _, _ = oracle.reconstruct(synth.Scan("r", base.detector, w0, base.grid, None, 0.0,
+                                                  False, 0, images=modulated), lib=lib)
+        assert not np.array_equal(raw, ref)
+        pix = np.arange(24 * 3)
+        gp, _, _ = oracle.reconstruct_pixels(norm, pix, want_bins=False, lib=lib)
+        assert np.array_equal(gp.T.reshape(ref.shape), ref), edge
+        w4 = synth.Wire(base.wire.radius, base.wire.centers, edge=edge,
+                        weights=np.full(base.wire.n_steps, 4.0))
+        g4, _, _ = oracle.reconstruct(synth.Scan("4", base.detector, w4, base.grid, None, 0.0,
+                                                 False, 0, images=base.images), lib=lib)
+        assert np.array_equal(g4, 4.0 * ref), edge
+    wr = rng.uniform(0.5, 2.0, base.wire.n_steps)
+    sc = synth.Scan("w", base.detector, synth.Wire(base.wire.radius, base.wire.centers,
+                                                   weights=wr),
+                    base.grid, None, 0.0, False, 0, images=base.images)
+    out, _, bins = oracle.reconstruct(sc, want_bins=True, lib=lib)
+    I = base.images.reshape(base.wire.n_steps, -1).astype(np.float64)
+    want = I[0] * wr[0] - I[-1] * wr[-1]
+    inside = (bins.min(1) >= 0) & (bins.max(1) <= base.grid.n_bins - 1)
+    assert inside.sum() > 10
+    sums = out.reshape(base.grid.n_bins, -1).sum(0)
+    assert np.allclose(sums[inside], want[inside], rtol=0, atol=1e-9 * np.abs(I).sum(0).max())
+
 ALL_PINS = [
     pin_closed_form_level, pin_zero_radius, pin_bisection, pin_mirror, pin_edge_sign,
     pin_hand_profiles, pin_conservation_random, pin_conservation_scan, pin_brute_force,
     pin_planted_sources, pin_poisson_recovery, pin_tilted_axis_bisection,
-    pin_tilted_axis_brute_force, pin_activity, pin_select_top,
+    pin_tilted_axis_brute_force, pin_activity, pin_select_top, pin_step_weights,
 ]

@@ -62,6 +62,10 @@ MUTANTS = [
      "for (int k = 0; k + 2 < n_steps; ++k) {"),
     ("select_ascending", "return g_sel_act[a] > g_sel_act[b] ? -1 : 1;",
      "return g_sel_act[a] < g_sel_act[b] ? -1 : 1;"),
+    ("weight_wrong_step", "if (step_weight) Ik[k] = Ik[k] * step_weight[k];",
+     "if (step_weight) Ik[k] = Ik[k] * step_weight[n_steps - 1 - k];"),
+    ("weight_ignored", "if (step_weight) Ik[k] = Ik[k] * step_weight[k];",
+     "if (step_weight) Ik[k] = Ik[k];"),
     ("select_ties_high", "    return a < b ? -1 : (a > b ? 1 : 0);\n}\nstatic int idx_cmp",
      "    return a > b ? -1 : (a < b ? 1 : 0);\n}\nstatic int idx_cmp"),
 ]
