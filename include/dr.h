@@ -154,6 +154,18 @@ dr_status dr_ctx_destroy(dr_ctx ctx);
 dr_status dr_geometry_init(dr_ctx ctx, const dr_detector* det, const dr_wire* wire,
                            const dr_depth_grid* grid, dr_geom* out);
 
+/* Per-step sample weights (beam-monitor normalisation; the paper describes
+ * none): with weights w[n_steps] set, every sample becomes I_k * w_k (FP64)
+ * before the differences are taken, I_k*w_k - I_{k+1}*w_{k+1} formed in FP64
+ * and rounded once for the FP32 accumulation; w_k = mean(m)/m_k normalises
+ * by monitor counts m_k.  NULL removes them.  Copied; waits for the device
+ * work already enqueued.  With weights the reconstruction uses one launch
+ * shape (1 pixel per lane, 4 waves, prefetch 16; dr_set_tile and dr_autotune
+ * do not change it), and batches and serving return DR_E_UNSUPPORTED.
+ * Errors: DR_E_INVAL (NULL geometry, a non-finite weight), DR_E_BUSY
+ * (serving requests in flight). */
+dr_status dr_geometry_set_step_weights(dr_geom geom, const double* weights);
+
 /* Which path a geometry takes: DR_PATH_ROWS (per-row FP64 bin tables built
  * once, HBM-bound kernel) or DR_PATH_PIXELS (positions computed per pixel on
  * the fly).  Errors: DR_E_INVAL for NULL arguments. */

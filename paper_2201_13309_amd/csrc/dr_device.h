@@ -442,9 +442,21 @@ __device__ __forceinline__ TileAddr<Acc> list_tile_addr(const ScanArgs& a, const
     return ta;
 }
 
+// Difference of two consecutive samples: exact in integers, or with per-step
+// weights (NORM) both weighted samples formed in FP64 (one rounding each, the
+// oracle's order) and their difference rounded once to Acc.
+template <typename Acc, bool NORM>
+__device__ __forceinline__ Acc sample_diff(int i0, int i1, const double* wk, int k)
+{
+    if constexpr (NORM)
+        return (Acc)((double)i0 * wk[k] - (double)i1 * wk[k + 1]);
+    else
+        return (Acc)(i0 - i1);
+}
+
 // Non-monotone rows: zero the tile's bins, then read-modify-write every
 // contribution in step order (each lane touches only its own pixels).
-template <typename Acc, int PPL, int WAVES>
+template <typename Acc, int PPL, int WAVES, bool NORM>
 __device__ __forceinline__ void process_tile_generic(const ScanArgs& a, int row,
                                                      const TileAddr<Acc>& ta, PlanLds<Acc>& L)
 {
@@ -472,8 +484,9 @@ __device__ __forceinline__ void process_tile_generic(const ScanArgs& a, int row,
             const int bh = bl + nb - 1;
 #pragma unroll
             for (int q = 0; q < PPL; ++q) {
-                const Acc dI = (Acc)((int)ip[(int64_t)k * ta.istep + q] -
-                                     (int)ip[(int64_t)(k + 1) * ta.istep + q]);
+                const Acc dI = sample_diff<Acc, NORM>((int)ip[(int64_t)k * ta.istep + q],
+                                                      (int)ip[(int64_t)(k + 1) * ta.istep + q],
+                                                      a.wk, k);
                 for (int b = bl; b <= bh; ++b) {
                     const Acc f = (b == bl) ? f0 : ((b == bh) ? f1 : fm);
                     Acc* o = op + (int64_t)b * plane + q;
@@ -506,7 +519,7 @@ __device__ __forceinline__ void process_tile_generic(const ScanArgs& a, int row,
 // unconditional, so the prefetch ring stays in registers), the open bin in
 // registers, each touched bin stored once as soon as the edge has passed it,
 // untouched bins zeroed after the last load.
-template <typename Acc, int PPL, int WAVES, int PF, bool NB2, bool ADD>
+template <typename Acc, int PPL, int WAVES, int PF, bool NB2, bool ADD, bool NORM>
 __device__ __forceinline__ void process_tile_mono(const ScanArgs& a, int row,
                                                   const TileAddr<Acc>& ta, PlanLds<Acc>& L,
                                                   int cls)
@@ -558,14 +571,15 @@ __device__ __forceinline__ void process_tile_mono(const ScanArgs& a, int row,
             pwin.add(cb, wave_total(act ? s : (Acc)0), lane);
         }
     };
-    auto interval = [&](int kk, const V& prev, const V& cur) {
+    auto interval = [&](int kk, int k, const V& prev, const V& cur) {
         const int nb = uni(L.nb[kk]);
         if (nb == 0) return;
         const int bl = uni(L.bl[kk]);
         const Acc f0 = uni(L.f0[kk]), fm = uni(L.fm[kk]), f1 = uni(L.f1[kk]);
         Acc dI[PPL];
 #pragma unroll
-        for (int q = 0; q < PPL; ++q) dI[q] = (Acc)(pix<PPL>(prev, q) - pix<PPL>(cur, q));
+        for (int q = 0; q < PPL; ++q)
+            dI[q] = sample_diff<Acc, NORM>(pix<PPL>(prev, q), pix<PPL>(cur, q), a.wk, k);
         const int bh = bl + nb - 1;
         auto visit = [&](int b, Acc f) {
             if (b != cb) {
@@ -624,14 +638,14 @@ __device__ __forceinline__ void process_tile_mono(const ScanArgs& a, int row,
         for (; kk + U <= nk; kk += U) {
 #pragma unroll
             for (int d = 0; d < U; ++d) {
-                interval(kk + d, ring[d], ring[(d + 1) % U]);
+                interval(kk + d, kc + kk + d, ring[d], ring[(d + 1) % U]);
                 ring[d] = load(min(kc + kk + d + U, N - 1));
             }
         }
 #pragma unroll
         for (int d = 0; d < U; ++d) {
             if (kk + d < nk) {
-                interval(kk + d, ring[d], ring[(d + 1) % U]);
+                interval(kk + d, kc + kk + d, ring[d], ring[(d + 1) % U]);
                 ring[d] = load(min(kc + kk + d + U, N - 1));
             }
         }
@@ -654,18 +668,20 @@ __device__ __forceinline__ void process_tile_mono(const ScanArgs& a, int row,
 }
 
 // ADD: the scan's pass is 2 (compile-time, so that a single pass carries no
-// code for adding onto an earlier output)
-template <typename Acc, int PPL, int WAVES, int PF, bool ADD>
+// code for adding onto an earlier output).  NORM: per-step sample weights
+// (a.wk) apply.
+template <typename Acc, int PPL, int WAVES, int PF, bool ADD, bool NORM = false>
 __device__ __forceinline__ void process_tile(const ScanArgs& a, int row, const TileAddr<Acc>& ta,
                                              PlanLds<Acc>& L)
 {
     const int cls = a.row_class[row];
     if (cls == kRowGeneric)
-        process_tile_generic<Acc, PPL, WAVES>(a, row, ta, L);
+        process_tile_generic<Acc, PPL, WAVES, NORM>(a, row, ta, L);
     else if (cls & kRowNarrow)
-        process_tile_mono<Acc, PPL, WAVES, PF, true, ADD>(a, row, ta, L, cls);
+        process_tile_mono<Acc, PPL, WAVES, PF, true, ADD, NORM>(a, row, ta, L, cls);
     else  // intervals wider than two bins: rare, a short prefetch suffices
-        process_tile_mono<Acc, PPL, WAVES, (PF < 4 ? PF : 4), false, ADD>(a, row, ta, L, cls);
+        process_tile_mono<Acc, PPL, WAVES, (PF < 4 ? PF : 4), false, ADD, NORM>(a, row, ta, L,
+                                                                                cls);
 }
 
 template <int PPL, int WAVES, int PF, bool ADD>
@@ -678,33 +694,44 @@ __global__ __launch_bounds__(64 * WAVES) void rows_f32_kernel(ScanArgs a)
                                              L);
 }
 
-template <bool ADD>
+template <bool ADD, bool NORM>
 __global__ __launch_bounds__(256) void rows_f64_kernel(ScanArgs a)
 {
     __shared__ PlanLds<double> L;
     const int row = a.row_begin + (int)(blockIdx.x / (unsigned)a.tiles_per_row);
     const int tile = (int)(blockIdx.x % (unsigned)a.tiles_per_row);
-    process_tile<double, 1, 4, 4, ADD>(a, row, row_tile_addr<double, 1, 4>(a, row, tile), L);
+    process_tile<double, 1, 4, 4, ADD, NORM>(a, row, row_tile_addr<double, 1, 4>(a, row, tile), L);
+}
+
+// Scans with per-step sample weights: one launch shape (a pixel per lane,
+// four waves, 16 steps in flight).
+template <bool ADD>
+__global__ __launch_bounds__(256) void rows_norm_f32_kernel(ScanArgs a)
+{
+    __shared__ PlanLds<float> L;
+    const int row = a.row_begin + (int)(blockIdx.x / (unsigned)a.tiles_per_row);
+    const int tile = (int)(blockIdx.x % (unsigned)a.tiles_per_row);
+    process_tile<float, 1, 4, 16, ADD, true>(a, row, row_tile_addr<float, 1, 4>(a, row, tile), L);
 }
 
 // Pixel lists: one workgroup per list tile (tiles [tile_first, tile_first +
 // gridDim.x) of the list's table).
-template <int PF, bool ADD>
+template <int PF, bool ADD, bool NORM>
 __global__ __launch_bounds__(256) void list_f32_kernel(ScanArgs a, ListArgs l)
 {
     __shared__ PlanLds<float> L;
     const int64_t t = l.tile_first + blockIdx.x;
     const int row = l.tile_row[t];
-    process_tile<float, 1, 4, PF, ADD>(a, row, list_tile_addr<float, 4>(a, l, t, row), L);
+    process_tile<float, 1, 4, PF, ADD, NORM>(a, row, list_tile_addr<float, 4>(a, l, t, row), L);
 }
 
-template <bool ADD>
+template <bool ADD, bool NORM>
 __global__ __launch_bounds__(256) void list_f64_kernel(ScanArgs a, ListArgs l)
 {
     __shared__ PlanLds<double> L;
     const int64_t t = l.tile_first + blockIdx.x;
     const int row = l.tile_row[t];
-    process_tile<double, 1, 4, 4, ADD>(a, row, list_tile_addr<double, 4>(a, l, t, row), L);
+    process_tile<double, 1, 4, 4, ADD, NORM>(a, row, list_tile_addr<double, 4>(a, l, t, row), L);
 }
 
 // Persistent grid: workgroups pull (scan, tile) items until the queue is dry.

@@ -46,6 +46,7 @@ struct ScanArgs {
     void* partials;       // per-wave partial sums of totals, [slots][n_bins]
     int32_t pass;         // 0: single pass; 1, 2: first and second pass of a two-edge
                           // reconstruction (the second adds onto the first's output)
+    const double* wk;     // [n_steps] per-step sample weights, or null
     // plan tables (row mode)
     const int32_t* bl;
     const int32_t* nb;
@@ -129,6 +130,8 @@ hipError_t launch_totals_f64(const double* partials, int64_t slots, int n_bins, 
                              int work_rows, double* totals, hipStream_t s);
 hipError_t launch_debug_plan(const GeomArgs& g, const int64_t* pixels, int n, int side,
                              int32_t* bins, double* upos, hipStream_t s);
+// scans with per-step sample weights: launch shape (1, 4, 16) only
+hipError_t launch_rows_norm_f32(const ScanArgs& a, hipStream_t s);
 // projected wire table; status bit 4 when the axis is zero or along the beam
 hipError_t launch_project_wire(const GeomArgs& g, double* wire_yz, int* d_status, hipStream_t s);
 // flags[j] = 1 when every pixel of row j has the row's first (eta, xi) bit for

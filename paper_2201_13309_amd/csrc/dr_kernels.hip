@@ -224,7 +224,7 @@ __global__ __launch_bounds__(256) void validate_pixels_kernel(GeomArgs g, int* s
 // l.tile_first + w: lane i holds entry tile_start + i, its output goes to
 // column `entry` of [n_bins][n], and its images are gathered from full frames
 // (pixel index) or read from a compact [N][entries] buffer.
-template <typename Acc, int PF>
+template <typename Acc, int PF, bool NORM>
 __global__ __launch_bounds__(kPixelTile) void pixels_kernel(ScanArgs a, GeomArgs g, int side,
                                                             double scale, ListArgs l)
 {
@@ -327,7 +327,8 @@ __global__ __launch_bounds__(kPixelTile) void pixels_kernel(ScanArgs a, GeomArgs
         for (int d = 0; d < U; ++d) {
             const double u_next = edge_position(g, py, pz, k + d + 1, sr, f.c, e0, invw);
             const PlanD e = make_plan<(sizeof(Acc) == 8)>(u_prev, u_next, B);
-            const Acc dI = (Acc)((int)ring[d] - (int)ring[(d + 1) % U]);
+            const Acc dI =
+                sample_diff<Acc, NORM>((int)ring[d], (int)ring[(d + 1) % U], a.wk, k + d);
             const Acc f0 = (Acc)(e.f0 * scale), fm = (Acc)(e.fm * scale), f1 = (Acc)(e.f1 * scale);
             const int bh = e.bl + e.nb - 1;
             int b = dir > 0 ? e.bl : bh;
@@ -342,7 +343,8 @@ __global__ __launch_bounds__(kPixelTile) void pixels_kernel(ScanArgs a, GeomArgs
         if (k + d < N - 1) {
             const double u_next = edge_position(g, py, pz, k + d + 1, sr, f.c, e0, invw);
             const PlanD e = make_plan<(sizeof(Acc) == 8)>(u_prev, u_next, B);
-            const Acc dI = (Acc)((int)ring[d] - (int)ring[(d + 1) % U]);
+            const Acc dI =
+                sample_diff<Acc, NORM>((int)ring[d], (int)ring[(d + 1) % U], a.wk, k + d);
             const Acc f0 = (Acc)(e.f0 * scale), fm = (Acc)(e.fm * scale), f1 = (Acc)(e.f1 * scale);
             const int bh = e.bl + e.nb - 1;
             int b = dir > 0 ? e.bl : bh;
@@ -411,10 +413,17 @@ hipError_t launch_rows_f64(const ScanArgs& a, hipStream_t s)
     const int64_t rows = a.row_end - a.row_begin;
     if (rows <= 0) return hipSuccess;
     const dim3 grid((unsigned)(rows * a.tiles_per_row));
-    if (a.pass == 2)
-        hipLaunchKernelGGL(rows_f64_kernel<true>, grid, dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL(rows_f64_kernel<false>, grid, dim3(256), 0, s, a);
+    if (a.wk) {
+        if (a.pass == 2)
+            hipLaunchKernelGGL((rows_f64_kernel<true, true>), grid, dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((rows_f64_kernel<false, true>), grid, dim3(256), 0, s, a);
+    } else {
+        if (a.pass == 2)
+            hipLaunchKernelGGL((rows_f64_kernel<true, false>), grid, dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((rows_f64_kernel<false, false>), grid, dim3(256), 0, s, a);
+    }
     return hipGetLastError();
 }
 
@@ -488,8 +497,12 @@ static hipError_t launch_pixels(const ScanArgs& a, const GeomArgs& g, int side, 
     const size_t need = (size_t)a.n_bins * sizeof(Acc);
     const size_t lds = (a.partials && need <= kPixelLdsBytes) ? need : 0;
     const ListArgs none{};
-    hipLaunchKernelGGL((pixels_kernel<Acc, 8>), dim3((unsigned)groups), dim3(kPixelTile), lds, s,
-                       a, g, side, scale, l ? *l : none);
+    if (a.wk)
+        hipLaunchKernelGGL((pixels_kernel<Acc, 8, true>), dim3((unsigned)groups), dim3(kPixelTile),
+                           lds, s, a, g, side, scale, l ? *l : none);
+    else
+        hipLaunchKernelGGL((pixels_kernel<Acc, 8, false>), dim3((unsigned)groups),
+                           dim3(kPixelTile), lds, s, a, g, side, scale, l ? *l : none);
     return hipGetLastError();
 }
 
@@ -521,10 +534,13 @@ hipError_t launch_list_f32(const ScanArgs& a, const ListArgs& l, int64_t n_tiles
 {
     if (n_tiles <= 0) return hipSuccess;
     const dim3 grid((unsigned)n_tiles);
-    if (a.pass == 2)
-        hipLaunchKernelGGL((list_f32_kernel<16, true>), grid, dim3(256), 0, s, a, l);
-    else
-        hipLaunchKernelGGL((list_f32_kernel<16, false>), grid, dim3(256), 0, s, a, l);
+    const int v = (a.pass == 2 ? 1 : 0) + (a.wk ? 2 : 0);
+    switch (v) {
+    case 0: hipLaunchKernelGGL((list_f32_kernel<16, false, false>), grid, dim3(256), 0, s, a, l); break;
+    case 1: hipLaunchKernelGGL((list_f32_kernel<16, true, false>), grid, dim3(256), 0, s, a, l); break;
+    case 2: hipLaunchKernelGGL((list_f32_kernel<16, false, true>), grid, dim3(256), 0, s, a, l); break;
+    default: hipLaunchKernelGGL((list_f32_kernel<16, true, true>), grid, dim3(256), 0, s, a, l); break;
+    }
     return hipGetLastError();
 }
 
@@ -532,10 +548,25 @@ hipError_t launch_list_f64(const ScanArgs& a, const ListArgs& l, int64_t n_tiles
 {
     if (n_tiles <= 0) return hipSuccess;
     const dim3 grid((unsigned)n_tiles);
+    const int v = (a.pass == 2 ? 1 : 0) + (a.wk ? 2 : 0);
+    switch (v) {
+    case 0: hipLaunchKernelGGL((list_f64_kernel<false, false>), grid, dim3(256), 0, s, a, l); break;
+    case 1: hipLaunchKernelGGL((list_f64_kernel<true, false>), grid, dim3(256), 0, s, a, l); break;
+    case 2: hipLaunchKernelGGL((list_f64_kernel<false, true>), grid, dim3(256), 0, s, a, l); break;
+    default: hipLaunchKernelGGL((list_f64_kernel<true, true>), grid, dim3(256), 0, s, a, l); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_rows_norm_f32(const ScanArgs& a, hipStream_t s)
+{
+    const int64_t rows = a.row_end - a.row_begin;
+    if (rows <= 0) return hipSuccess;
+    const dim3 grid((unsigned)(rows * a.tiles_per_row));
     if (a.pass == 2)
-        hipLaunchKernelGGL(list_f64_kernel<true>, grid, dim3(256), 0, s, a, l);
+        hipLaunchKernelGGL(rows_norm_f32_kernel<true>, grid, dim3(256), 0, s, a);
     else
-        hipLaunchKernelGGL(list_f64_kernel<false>, grid, dim3(256), 0, s, a, l);
+        hipLaunchKernelGGL(rows_norm_f32_kernel<false>, grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

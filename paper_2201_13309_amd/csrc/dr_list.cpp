@@ -127,6 +127,7 @@ static ScanArgs list_scan_args(const dr_list l, int p, const uint16_t* img, int6
     a.out = out;
     a.out_plane = l->n;
     a.partials = partials ? (char*)partials + (size_t)p * slots * g->n_bins * elem : nullptr;
+    a.wk = g->weighted ? g->wbuf.as<double>() : nullptr;
     if (g->row_mode) {
         const PlanTables& pt = g->t[p];
         a.bl = pt.bl;

@@ -91,6 +91,7 @@ ScanArgs scan_args(const dr_geom g, const TileCfg& t, int pass, const uint16_t* 
     a.out = out;
     a.out_plane = (int64_t)g->nx * g->ny;
     a.partials = partials ? partials + (size_t)pass * partial_slots(g, t) * g->n_bins : nullptr;
+    a.wk = g->weighted ? g->wbuf.as<double>() : nullptr;
     if (!g->row_mode) return a;
     const PlanTables& pt = g->t[pass];
     a.bl = pt.bl;
@@ -118,6 +119,7 @@ hipError_t enqueue_totals(const dr_geom g, const float* partials, int64_t slots,
 static TileCfg choose_tile(dr_geom g, const void* img, const void* out)
 {
     std::lock_guard<std::mutex> lk(g->mu);
+    if (g->weighted) return TileCfg{1, 4, 16};  // the weighted kernel's one shape
     if ((g->forced || g->tuned) && tile_fits(g, g->tile, img, out)) return g->tile;
     return default_tile(g, img, out);
 }
@@ -425,6 +427,27 @@ dr_status dr_geometry_init(dr_ctx c, const dr_detector* det, const dr_wire* wire
     return ok();
 }
 
+dr_status dr_geometry_set_step_weights(dr_geom g, const double* weights)
+{
+    if (!g) return set_error(DR_E_INVAL, "dr_geometry_set_step_weights: NULL geometry");
+    if (g->inflight.load() != 0)
+        return set_error(DR_E_BUSY, "dr_geometry_set_step_weights: serving requests use it");
+    if (!weights) {
+        g->weighted = false;
+        return ok();
+    }
+    for (int k = 0; k < g->n_steps; ++k)
+        if (!std::isfinite(weights[k]))
+            return set_error(DR_E_INVAL, "dr_geometry_set_step_weights: weights must be finite");
+    DR_HIP(hipSetDevice(g->ctx->device));
+    DR_HIP(hipDeviceSynchronize());  // earlier launches may still read the old weights
+    DR_HIP(g->wbuf.reserve((size_t)g->n_steps * sizeof(double)));
+    DR_HIP(hipMemcpy(g->wbuf.p, weights, (size_t)g->n_steps * sizeof(double),
+                     hipMemcpyHostToDevice));
+    g->weighted = true;
+    return ok();
+}
+
 dr_status dr_geometry_path(dr_geom g, int32_t* path)
 {
     if (!g || !path) return set_error(DR_E_INVAL, "dr_geometry_path: NULL argument");
@@ -470,7 +493,7 @@ dr_status dr_set_tile(dr_geom g, const dr_tile_config* tile)
 static hipError_t launch_f32(const dr_geom g, const TileCfg& t, int p, const ScanArgs& a,
                              hipStream_t s)
 {
-    if (g->row_mode) return launch_rows_f32(t, a, s);
+    if (g->row_mode) return a.wk ? launch_rows_norm_f32(a, s) : launch_rows_f32(t, a, s);
     return launch_pixels_f32(a, g->g, g->side[p], g->scale[p], s);
 }
 
@@ -669,6 +692,10 @@ dr_status dr_autotune(dr_geom g, const uint16_t* images, float* out, dr_tile_con
         if (chosen) *chosen = dr_tile_config{1, kPixelTile / 64, 8, 0};
         return ok();
     }
+    if (g->weighted) {  // one launch shape with step weights
+        if (chosen) *chosen = dr_tile_config{1, 4, 16, 0};
+        return ok();
+    }
     dr_ctx c = g->ctx;
     DR_HIP(hipSetDevice(c->device));
     hipStream_t s = c->stream;
@@ -848,9 +875,10 @@ dr_status dr_batch_create(dr_ctx c, int32_t n, const dr_batch_item* items, int32
             return set_error(DR_E_INVAL, "dr_batch_create: NULL item field");
         if (it.geom->ctx != c)
             return set_error(DR_E_INVAL, "dr_batch_create: geometry of another context");
-        if (!items[i].geom->row_mode)
+        if (!items[i].geom->row_mode || items[i].geom->weighted)
             return set_error(DR_E_UNSUPPORTED,
-                             "dr_batch_create: per-pixel geometries are reconstructed one by one");
+                             "dr_batch_create: per-pixel geometries and geometries with step "
+                             "weights are reconstructed one by one");
         b->items.push_back(it);
         b->geoms.push_back(it.geom);
     }

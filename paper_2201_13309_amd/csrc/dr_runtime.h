@@ -95,6 +95,8 @@ struct dr_geom_s {
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     std::atomic<int> inflight{0};  // serving requests using this geometry
     std::atomic<int> lists{0};     // pixel lists built on this geometry
+    bool weighted = false;         // per-step sample weights set (wbuf holds them)
+    dr::DevBuf wbuf;
 };
 
 struct dr_batch_s {

@@ -458,9 +458,9 @@ dr_status dr_submit(dr_ctx c, dr_geom g, const uint16_t* images, int images_on_d
     if (!c || !g || !images || !out || !ticket)
         return set_error(DR_E_INVAL, "dr_submit: NULL argument");
     if (g->ctx != c) return set_error(DR_E_INVAL, "dr_submit: geometry of another context");
-    if (!g->row_mode)
-        return set_error(DR_E_UNSUPPORTED, "dr_submit: per-pixel geometries are reconstructed "
-                                           "with dr_reconstruct");
+    if (!g->row_mode || g->weighted)
+        return set_error(DR_E_UNSUPPORTED, "dr_submit: per-pixel geometries and geometries with "
+                                           "step weights are reconstructed with dr_reconstruct");
     auto r = std::make_unique<Request>();
     r->g = g;
     r->images = images;

@@ -30,6 +30,7 @@ DR_LAYOUT_FULL, DR_LAYOUT_LIST = 0, 1
 # names exported by libdr.so, as declared in include/dr.h
 ABI_SYMBOLS = (
     "dr_ctx_create", "dr_ctx_destroy", "dr_geometry_init", "dr_geometry_path",
+    "dr_geometry_set_step_weights",
     "dr_geometry_free", "dr_set_tile",
     "dr_autotune", "dr_reconstruct", "dr_reconstruct_f64", "dr_debug_plan", "dr_enable_timing",
     "dr_last_timing", "dr_batch_create", "dr_batch_run", "dr_batch_tile", "dr_batch_free",
@@ -101,6 +102,7 @@ def load(path: Optional[str] = None):
         "dr_ctx_destroy": [vp],
         "dr_geometry_init": [vp, P(dr_detector), P(dr_wire), P(dr_depth_grid), P(vp)],
         "dr_geometry_path": [vp, P(i32)],
+        "dr_geometry_set_step_weights": [vp, vp],
         "dr_geometry_free": [vp],
         "dr_set_tile": [vp, P(dr_tile_config)],
         "dr_autotune": [vp, vp, vp, P(dr_tile_config)],
@@ -220,7 +222,23 @@ def dr_geometry_init(ctx: int, detector, wire, grid) -> int:
                                  ctypes.byref(h))
     del keep_d, keep_w
     _check(rc)
+    weights = getattr(wire, "weights", None)
+    if weights is not None:
+        try:
+            dr_geometry_set_step_weights(h.value, weights)
+        except DRError:
+            dr_geometry_free(h.value)
+            raise
     return h.value
+
+
+def dr_geometry_set_step_weights(geom: int, weights) -> None:
+    """weights: n_steps floats (host), or None to remove them."""
+    if weights is None:
+        _check(load().dr_geometry_set_step_weights(geom, None))
+        return
+    w = np.ascontiguousarray(weights, dtype=np.float64)
+    _check(load().dr_geometry_set_step_weights(geom, ptr(w)))
 
 
 def dr_geometry_path(geom: int) -> int:
