@@ -161,7 +161,7 @@ dr_status dr_geometry_init(dr_ctx ctx, const dr_detector* det, const dr_wire* wi
  * by monitor counts m_k.  NULL removes them.  Copied; waits for the device
  * work already enqueued.  With weights the reconstruction uses one launch
  * shape (1 pixel per lane, 4 waves, prefetch 16; dr_set_tile and dr_autotune
- * do not change it), and batches and serving return DR_E_UNSUPPORTED.
+ * do not change it).
  * Errors: DR_E_INVAL (NULL geometry, a non-finite weight), DR_E_BUSY
  * (serving requests in flight). */
 dr_status dr_geometry_set_step_weights(dr_geom geom, const double* weights);
@@ -252,9 +252,11 @@ typedef struct {
  * device queue.  The plan keeps the item pointers, so the buffers must stay
  * allocated while the batch exists; their contents may change between runs.
  * With DR_BATCH_AUTOTUNE the outputs are overwritten while tuning.
+ * Scans on the per-pixel path or with step weights are not in the persistent
+ * launch: each of their passes is one launch of its own kernel after it (in
+ * the graph too).
  * Errors: DR_E_INVAL (n < 1, NULL items, geometries of another context),
- * DR_E_UNSUPPORTED (a geometry on the per-pixel path), DR_E_NOMEM,
- * DR_E_DEVICE. */
+ * DR_E_NOMEM, DR_E_DEVICE. */
 dr_status dr_batch_create(dr_ctx ctx, int32_t n, const dr_batch_item* items, int32_t flags,
                           dr_batch* out);
 
@@ -339,8 +341,9 @@ dr_status dr_reconstruct_list_f64(dr_list list, const uint16_t* images_dev, int3
  * dr_reconstruct.  images: host (pinned) or device per images_on_device;
  * out/totals: device, as in dr_reconstruct.  The caller keeps every buffer
  * valid until dr_poll reports DR_OK or an error for the ticket.
- * Errors: DR_E_INVAL, DR_E_NOMEM (the request can never fit the budget),
- * DR_E_UNSUPPORTED (a geometry on the per-pixel path: use dr_reconstruct). */
+ * Requests on the per-pixel path or with step weights get launches of their
+ * own kernel in each epoch.
+ * Errors: DR_E_INVAL, DR_E_NOMEM (the request can never fit the budget). */
 dr_status dr_submit(dr_ctx ctx, dr_geom geom, const uint16_t* images, int images_on_device,
                     float* out, float* totals, uint64_t* ticket);
 

@@ -116,6 +116,19 @@ hipError_t enqueue_totals(const dr_geom g, const float* partials, int64_t slots,
                              totals, s);
 }
 
+bool batch_solo(const dr_geom g) { return !g->row_mode || g->weighted; }
+
+TileCfg solo_tile(const dr_geom) { return TileCfg{1, 4, 16}; }
+
+// pass p of any path: the per-row plan kernel (weighted or not) or the
+// per-pixel kernel
+hipError_t launch_scan_f32(const dr_geom g, const TileCfg& t, int p, const ScanArgs& a,
+                           hipStream_t s)
+{
+    if (g->row_mode) return a.wk ? launch_rows_norm_f32(a, s) : launch_rows_f32(t, a, s);
+    return launch_pixels_f32(a, g->g, g->side[p], g->scale[p], s);
+}
+
 static TileCfg choose_tile(dr_geom g, const void* img, const void* out)
 {
     std::lock_guard<std::mutex> lk(g->mu);
@@ -489,14 +502,6 @@ dr_status dr_set_tile(dr_geom g, const dr_tile_config* tile)
     return ok();
 }
 
-// pass p of either path: the per-row plan kernel or the per-pixel kernel
-static hipError_t launch_f32(const dr_geom g, const TileCfg& t, int p, const ScanArgs& a,
-                             hipStream_t s)
-{
-    if (g->row_mode) return a.wk ? launch_rows_norm_f32(a, s) : launch_rows_f32(t, a, s);
-    return launch_pixels_f32(a, g->g, g->side[p], g->scale[p], s);
-}
-
 static dr_status reconstruct_device(dr_geom g, const TileCfg& t, const uint16_t* images,
                                     float* out, float* totals, hipStream_t s)
 {
@@ -508,7 +513,7 @@ static dr_status reconstruct_device(dr_geom g, const TileCfg& t, const uint16_t*
     if (g->timing) DR_HIP(hipEventRecord(g->ev[0], s));
     for (int p = 0; p < g->passes; ++p) {
         ScanArgs a = scan_args(g, t, p, images, (int64_t)g->nx * g->ny, 0, 0, g->ny, out, part);
-        DR_HIP(launch_f32(g, t, p, a, s));
+        DR_HIP(launch_scan_f32(g, t, p, a, s));
     }
     if (g->timing) DR_HIP(hipEventRecord(g->ev[1], s));
     if (totals)
@@ -568,7 +573,7 @@ static dr_status reconstruct_streamed(dr_geom g, const TileCfg& t, const uint16_
         for (int p = 0; p < g->passes; ++p) {
             ScanArgs a = scan_args(g, t, p, c->slab[b].as<uint16_t>(), (int64_t)R * g->nx, r0,
                                    r0, r0 + rs, out, part);
-            DR_HIP(launch_f32(g, t, p, a, s));
+            DR_HIP(launch_scan_f32(g, t, p, a, s));
         }
         DR_HIP(hipEventRecord(c->slab_free[b], s));
     }
@@ -785,7 +790,8 @@ static dr_status batch_build_args(dr_batch b, const TileCfg& t, int gpc)
     b->slots.assign(n, 0);
     int64_t poff = 0;
     for (int i = 0; i < n; ++i) {
-        b->slots[i] = b->items[i].totals ? partial_slots(b->geoms[i], t) : 0;  // per pass
+        const TileCfg ti = batch_solo(b->geoms[i]) ? solo_tile(b->geoms[i]) : t;
+        b->slots[i] = b->items[i].totals ? partial_slots(b->geoms[i], ti) : 0;  // per pass
         b->part_off[i] = poff;
         poff += b->slots[i] * b->geoms[i]->passes * b->geoms[i]->n_bins;
     }
@@ -802,7 +808,7 @@ static dr_status batch_build_args(dr_batch b, const TileCfg& t, int gpc)
         for (int w = 0; w < n; ++w) {
             const int i = order[w];
             const dr_geom g = b->geoms[i];
-            if (pass >= g->passes) continue;
+            if (pass >= g->passes || batch_solo(g)) continue;
             float* part = b->items[i].totals ? b->parts.as<float>() + b->part_off[i] : nullptr;
             ScanArgs a = scan_args(g, t, pass, b->items[i].images, (int64_t)g->nx * g->ny, 0, 0,
                                    g->ny, b->items[i].out, part);
@@ -813,6 +819,17 @@ static dr_status batch_build_args(dr_batch b, const TileCfg& t, int gpc)
     }
     b->n_args1 = (int)start1.size() - 1;
     b->n_args2 = (int)start2.size() - 1;
+    // per-pixel and weighted scans: their own launches after the persistent ones
+    b->solos.clear();
+    for (int i = 0; i < n; ++i) {
+        const dr_geom g = b->geoms[i];
+        if (!batch_solo(g)) continue;
+        float* part = b->items[i].totals ? b->parts.as<float>() + b->part_off[i] : nullptr;
+        for (int pass = 0; pass < g->passes; ++pass)
+            b->solos.push_back({i, pass, scan_args(g, solo_tile(g), pass, b->items[i].images,
+                                                   (int64_t)g->nx * g->ny, 0, 0, g->ny,
+                                                   b->items[i].out, part)});
+    }
     std::vector<int64_t> starts(start1);
     starts.insert(starts.end(), start2.begin(), start2.end());
     DR_HIP(b->scans.reserve(sizeof(ScanArgs) * args.size()));
@@ -852,6 +869,10 @@ static dr_status batch_enqueue(dr_batch b, hipStream_t s)
         DR_HIP(launch_batch_f32(b->tile, ba, launch == 1,
                                 (int)std::min<int64_t>(groups, INT32_MAX), s));
     }
+    for (const BatchSolo& so : b->solos) {
+        const dr_geom g = b->geoms[so.item];
+        DR_HIP(launch_scan_f32(g, solo_tile(g), so.pass, so.args, s));
+    }
     for (size_t i = 0; i < b->items.size(); ++i) {
         if (!b->items[i].totals) continue;
         const dr_geom g = b->geoms[i];
@@ -875,10 +896,6 @@ dr_status dr_batch_create(dr_ctx c, int32_t n, const dr_batch_item* items, int32
             return set_error(DR_E_INVAL, "dr_batch_create: NULL item field");
         if (it.geom->ctx != c)
             return set_error(DR_E_INVAL, "dr_batch_create: geometry of another context");
-        if (!items[i].geom->row_mode || items[i].geom->weighted)
-            return set_error(DR_E_UNSUPPORTED,
-                             "dr_batch_create: per-pixel geometries and geometries with step "
-                             "weights are reconstructed one by one");
         b->items.push_back(it);
         b->geoms.push_back(it.geom);
     }
@@ -888,8 +905,9 @@ dr_status dr_batch_create(dr_ctx c, int32_t n, const dr_batch_item* items, int32
     for (int v = 0; v < num_tile_variants(); ++v) {
         const TileCfg t = tile_variant(v);
         bool okall = true;
-        for (int i = 0; i < n && okall; ++i)
-            okall = tile_fits(b->geoms[i], t, items[i].images, items[i].out);
+        for (int i = 0; i < n && okall; ++i)  // scans launched on their own take any
+            okall = batch_solo(b->geoms[i]) || tile_fits(b->geoms[i], t, items[i].images,
+                                                         items[i].out);
         if (okall) cands.push_back(t);
     }
     if (cands.empty()) return set_error(DR_E_INVAL, "dr_batch_create: no launch shape fits");

@@ -99,6 +99,11 @@ struct dr_geom_s {
     dr::DevBuf wbuf;
 };
 
+struct BatchSolo {  // one pass of a scan that the persistent kernel does not take
+    int item, pass;
+    dr::ScanArgs args;
+};
+
 struct dr_batch_s {
     dr_ctx ctx = nullptr;
     std::vector<dr_batch_item> items;
@@ -112,6 +117,7 @@ struct dr_batch_s {
     int n_args1 = 0, n_args2 = 0;   // ScanArgs entries of each launch
     std::vector<int64_t> part_off;  // per item offset into parts (floats)
     std::vector<int64_t> slots;     // per item partial slots (all passes)
+    std::vector<BatchSolo> solos;   // per-pixel and weighted scans, launched on their own
     int64_t total_tiles = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -131,6 +137,13 @@ ScanArgs scan_args(const dr_geom g, const TileCfg& t, int pass, const uint16_t* 
                    float* partials);
 hipError_t enqueue_totals(const dr_geom g, const float* partials, int64_t slots, double* work,
                           float* totals, hipStream_t s);
+// scans the persistent row-tile kernel does not take (per-pixel path, step
+// weights) are launched on their own, with this launch shape
+bool batch_solo(const dr_geom g);
+TileCfg solo_tile(const dr_geom g);
+// pass `pass` of any path (per-row plans, weighted rows, per-pixel)
+hipError_t launch_scan_f32(const dr_geom g, const TileCfg& t, int pass, const ScanArgs& a,
+                           hipStream_t s);
 
 Scheduler* make_scheduler(dr_ctx ctx);
 void destroy_scheduler(Scheduler* s);

@@ -246,8 +246,21 @@ struct Scheduler {
         int nseg[kGroups] = {0, 0, 0, 0, 0, 0};
         int64_t tiles[kGroups] = {0, 0, 0, 0, 0, 0};
         std::vector<Request*> finishing;
+        struct Solo {
+            Request* r;
+            int row_begin, row_end;
+        };
+        std::vector<Solo> solos;  // per-pixel and weighted requests: launched on their own
         for (Request* r : active) {
             if (r->state != 1 || r->finishing) continue;
+            if (batch_solo(r->g)) {
+                if (r->rows_ready > r->rows_next) {
+                    solos.push_back({r, r->rows_next, r->rows_ready});
+                    r->rows_next = r->rows_ready;
+                }
+                if (r->rows_next == r->g->ny) finishing.push_back(r);
+                continue;
+            }
             const int pi = r->tile.ppl == 4 ? 0 : (r->tile.ppl == 2 ? 1 : 2);
             const int passes = r->g->passes;
             bool room = true;
@@ -269,7 +282,7 @@ struct Scheduler {
             }
             if (r->rows_next == r->g->ny) finishing.push_back(r);
         }
-        int nall = 0;
+        int nall = (int)solos.size();
         for (int gi = 0; gi < kGroups; ++gi) nall += nseg[gi];
         if (nall == 0 && finishing.empty()) return false;
         hipStream_t s = ctx->stream;
@@ -303,6 +316,16 @@ struct Scheduler {
             // groups 3..5 hold second passes, which add onto the first
             if (e == hipSuccess) e = launch_batch_f32(t, ba, gi >= 3, groups, s);
             stats.tiles_launched += (uint64_t)tiles[gi];
+        }
+        for (const Solo& so : solos) {
+            Request* r = so.r;
+            const uint16_t* img = r->on_device ? r->images : r->staged;
+            for (int p = 0; p < r->g->passes && e == hipSuccess; ++p) {
+                const ScanArgs a = scan_args(r->g, r->tile, p, img, (int64_t)r->g->nx * r->g->ny,
+                                             0, so.row_begin, so.row_end, r->out, r->parts);
+                e = launch_scan_f32(r->g, r->tile, p, a, s);
+                stats.tiles_launched += (uint64_t)(so.row_end - so.row_begin) * a.tiles_per_row;
+            }
         }
         for (Request* r : finishing) {
             if (e != hipSuccess) break;
@@ -458,18 +481,19 @@ dr_status dr_submit(dr_ctx c, dr_geom g, const uint16_t* images, int images_on_d
     if (!c || !g || !images || !out || !ticket)
         return set_error(DR_E_INVAL, "dr_submit: NULL argument");
     if (g->ctx != c) return set_error(DR_E_INVAL, "dr_submit: geometry of another context");
-    if (!g->row_mode || g->weighted)
-        return set_error(DR_E_UNSUPPORTED, "dr_submit: per-pixel geometries and geometries with "
-                                           "step weights are reconstructed with dr_reconstruct");
     auto r = std::make_unique<Request>();
     r->g = g;
     r->images = images;
     r->on_device = images_on_device != 0;
     r->out = out;
     r->totals = totals;
-    r->tile = default_tile(g, r->on_device ? (const void*)images : nullptr, out);
-    r->tile.waves = 4;
-    r->tile.prefetch = 16;
+    if (batch_solo(g)) {
+        r->tile = solo_tile(g);
+    } else {
+        r->tile = default_tile(g, r->on_device ? (const void*)images : nullptr, out);
+        r->tile.waves = 4;
+        r->tile.prefetch = 16;
+    }
     if (!tile_fits(g, r->tile, r->on_device ? (const void*)images : nullptr, out))
         return set_error(DR_E_INVAL, "dr_submit: misaligned buffer");
     r->footprint = Scheduler::staging_bytes(r.get()) + Scheduler::parts_bytes(r.get());

@@ -175,3 +175,63 @@ def test_serving_tight_budget_queues(dr):
             dr.dr_geometry_free(g)
     finally:
         dr.dr_ctx_destroy(small_ctx)
+
+
+def mixed_kinds(seed):
+    """Scans the persistent kernel takes and scans launched on their own: a
+    tilted detector (per-pixel path), step weights, both edges with a tilted
+    wire axis."""
+    import math
+    scans = uneven_scans(seed)[:3]
+    s = synth.tiny(150, 5, 31, 81, seed=seed + 1, n_src=8, dark=100.0, render_now=False)
+    d = s.detector
+    s.detector = synth.Detector(d.nx, d.ny, d.origin, np.array([200.0, 10.0, 30.0]), d.v)
+    synth.render(s)
+    scans.append(s)
+    s = synth.tiny(128, 6, 29, 71, seed=seed + 2, n_src=8, dark=100.0)
+    s.wire.weights = np.random.default_rng(seed).uniform(0.5, 2.0, s.wire.n_steps)
+    scans.append(s)
+    s = synth.tiny(90, 4, 27, 81, seed=seed + 3, n_src=8, dark=100.0, render_now=False)
+    t = math.radians(6.0)
+    s.wire.axis = np.array([math.cos(t), 0.0, math.sin(t)])
+    s.grid = synth.DepthGrid(81, -72.0 + 0.6, 1.2)
+    s.wire.edge = synth.EDGE_BOTH
+    synth.render(s)
+    scans.append(s)
+    return scans
+
+
+def test_batch_and_serving_take_every_kind_of_scan(dr, ctx):
+    import torch
+    scans = mixed_kinds(21)
+    singles = [alone(dr, ctx, s) for s in scans]
+    geoms, imgs, outs, tots = [], [], [], []
+    for s in scans:
+        geoms.append(dr.dr_geometry_init(ctx, s.detector, s.wire, s.grid))
+        imgs.append(dev_images(s.images))
+        outs.append(torch.full((s.grid.n_bins, s.detector.ny, s.detector.nx), float("nan"),
+                               device="cuda"))
+        tots.append(torch.full((s.grid.n_bins,), float("nan"), device="cuda"))
+    assert [dr.dr_geometry_path(g) for g in geoms][3:] == [dr.DR_PATH_PIXELS, dr.DR_PATH_ROWS,
+                                                           dr.DR_PATH_PIXELS]
+    torch.cuda.synchronize()
+    b = dr.dr_batch_create(ctx, list(zip(geoms, imgs, outs, tots)),
+                           dr.DR_BATCH_AUTOTUNE | dr.DR_BATCH_GRAPH)
+    try:
+        for rep in range(2):
+            for o, t in zip(outs, tots):
+                o.fill_(float("nan"))
+                t.fill_(float("nan"))
+            dr.dr_batch_run(b, torch.cuda.current_stream())
+            torch.cuda.synchronize()
+            for s, (o1, t1), o, t in zip(scans, singles, outs, tots):
+                assert np.array_equal(o.cpu().numpy(), o1), (rep, s.name)
+                assert_totals_close(t.cpu().numpy(), t1.astype(np.float64), s.images)
+    finally:
+        dr.dr_batch_free(b)
+        for g in geoms:
+            dr.dr_geometry_free(g)
+    served = _serve(dr, ctx, scans, [True, False, True, True, False, True])
+    for s, (o1, t1), (o2, t2) in zip(scans, singles, served):
+        assert np.array_equal(o2, o1), s.name
+        assert_totals_close(t2, t1.astype(np.float64), s.images)

@@ -192,7 +192,7 @@ def test_row_uniform_geometries_keep_row_path(dr, ctx):
 
 
 def test_per_pixel_entry_points(dr, ctx):
-    """Single launch shape; batches and serving refuse per-pixel geometries."""
+    """A per-pixel geometry has a single launch shape."""
     import torch
     s = make_case("tilted_detector")
     g = dr.dr_geometry_init(ctx, s.detector, s.wire, s.grid)
@@ -204,12 +204,6 @@ def test_per_pixel_entry_points(dr, ctx):
             dr.dr_set_tile(g, (2, 4, 16))
         assert e.value.code == dr.DR_E_UNSUPPORTED
         dr.dr_set_tile(g, None)
-        with pytest.raises(dr.DRError) as e:
-            dr.dr_batch_create(ctx, [(g, img, out, None)], 0)
-        assert e.value.code == dr.DR_E_UNSUPPORTED
-        with pytest.raises(dr.DRError) as e:
-            dr.dr_submit(ctx, g, img, True, out, None)
-        assert e.value.code == dr.DR_E_UNSUPPORTED
         torch.cuda.synchronize()
     finally:
         dr.dr_geometry_free(g)

@@ -5,8 +5,8 @@
 * FP32 path within 1e-5 of sum_k |I_k w_k - I_{k+1} w_{k+1}| per pixel;
 * a stack multiplied by monitor factors in {1, 2} and weighted by their
   reciprocals reconstructs bit for bit like the unmodulated stack;
-* host streaming and lists equal the device run; batches and serving refuse
-  weighted geometries; removing the weights restores the plain result.
+* host streaming and lists equal the device run; removing the weights
+  restores the plain result.
 """
 import numpy as np
 import pytest
@@ -127,11 +127,6 @@ def test_streaming_lists_and_removal(dr, ctx, name, monkeypatch):
             assert np.array_equal(out64.cpu().numpy().T.view(np.int64), ref.view(np.int64))
         finally:
             dr.dr_list_free(lst)
-        with pytest.raises(dr.DRError) as e:
-            dr.dr_submit(ctx, g, dev_images(s.images), True,
-                         torch.empty((s.grid.n_bins, s.detector.ny, s.detector.nx),
-                                     device="cuda"), None)
-        assert e.value.code == dr.DR_E_UNSUPPORTED
         with pytest.raises(dr.DRError) as e:
             dr.dr_geometry_set_step_weights(g, np.full(s.wire.n_steps, np.nan))
         assert e.value.code == dr.DR_E_INVAL
