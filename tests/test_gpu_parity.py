@@ -77,6 +77,12 @@ def make_case(name):
         s.detector = synth.Detector(40, 6, s.detector.origin, s.detector.u, s.detector.v,
                                     pixel_xyz=xyz)
         return s
+    if name == "many_bins":      # 20000 bins: partial-total windows and zero fill at scale
+        return synth.tiny(64, 3, 41, 20000, seed=114, n_src=6, dark=100.0, width=0.002)
+    if name == "wide_8191x2":    # long odd row: many tiles, ragged tail, one pixel per lane
+        return synth.tiny(8191, 2, 25, 61, seed=115, n_src=30, dark=100.0, pitch=50.0)
+    if name == "single_row":
+        return synth.tiny(700, 1, 33, 81, seed=116, n_src=6, dark=100.0)
     if name.startswith("trailing_") or name.startswith("both_"):
         edge, base = name.split("_", 1)
         s = make_case(base)
@@ -90,7 +96,8 @@ def make_case(name):
 CASES = ["config1", "ragged_301x7", "wide_2500x5", "long_1500_steps", "decreasing",
          "non_monotone", "narrow_grid", "coarse_steps", "degenerate_1x1", "pixel_table",
          "trailing_config1", "trailing_decreasing", "both_config1", "both_ragged_301x7",
-         "both_decreasing", "both_non_monotone", "both_long_1500_steps"]
+         "both_decreasing", "both_non_monotone", "both_long_1500_steps", "many_bins",
+         "wide_8191x2", "single_row", "both_many_bins"]
 
 
 @pytest.mark.parametrize("name", CASES)
