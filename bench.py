@@ -530,6 +530,24 @@ def main():
                      "totals_ms": float(np.mean(tms)), "algorithmic_bytes": alg,
                      "kernel_source_sha256_16": digest},
     }
+    # reference for the byte mix: torch's int16 -> float32 conversion of the same
+    # stack reads 2 B and writes 4 B per element, as the kernel does (N = B here)
+    if out.numel() == dev.numel():
+        flat_in, flat_out = dev.view(-1), out.view(-1)
+        flat_out.copy_(flat_in)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(3):
+            flat_out.copy_(flat_in)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ref_ms = ev0.elapsed_time(ev1) / 3
+        ref_bytes = dev.numel() * 6
+        result["roofline"]["stream_reference"] = {
+            "op": "torch int16->float32 conversion of the same stack (2 B read + 4 B written "
+                  "per element)",
+            "ms": ref_ms, "GBps": ref_bytes / (ref_ms * 1e-3) / 1e9, "bytes": ref_bytes}
+        log(f"stream reference: {ref_ms:.3f} ms, {ref_bytes / ref_ms / 1e6:.0f} GB/s")
     if not args.no_e2e:
         # host images over PCIe, row slabs double-buffered against the kernel
         torch.cuda.synchronize()
