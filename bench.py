@@ -88,6 +88,54 @@ def cpu_baseline(scan, target_s: float):
                       f"({work:.3e} pixel-wire-steps, FP64, {spent:.1f} s)"}
 
 
+def run_size_sweep(torch, synth, dr, ctx, s, host, dev, out, tot, stream, steps: int):
+    """The paper's data-size experiment on this machine: stacks of 2.1, 2.7,
+    3.6 and 5.2 GB (the first 250, 322, 429 and 620 steps of the 2048x2048
+    scan, same detector and depth grid), GPU time from HBM and from pinned
+    host memory, and the oracle's time estimated from a 64-row sample on the
+    host's cores; the ratio GPU / CPU is the paper's metric."""
+    import oracle
+    d, grid = s.detector, s.grid
+    cores = min(16, os.cpu_count() or 1)
+    res = []
+    for n_steps in (250, 322, 429, 620):
+        wire = synth.Wire(s.wire.radius, np.ascontiguousarray(s.wire.centers[:n_steps]))
+        g = dr.dr_geometry_init(ctx, d, wire, grid)
+        try:
+            dv, hv = dev[:n_steps], host[:n_steps]
+            dr.dr_reconstruct(g, dv, True, out, tot, stream)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(steps):
+                dr.dr_reconstruct(g, dv, True, out, tot, stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            gpu_ms = e0.elapsed_time(e1) / steps
+            t0 = time.perf_counter()
+            dr.dr_reconstruct(g, hv, False, out, tot, stream)
+            torch.cuda.synchronize()
+            host_ms = (time.perf_counter() - t0) * 1e3
+        finally:
+            dr.dr_geometry_free(g)
+        scan = synth.Scan("sweep", d, wire, grid, None, 0.0, False, 0)
+        img = hv.numpy().view(np.uint16)
+        t0 = time.perf_counter()
+        oracle.reconstruct(scan, images=img, row0=0, nrows=64, nthreads=cores)
+        cpu_rate = 64 * d.nx * n_steps / (time.perf_counter() - t0)
+        work = d.nx * d.ny * n_steps
+        cpu_s = work / cpu_rate
+        res.append({"input_GB": 2 * work / 1e9, "steps": n_steps, "gpu_ms": gpu_ms,
+                    "gpu_from_host_ms": host_ms, "cpu_s_estimate": cpu_s,
+                    "gpu_over_cpu": gpu_ms * 1e-3 / cpu_s,
+                    "gpu_from_host_over_cpu": host_ms * 1e-3 / cpu_s})
+        log(f"size {2 * work / 1e9:.1f} GB: GPU {gpu_ms:.2f} ms (from host {host_ms:.0f} ms), "
+            f"CPU oracle ~{cpu_s:.1f} s on {cores} threads")
+    return {"note": "the paper's dataset sizes; GPU / CPU time is its metric (25-30% on its "
+                    "Fermi GPU against a 4-core Xeon); CPU time from a 64-row oracle sample",
+            "cores": cores, "sizes": res}
+
+
 def run_per_pixel(torch, synth, dr, ctx, s, dev, out, tot, stream, steps: int):
     """The per-pixel path at the same size: the detector's columns tilted 0.3
     degrees out of the x axis (u gains a z part), so no two pixels of a row
@@ -421,6 +469,7 @@ def main():
     ap.add_argument("--no-per-pixel", action="store_true")
     ap.add_argument("--no-fraction", action="store_true")
     ap.add_argument("--no-files", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-rate", type=float, default=20.0)
@@ -560,6 +609,9 @@ def main():
                                 "note": "pinned host images streamed in row slabs; PCIe-bound"}
         log(f"end-to-end (PCIe) {dt * 1e3:.1f} ms")
     dr.dr_geometry_free(g)
+    if not args.no_sweep and args.workload == "config3":
+        result["size_sweep"] = run_size_sweep(torch, synth, dr, ctx, s, host, dev, out, tot,
+                                              stream, max(2, args.steps // 2))
     if not args.no_per_pixel:
         result["per_pixel"] = run_per_pixel(torch, synth, dr, ctx, s, dev, out, tot, stream,
                                             max(2, args.steps // 2))
