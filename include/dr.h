@@ -163,7 +163,8 @@ dr_status dr_geometry_init(dr_ctx ctx, const dr_detector* det, const dr_wire* wi
  * shape (1 pixel per lane, 4 waves, prefetch 16; dr_set_tile and dr_autotune
  * do not change it).
  * Errors: DR_E_INVAL (NULL geometry, a non-finite weight), DR_E_BUSY
- * (serving requests in flight). */
+ * (serving requests in flight, or a batch built on the geometry: batches
+ * keep the launch plan they were built with). */
 dr_status dr_geometry_set_step_weights(dr_geom geom, const double* weights);
 
 /* Which path a geometry takes: DR_PATH_ROWS (per-row FP64 bin tables built
@@ -174,7 +175,8 @@ dr_status dr_geometry_set_step_weights(dr_geom geom, const double* weights);
 dr_status dr_geometry_path(dr_geom geom, int32_t* path);
 
 /* Free a geometry.  Waits for the device work already enqueued on it.
- * DR_E_BUSY while serving requests that use it are in flight. */
+ * DR_E_BUSY while serving requests that use it are in flight, or while
+ * pixel lists or batches built on it exist. */
 dr_status dr_geometry_free(dr_geom geom);
 
 /* Force a launch shape for this geometry (tile-invariance tests, manual

@@ -445,6 +445,8 @@ dr_status dr_geometry_set_step_weights(dr_geom g, const double* weights)
     if (!g) return set_error(DR_E_INVAL, "dr_geometry_set_step_weights: NULL geometry");
     if (g->inflight.load() != 0)
         return set_error(DR_E_BUSY, "dr_geometry_set_step_weights: serving requests use it");
+    if (g->batches.load() != 0)  // batches keep the launch plan they were built with
+        return set_error(DR_E_BUSY, "dr_geometry_set_step_weights: a batch uses it");
     if (!weights) {
         g->weighted = false;
         return ok();
@@ -475,6 +477,8 @@ dr_status dr_geometry_free(dr_geom g)
         return set_error(DR_E_BUSY, "dr_geometry_free: serving requests still use it");
     if (g->lists.load() != 0)
         return set_error(DR_E_BUSY, "dr_geometry_free: pixel lists still use it");
+    if (g->batches.load() != 0)
+        return set_error(DR_E_BUSY, "dr_geometry_free: batches still use it");
     DR_HIP(hipSetDevice(g->ctx->device));
     DR_HIP(hipDeviceSynchronize());
     for (int i = 0; i < 3; ++i)
@@ -898,6 +902,7 @@ dr_status dr_batch_create(dr_ctx c, int32_t n, const dr_batch_item* items, int32
             return set_error(DR_E_INVAL, "dr_batch_create: geometry of another context");
         b->items.push_back(it);
         b->geoms.push_back(it.geom);
+        it.geom->batches++;  // given back when the batch is deleted
     }
     DR_HIP(hipSetDevice(c->device));
     // launch shapes valid for every scan

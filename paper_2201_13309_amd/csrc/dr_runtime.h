@@ -95,6 +95,7 @@ struct dr_geom_s {
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     std::atomic<int> inflight{0};  // serving requests using this geometry
     std::atomic<int> lists{0};     // pixel lists built on this geometry
+    std::atomic<int> batches{0};   // batch items that use this geometry
     bool weighted = false;         // per-step sample weights set (wbuf holds them)
     dr::DevBuf wbuf;
 };
@@ -105,6 +106,10 @@ struct BatchSolo {  // one pass of a scan that the persistent kernel does not ta
 };
 
 struct dr_batch_s {
+    ~dr_batch_s()
+    {
+        for (dr_geom g : geoms) g->batches--;
+    }
     dr_ctx ctx = nullptr;
     std::vector<dr_batch_item> items;
     std::vector<dr_geom> geoms;

@@ -235,3 +235,23 @@ def test_batch_and_serving_take_every_kind_of_scan(dr, ctx):
     for s, (o1, t1), (o2, t2) in zip(scans, singles, served):
         assert np.array_equal(o2, o1), s.name
         assert_totals_close(t2, t1.astype(np.float64), s.images)
+
+
+def test_batch_keeps_its_geometries(dr, ctx):
+    """A batch keeps the launch plan it was built with: while it exists its
+    geometries can be neither freed nor given step weights."""
+    import torch
+    s = uneven_scans(31)[0]
+    g = dr.dr_geometry_init(ctx, s.detector, s.wire, s.grid)
+    out = torch.empty((s.grid.n_bins, s.detector.ny, s.detector.nx), device="cuda")
+    b = dr.dr_batch_create(ctx, [(g, dev_images(s.images), out, None)], 0)
+    try:
+        for call in (lambda: dr.dr_geometry_set_step_weights(g, np.ones(s.wire.n_steps)),
+                     lambda: dr.dr_geometry_free(g)):
+            with pytest.raises(dr.DRError) as e:
+                call()
+            assert e.value.code == dr.DR_E_BUSY
+    finally:
+        dr.dr_batch_free(b)
+    dr.dr_geometry_set_step_weights(g, np.ones(s.wire.n_steps))
+    dr.dr_geometry_free(g)
