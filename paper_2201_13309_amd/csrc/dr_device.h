@@ -309,20 +309,35 @@ __device__ __forceinline__ double uni(double x)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-template <typename Acc> struct PlanLds {
-    int bl[kPlanChunk];
-    int nb[kPlanChunk];
-    Acc f0[kPlanChunk];
-    Acc fm[kPlanChunk];
-    Acc f1[kPlanChunk];
+template <typename Acc, int CH = kPlanChunk> struct PlanLds {
+    int bl[CH];
+    int nb[CH];
+    Acc f0[CH];
+    Acc fm[CH];
+    Acc f1[CH];
 };
 
-template <typename Acc>
+// WT (wave tiles): each wave owns its tile and its plan buffer; the waves of
+// a workgroup never wait for each other, and a wave orders its own LDS
+// writes before its reads.
+template <bool WT>
+__device__ __forceinline__ void tile_sync()
+{
+    if constexpr (WT) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
+template <typename Acc, int CH = kPlanChunk, bool WT = false>
 __device__ __forceinline__ void stage_plan(const ScanArgs& a, int row, int kc, int nk,
-                                           PlanLds<Acc>& L)
+                                           PlanLds<Acc, CH>& L)
 {
     const int64_t base = (int64_t)row * (a.n_steps - 1) + kc;
-    for (int e = threadIdx.x; e < nk; e += blockDim.x) {
+    auto copy = [&](int e) {
         L.bl[e] = a.bl[base + e];
         L.nb[e] = a.nb[base + e];
         if constexpr (sizeof(Acc) == 4) {
@@ -334,6 +349,11 @@ __device__ __forceinline__ void stage_plan(const ScanArgs& a, int row, int kc, i
             L.fm[e] = a.dm[base + e];
             L.f1[e] = a.d1[base + e];
         }
+    };
+    if constexpr (WT) {
+        for (int e = (int)(threadIdx.x & 63); e < nk; e += 64) copy(e);
+    } else {
+        for (int e = threadIdx.x; e < nk; e += blockDim.x) copy(e);
     }
 }
 
@@ -412,21 +432,23 @@ __device__ __forceinline__ TileAddr<Acc> row_tile_addr(const ScanArgs& a, int ro
     return t;
 }
 
-// Tile t of a pixel list: entries [tile_start, tile_start + tile_count), all
-// in one detector row, one pixel per lane, lane i holding entry
-// (tile_start rounded down to kListAlign) + i so that every wave reads and
-// writes whole aligned lines; the output is [n_bins][n] in list order.  Images are full frames (gathered by pixel) or compact [N][entries]
-// in list order, the buffer holding entries from entry_base on.
-template <typename Acc, int WAVES>
-__device__ __forceinline__ TileAddr<Acc> list_tile_addr(const ScanArgs& a, const ListArgs& l,
+// Wave tile t of a pixel list: entries [tile_start, tile_start + tile_count)
+// of one detector row, at most 64 from the start rounded down to kListAlign;
+// lane i holds entry (start rounded down) + i, so the wave reads and writes
+// whole aligned lines; the output is [n_bins][n] in list order.  Images are
+// compact [N][entries] in list order (the buffer holding entries from
+// entry_base on) or gathered from full frames.  One partial-total row per
+// wave tile.
+template <typename Acc>
+__device__ __forceinline__ TileAddr<Acc> list_wave_addr(const ScanArgs& a, const ListArgs& l,
                                                         int64_t t, int row)
 {
-    const int tid = threadIdx.x, wave = tid >> 6;
+    const int lane = (int)(threadIdx.x & 63);
     const int64_t e0 = l.tile_start[t];
     const int64_t base = e0 & ~(int64_t)(kListAlign - 1);  // lane 0's entry
     TileAddr<Acc> ta;
-    ta.act = base + tid >= e0 && base + tid < e0 + l.tile_count[t];
-    const int64_t e = ta.act ? base + tid : e0;
+    ta.act = base + lane >= e0 && base + lane < e0 + l.tile_count[t];
+    const int64_t e = ta.act ? base + lane : e0;
     if (l.compact) {
         ta.ibase = a.img;
         ta.ioff = (uint32_t)(e - l.entry_base);
@@ -437,8 +459,8 @@ __device__ __forceinline__ TileAddr<Acc> list_tile_addr(const ScanArgs& a, const
     ta.istep = a.img_step;
     ta.obase = (Acc*)a.out;
     ta.plane = a.out_plane;
-    ta.ooff = (uint32_t)(base + tid);
-    ta.part = a.partials ? (Acc*)a.partials + (t * WAVES + wave) * a.n_bins : nullptr;
+    ta.ooff = (uint32_t)(base + lane);
+    ta.part = a.partials ? (Acc*)a.partials + t * a.n_bins : nullptr;
     return ta;
 }
 
@@ -456,9 +478,9 @@ __device__ __forceinline__ Acc sample_diff(int i0, int i1, const double* wk, int
 
 // Non-monotone rows: zero the tile's bins, then read-modify-write every
 // contribution in step order (each lane touches only its own pixels).
-template <typename Acc, int PPL, int WAVES, bool NORM>
+template <typename Acc, int PPL, int WAVES, bool NORM, int CH, bool WT>
 __device__ __forceinline__ void process_tile_generic(const ScanArgs& a, int row,
-                                                     const TileAddr<Acc>& ta, PlanLds<Acc>& L)
+                                                     const TileAddr<Acc>& ta, PlanLds<Acc, CH>& L)
 {
     const int tid = threadIdx.x, lane = tid & 63;
     (void)tid;
@@ -471,13 +493,17 @@ __device__ __forceinline__ void process_tile_generic(const ScanArgs& a, int row,
         for (int b = 0; b < B; ++b)
 #pragma unroll
             for (int q = 0; q < PPL; ++q) op[(int64_t)b * plane + q] = (Acc)0;
-    for (int kc = 0; kc < nint; kc += kPlanChunk) {
-        const int nk = min(kPlanChunk, nint - kc);
-        __syncthreads();
-        stage_plan<Acc>(a, row, kc, nk, L);
-        __syncthreads();
+    for (int kc = 0; kc < nint; kc += CH) {
+        const int nk = min(CH, nint - kc);
+        tile_sync<WT>();
+        stage_plan<Acc, CH, WT>(a, row, kc, nk, L);
+        tile_sync<WT>();
         for (int kk = 0; kk < nk; ++kk) {
-            const int bl = uni(L.bl[kk]), nb = uni(L.nb[kk]);
+            int bl = uni(L.bl[kk]), nb = uni(L.nb[kk]);
+            if constexpr (WT) {  // keep every address inside the output, whatever was read
+                bl = min(max(bl, 0), B - 1);
+                nb = min(max(nb, 0), B - bl);
+            }
             if (nb == 0 || !act) continue;
             const Acc f0 = uni(L.f0[kk]), fm = uni(L.fm[kk]), f1 = uni(L.f1[kk]);
             const int k = kc + kk;
@@ -519,9 +545,10 @@ __device__ __forceinline__ void process_tile_generic(const ScanArgs& a, int row,
 // unconditional, so the prefetch ring stays in registers), the open bin in
 // registers, each touched bin stored once as soon as the edge has passed it,
 // untouched bins zeroed after the last load.
-template <typename Acc, int PPL, int WAVES, int PF, bool NB2, bool ADD, bool NORM>
+template <typename Acc, int PPL, int WAVES, int PF, bool NB2, bool ADD, bool NORM, int CH,
+          bool WT>
 __device__ __forceinline__ void process_tile_mono(const ScanArgs& a, int row,
-                                                  const TileAddr<Acc>& ta, PlanLds<Acc>& L,
+                                                  const TileAddr<Acc>& ta, PlanLds<Acc, CH>& L,
                                                   int cls)
 {
     using V = typename U16V<PPL>::T;
@@ -572,9 +599,13 @@ __device__ __forceinline__ void process_tile_mono(const ScanArgs& a, int row,
         }
     };
     auto interval = [&](int kk, int k, const V& prev, const V& cur) {
-        const int nb = uni(L.nb[kk]);
+        int nb = uni(L.nb[kk]);
         if (nb == 0) return;
-        const int bl = uni(L.bl[kk]);
+        int bl = uni(L.bl[kk]);
+        if constexpr (WT) {  // keep every address inside the output, whatever was read
+            bl = min(max(bl, 0), B - 1);
+            nb = min(max(nb, 0), B - bl);
+        }
         const Acc f0 = uni(L.f0[kk]), fm = uni(L.fm[kk]), f1 = uni(L.f1[kk]);
         Acc dI[PPL];
 #pragma unroll
@@ -624,16 +655,16 @@ __device__ __forceinline__ void process_tile_mono(const ScanArgs& a, int row,
     // k % U (step k) and (k+1) % U (step k+1), then slot k % U is refilled
     // with step k + U.  Steps past the end re-read the last image (unused).
     constexpr int U = PF + 1;
-    constexpr int KCU = (kPlanChunk / U) * U;  // plan chunk, a whole number of rings
+    constexpr int KCU = (CH / U) * U;  // plan chunk, a whole number of rings
     V ring[U];
 #pragma unroll
     for (int d = 0; d < U; ++d) ring[d] = load(min(d, N - 1));
 
     for (int kc = 0; kc < nint; kc += KCU) {
         const int nk = min(KCU, nint - kc);
-        __syncthreads();
-        stage_plan<Acc>(a, row, kc, nk, L);
-        __syncthreads();
+        tile_sync<WT>();
+        stage_plan<Acc, CH, WT>(a, row, kc, nk, L);
+        tile_sync<WT>();
         int kk = 0;
         for (; kk + U <= nk; kk += U) {
 #pragma unroll
@@ -670,18 +701,19 @@ __device__ __forceinline__ void process_tile_mono(const ScanArgs& a, int row,
 // ADD: the scan's pass is 2 (compile-time, so that a single pass carries no
 // code for adding onto an earlier output).  NORM: per-step sample weights
 // (a.wk) apply.
-template <typename Acc, int PPL, int WAVES, int PF, bool ADD, bool NORM = false>
+template <typename Acc, int PPL, int WAVES, int PF, bool ADD, bool NORM = false,
+          int CH = kPlanChunk, bool WT = false>
 __device__ __forceinline__ void process_tile(const ScanArgs& a, int row, const TileAddr<Acc>& ta,
-                                             PlanLds<Acc>& L)
+                                             PlanLds<Acc, CH>& L)
 {
     const int cls = a.row_class[row];
     if (cls == kRowGeneric)
-        process_tile_generic<Acc, PPL, WAVES, NORM>(a, row, ta, L);
+        process_tile_generic<Acc, PPL, WAVES, NORM, CH, WT>(a, row, ta, L);
     else if (cls & kRowNarrow)
-        process_tile_mono<Acc, PPL, WAVES, PF, true, ADD, NORM>(a, row, ta, L, cls);
+        process_tile_mono<Acc, PPL, WAVES, PF, true, ADD, NORM, CH, WT>(a, row, ta, L, cls);
     else  // intervals wider than two bins: rare, a short prefetch suffices
-        process_tile_mono<Acc, PPL, WAVES, (PF < 4 ? PF : 4), false, ADD, NORM>(a, row, ta, L,
-                                                                                cls);
+        process_tile_mono<Acc, PPL, WAVES, (PF < 4 ? PF : 4), false, ADD, NORM, CH, WT>(a, row, ta,
+                                                                                        L, cls);
 }
 
 template <int PPL, int WAVES, int PF, bool ADD>
@@ -714,24 +746,35 @@ __global__ __launch_bounds__(256) void rows_norm_f32_kernel(ScanArgs a)
     process_tile<float, 1, 4, 16, ADD, true>(a, row, row_tile_addr<float, 1, 4>(a, row, tile), L);
 }
 
-// Pixel lists: one workgroup per list tile (tiles [tile_first, tile_first +
-// gridDim.x) of the list's table).
+// Pixel lists (per-row plans): four independent wave tiles per workgroup,
+// tiles [tile_first, tile_end) of the list's table; each wave stages its own
+// row's plan, kWaveChunk intervals at a time.
+constexpr int kWaveChunk = 256;
+
+template <typename Acc, int PF, bool ADD, bool NORM>
+__device__ __forceinline__ void list_wave_tile(const ScanArgs& a, const ListArgs& l,
+                                               PlanLds<Acc, kWaveChunk>* L)
+{
+    const int wave = (int)(threadIdx.x >> 6);
+    const int64_t t = l.tile_first + (int64_t)blockIdx.x * 4 + wave;
+    if (t >= l.tile_end) return;  // no workgroup barrier follows
+    const int row = l.tile_row[t];
+    process_tile<Acc, 1, 1, PF, ADD, NORM, kWaveChunk, true>(
+        a, row, list_wave_addr<Acc>(a, l, t, row), L[wave]);
+}
+
 template <int PF, bool ADD, bool NORM>
 __global__ __launch_bounds__(256) void list_f32_kernel(ScanArgs a, ListArgs l)
 {
-    __shared__ PlanLds<float> L;
-    const int64_t t = l.tile_first + blockIdx.x;
-    const int row = l.tile_row[t];
-    process_tile<float, 1, 4, PF, ADD, NORM>(a, row, list_tile_addr<float, 4>(a, l, t, row), L);
+    __shared__ PlanLds<float, kWaveChunk> L[4];
+    list_wave_tile<float, PF, ADD, NORM>(a, l, L);
 }
 
 template <bool ADD, bool NORM>
 __global__ __launch_bounds__(256) void list_f64_kernel(ScanArgs a, ListArgs l)
 {
-    __shared__ PlanLds<double> L;
-    const int64_t t = l.tile_first + blockIdx.x;
-    const int row = l.tile_row[t];
-    process_tile<double, 1, 4, 4, ADD, NORM>(a, row, list_tile_addr<double, 4>(a, l, t, row), L);
+    __shared__ PlanLds<double, kWaveChunk> L[4];
+    list_wave_tile<double, 4, ADD, NORM>(a, l, L);
 }
 
 // Persistent grid: workgroups pull (scan, tile) items until the queue is dry.

@@ -75,8 +75,9 @@ struct GeomArgs {
 };
 
 // A pixel list as seen by the list kernels: entries sorted by pixel index and
-// cut into tiles of at most 256 entries that lie in one detector row (the
-// per-pixel path ignores the row).
+// cut into tiles that lie in one detector row: wave tiles of at most 64
+// entries for the per-row plan path, 256-entry tiles for the per-pixel path
+// (which ignores the row).
 struct ListArgs {
     const int64_t* pixels;      // [n] flat pixel indices j*nx + i, increasing
     const int32_t* tile_row;    // [n_tiles]
@@ -84,6 +85,7 @@ struct ListArgs {
     const int32_t* tile_count;  // [n_tiles] entries in the tile
     int64_t n;
     int64_t tile_first;         // first tile of this launch
+    int64_t tile_end;           // one past its last tile
     int32_t compact;            // images are [N][entries] in list order, else full frames
     int64_t entry_base;         // first entry held by a compact image buffer
 };

@@ -530,10 +530,12 @@ hipError_t launch_list_pixels_f64(const ScanArgs& a, const GeomArgs& g, int side
     return launch_pixels<double>(a, g, side, scale, &l, n_tiles, s);
 }
 
-hipError_t launch_list_f32(const ScanArgs& a, const ListArgs& l, int64_t n_tiles, hipStream_t s)
+hipError_t launch_list_f32(const ScanArgs& a, const ListArgs& lt, int64_t n_tiles, hipStream_t s)
 {
     if (n_tiles <= 0) return hipSuccess;
-    const dim3 grid((unsigned)n_tiles);
+    ListArgs l = lt;
+    l.tile_end = l.tile_first + n_tiles;
+    const dim3 grid((unsigned)((n_tiles + 3) / 4));  // four wave tiles per workgroup
     const int v = (a.pass == 2 ? 1 : 0) + (a.wk ? 2 : 0);
     switch (v) {
     case 0: hipLaunchKernelGGL((list_f32_kernel<16, false, false>), grid, dim3(256), 0, s, a, l); break;
@@ -544,10 +546,12 @@ hipError_t launch_list_f32(const ScanArgs& a, const ListArgs& l, int64_t n_tiles
     return hipGetLastError();
 }
 
-hipError_t launch_list_f64(const ScanArgs& a, const ListArgs& l, int64_t n_tiles, hipStream_t s)
+hipError_t launch_list_f64(const ScanArgs& a, const ListArgs& lt, int64_t n_tiles, hipStream_t s)
 {
     if (n_tiles <= 0) return hipSuccess;
-    const dim3 grid((unsigned)n_tiles);
+    ListArgs l = lt;
+    l.tile_end = l.tile_first + n_tiles;
+    const dim3 grid((unsigned)((n_tiles + 3) / 4));  // four wave tiles per workgroup
     const int v = (a.pass == 2 ? 1 : 0) + (a.wk ? 2 : 0);
     switch (v) {
     case 0: hipLaunchKernelGGL((list_f64_kernel<false, false>), grid, dim3(256), 0, s, a, l); break;

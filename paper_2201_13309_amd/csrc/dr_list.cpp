@@ -34,10 +34,10 @@ static size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
 // entries (128 bytes), the last one at the end of the list
 constexpr int64_t kRunAlign = kListAlign;
 
-// Tile table of a validated list held in l->pixels: per-row plan path, tiles
-// inside one detector row, each ending at most kListTile entries after its
-// start rounded down to kListAlign; per-pixel path, aligned runs of kListTile
-// consecutive entries.  Synchronous (reads the row starts back).
+// Tile table of a validated list held in l->pixels: per-row plan path, wave
+// tiles inside one detector row, each ending at the next multiple of
+// kListAlign entries; per-pixel path, aligned runs of kListTile consecutive
+// entries.  Synchronous (reads the row starts back).
 static dr_status build_tiles(dr_list l, hipStream_t s)
 {
     const dr_geom g = l->g;
@@ -53,11 +53,12 @@ static dr_status build_tiles(dr_list l, hipStream_t s)
         DR_HIP(hipMemcpyAsync(h.data(), starts.p, h.size() * sizeof(int64_t),
                               hipMemcpyDeviceToHost, s));
         DR_HIP(hipStreamSynchronize(s));
-        // a tile ends kListTile entries after its start rounded down to
-        // kListAlign, so the tiles after a row's first start aligned
+        // wave tiles: a tile ends at the next multiple of kListAlign entries
+        // (at most 64 lanes from its start rounded down), so all but a row's
+        // first start aligned
         for (int j = 0; j < g->ny; ++j)
             for (int64_t e = h[j]; e < h[j + 1];) {
-                const int64_t end = std::min<int64_t>(h[j + 1], e - e % kListAlign + kListTile);
+                const int64_t end = std::min<int64_t>(h[j + 1], e - e % kListAlign + kListAlign);
                 rows.push_back(j);
                 l->h_start.push_back(e);
                 l->h_count.push_back((int32_t)(end - e));
@@ -103,7 +104,7 @@ static ListArgs list_args(const dr_list l, int32_t compact)
 
 // workgroups of one pass, and partial-total rows of one pass
 static int64_t list_groups(const dr_list l) { return l->n_tiles; }
-static int64_t list_slots(const dr_list l) { return l->n_tiles * (l->g->row_mode ? 4 : 1); }
+static int64_t list_slots(const dr_list l) { return l->n_tiles; }  // one row per (wave) tile
 
 // Scan arguments of pass p over a list: images img (full frames: step stride
 // nx*ny; compact: step stride `img_step` entries), output [n_bins][n].
