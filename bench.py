@@ -165,7 +165,7 @@ def run_per_pixel(torch, synth, dr, ctx, s, dev, out, tot, stream, steps: int):
     work = d.nx * d.ny * s.wire.n_steps
     log(f"per-pixel path: {ms:.2f} ms/step")
     return {"value": work / (ms * 1e-3), "unit": UNIT, "ms_per_step": ms, "kernel_ms": kms,
-            "kernel": "pixels_kernel", "steps": steps,
+            "kernel": "pixels_f32_kernel", "steps": steps,
             "geometry": "detector columns tilted 0.3 deg out of x (u = (200, 0, 1) um): "
                         "positions computed per pixel in FP64 on the fly"}
 

@@ -214,154 +214,6 @@ __global__ __launch_bounds__(256) void validate_pixels_kernel(GeomArgs g, int* s
     if (bad) atomicOr(status, bad);
 }
 
-// Per-pixel path: one lane per pixel of a row tile of kPixelTile pixels.  Each
-// lane computes its own FP64 positions step by step, plans the interval, and
-// streams its bins in the direction its edge moves (bins are visited in order
-// then; a bin already stored and visited again is read, added to and
-// rewritten, so any sequence of positions is handled).  Partial totals are
-// accumulated per workgroup in LDS and written as one row per workgroup.
-// With a pixel list (l.pixels set) workgroup w takes list tile
-// l.tile_first + w: lane i holds entry tile_start + i, its output goes to
-// column `entry` of [n_bins][n], and its images are gathered from full frames
-// (pixel index) or read from a compact [N][entries] buffer.
-template <typename Acc, int PF, bool NORM>
-__global__ __launch_bounds__(kPixelTile) void pixels_kernel(ScanArgs a, GeomArgs g, int side,
-                                                            double scale, ListArgs l)
-{
-    extern __shared__ __align__(16) unsigned char dyn_lds[];
-    const int tid = threadIdx.x;
-    const int N = a.n_steps, B = a.n_bins;
-    const bool add_on = a.pass == 2;
-    const bool tot = a.partials != nullptr;
-    bool act;
-    int64_t pixel, slot;              // pixel index; partial-total row of the workgroup
-    const uint16_t* ip;               // the lane's step-0 sample
-    Acc* op;                          // the lane's bin 0
-    if (l.pixels) {
-        const int64_t t = l.tile_first + blockIdx.x;
-        const int64_t e0 = l.tile_start[t];
-        const int64_t base = e0 & ~(int64_t)(kListAlign - 1);
-        act = base + tid >= e0 && base + tid < e0 + l.tile_count[t];
-        const int64_t e = act ? base + tid : e0;
-        pixel = l.pixels[e];
-        ip = l.compact ? a.img + (e - l.entry_base) : a.img + pixel;
-        op = (Acc*)a.out + base + tid;
-        slot = t;
-    } else {
-        const int row = a.row_begin + (int)(blockIdx.x / (unsigned)a.tiles_per_row);
-        const int tile = (int)(blockIdx.x % (unsigned)a.tiles_per_row);
-        const int col = tile * kPixelTile + tid;
-        act = col < a.nx;
-        pixel = (int64_t)row * a.nx + (act ? col : 0);
-        ip = a.img + (int64_t)(row - a.row_base) * a.img_row + (act ? col : 0);
-        op = (Acc*)a.out + (int64_t)row * a.nx + col;
-        slot = (int64_t)row * a.tiles_per_row + tile;
-    }
-    // the workgroup's partial-total row: summed in LDS when it fits, else in
-    // place in its own row of the partials buffer
-    Acc* const gp = tot ? (Acc*)a.partials + slot * B : nullptr;
-    const bool in_lds = (size_t)B * sizeof(Acc) <= kPixelLdsBytes;
-    Acc* const ltot = in_lds ? reinterpret_cast<Acc*>(dyn_lds) : gp;
-    if (tot)
-        for (int b = tid; b < B; b += kPixelTile) ltot[b] = (Acc)0;
-    __syncthreads();
-
-    const Frame f = axis_frame(g);
-    double py, pz;
-    pixel_key(g, f, pixel, py, pz);
-    const int s = side ? -leading_sign(g, py, pz) : leading_sign(g, py, pz);
-    const double sr = (double)s * g.radius;
-    const double e0 = g.first_center - g.width / 2.0;
-    const double invw = 1.0 / g.width;
-    const double u_first = edge_position(g, py, pz, 0, sr, f.c, e0, invw);
-    const double u_last = edge_position(g, py, pz, N - 1, sr, f.c, e0, invw);
-    const int dir = (u_last >= u_first) ? 1 : -1;
-
-    const int64_t plane = a.out_plane;
-    auto binp = [&](int bp) { return dir > 0 ? bp : B - 1 - bp; };
-
-    Acc acc = (Acc)0;
-    Acc tacc = (Acc)0;  // this pass's contributions to the open bin, for the totals
-    int cbp = -1;  // open bin in the direction frame (-1: none); when open, cbp == nxt
-    int nxt = 0;   // first bin (direction frame) not yet stored
-    auto store = [&](int bp, Acc v) {
-        if (act) stream_store(v, op + (int64_t)binp(bp) * plane);
-    };
-    auto close_open = [&]() {
-        if (cbp >= 0) {
-            store(cbp, acc);
-            if (tot && act) atomicAdd(&ltot[binp(cbp)], tacc);
-            nxt = cbp + 1;
-            cbp = -1;
-        }
-    };
-    auto visit = [&](int b, Acc fr, Acc dI) {
-        const int bp = dir > 0 ? b : B - 1 - b;
-        if (bp == cbp) {
-            acc = madd(fr, dI, acc);
-            tacc = madd(fr, dI, tacc);
-        } else if (bp >= nxt) {
-            close_open();
-            if (!add_on)
-                for (int z = nxt; z < bp; ++z) store(z, (Acc)0);
-            cbp = bp;
-            nxt = bp;
-            Acc* o = op + (int64_t)b * plane;
-            acc = madd(fr, dI, (add_on && act) ? *o : (Acc)0);
-            tacc = madd(fr, dI, (Acc)0);
-        } else if (act) {  // stored already: read, add, rewrite
-            Acc* o = op + (int64_t)b * plane;
-            *o = madd(fr, dI, *o);
-            if (tot) atomicAdd(&ltot[b], fr * dI);
-        }
-    };
-
-    constexpr int U = PF + 1;
-    unsigned short ring[U];
-#pragma unroll
-    for (int d = 0; d < U; ++d) ring[d] = stream_load(ip + (int64_t)min(d, N - 1) * a.img_step);
-    double u_prev = u_first;
-    int k = 0;
-    for (; k + U <= N - 1; k += U) {
-#pragma unroll
-        for (int d = 0; d < U; ++d) {
-            const double u_next = edge_position(g, py, pz, k + d + 1, sr, f.c, e0, invw);
-            const PlanD e = make_plan<(sizeof(Acc) == 8)>(u_prev, u_next, B);
-            const Acc dI =
-                sample_diff<Acc, NORM>((int)ring[d], (int)ring[(d + 1) % U], a.wk, k + d);
-            const Acc f0 = (Acc)(e.f0 * scale), fm = (Acc)(e.fm * scale), f1 = (Acc)(e.f1 * scale);
-            const int bh = e.bl + e.nb - 1;
-            int b = dir > 0 ? e.bl : bh;
-            for (int q = 0; q < e.nb; ++q, b += dir)
-                visit(b, (b == e.bl) ? f0 : ((b == bh) ? f1 : fm), dI);
-            u_prev = u_next;
-            ring[d] = stream_load(ip + (int64_t)min(k + d + U, N - 1) * a.img_step);
-        }
-    }
-#pragma unroll
-    for (int d = 0; d < U; ++d) {
-        if (k + d < N - 1) {
-            const double u_next = edge_position(g, py, pz, k + d + 1, sr, f.c, e0, invw);
-            const PlanD e = make_plan<(sizeof(Acc) == 8)>(u_prev, u_next, B);
-            const Acc dI =
-                sample_diff<Acc, NORM>((int)ring[d], (int)ring[(d + 1) % U], a.wk, k + d);
-            const Acc f0 = (Acc)(e.f0 * scale), fm = (Acc)(e.fm * scale), f1 = (Acc)(e.f1 * scale);
-            const int bh = e.bl + e.nb - 1;
-            int b = dir > 0 ? e.bl : bh;
-            for (int q = 0; q < e.nb; ++q, b += dir)
-                visit(b, (b == e.bl) ? f0 : ((b == bh) ? f1 : fm), dI);
-            u_prev = u_next;
-        }
-    }
-    close_open();
-    if (!add_on)
-        for (int z = nxt; z < B; ++z) store(z, (Acc)0);
-    if (tot && in_lds) {
-        __syncthreads();
-        for (int b = tid; b < B; b += kPixelTile) gp[b] = ltot[b];
-    }
-}
-
 // ---------------------------------------------------------- launch wrappers
 
 static const TileCfg kVariants[] = {
@@ -486,48 +338,6 @@ hipError_t launch_validate_pixels(const GeomArgs& g, int* d_status, hipStream_t 
     hipLaunchKernelGGL(validate_pixels_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
                        g, d_status);
     return hipGetLastError();
-}
-
-template <typename Acc>
-static hipError_t launch_pixels(const ScanArgs& a, const GeomArgs& g, int side, double scale,
-                                const ListArgs* l, int64_t n_tiles, hipStream_t s)
-{
-    const int64_t groups = l ? n_tiles : (int64_t)(a.row_end - a.row_begin) * a.tiles_per_row;
-    if (groups <= 0) return hipSuccess;
-    const size_t need = (size_t)a.n_bins * sizeof(Acc);
-    const size_t lds = (a.partials && need <= kPixelLdsBytes) ? need : 0;
-    const ListArgs none{};
-    if (a.wk)
-        hipLaunchKernelGGL((pixels_kernel<Acc, 8, true>), dim3((unsigned)groups), dim3(kPixelTile),
-                           lds, s, a, g, side, scale, l ? *l : none);
-    else
-        hipLaunchKernelGGL((pixels_kernel<Acc, 8, false>), dim3((unsigned)groups),
-                           dim3(kPixelTile), lds, s, a, g, side, scale, l ? *l : none);
-    return hipGetLastError();
-}
-
-hipError_t launch_pixels_f32(const ScanArgs& a, const GeomArgs& g, int side, double scale,
-                             hipStream_t s)
-{
-    return launch_pixels<float>(a, g, side, scale, nullptr, 0, s);
-}
-
-hipError_t launch_pixels_f64(const ScanArgs& a, const GeomArgs& g, int side, double scale,
-                             hipStream_t s)
-{
-    return launch_pixels<double>(a, g, side, scale, nullptr, 0, s);
-}
-
-hipError_t launch_list_pixels_f32(const ScanArgs& a, const GeomArgs& g, int side, double scale,
-                                  const ListArgs& l, int64_t n_tiles, hipStream_t s)
-{
-    return launch_pixels<float>(a, g, side, scale, &l, n_tiles, s);
-}
-
-hipError_t launch_list_pixels_f64(const ScanArgs& a, const GeomArgs& g, int side, double scale,
-                                  const ListArgs& l, int64_t n_tiles, hipStream_t s)
-{
-    return launch_pixels<double>(a, g, side, scale, &l, n_tiles, s);
 }
 
 hipError_t launch_list_f32(const ScanArgs& a, const ListArgs& lt, int64_t n_tiles, hipStream_t s)
