@@ -205,11 +205,13 @@ __global__ __launch_bounds__(kPixelTile) void pixels_f32_kernel(ScanArgs a, Geom
             add_total(b, v);
         }
     };
-    // lanes with `on` close the open bin nxt and open nxt + 1 (the common
-    // step of the walk); every lane of the wave takes part
-    auto advance = [&](bool on) {
+    // Lanes with `on` close the open bin nxt and open nxt + 1 (the common
+    // step of the walk); the bin closed and the partial total it carries are
+    // returned in cb and cv for wave_add_totals.
+    auto advance = [&](bool on, int& cb, float& cv) {
+        cb = nat(nxt);
+        cv = tacc;
         if (on && act) stream_store(acc, op + woff);
-        if (tot) wave_add_total(on && act, nat(nxt), tacc);
         if (on) {
             woff += ostep;
             ++nxt;
@@ -218,12 +220,34 @@ __global__ __launch_bounds__(kPixelTile) void pixels_f32_kernel(ScanArgs a, Geom
             if (add_on && act) acc = op[woff];
         }
     };
+    // The partial totals of the (at most two) bins each lane closed in one
+    // step: one wave sum when every closed bin is the same bin (a lane that
+    // closes two bins never is), else one wave_add_total per kind of close.
+    auto wave_add_totals = [&](bool ca, int ba, float va, bool cb, int bb, float vb) {
+        const unsigned long long m = __ballot(ca || cb);
+        if (m == 0) return;
+        const int lead = __builtin_ctzll(m);
+        const int b0 = __builtin_amdgcn_readlane(ca ? ba : bb, lead);
+        if (__ballot((ca && ba != b0) || (cb && bb != b0)) == 0) {
+            const float sum = wave_total((ca ? va : 0.0f) + (cb ? vb : 0.0f));
+            if (lane == lead) add_total(b0, sum);
+        } else {
+            wave_add_total(ca, ba, va);
+            wave_add_total(cb, bb, vb);
+        }
+    };
 
+    // a floor as an int, clamped to [-2, B + 1] (both ends lie outside the grid)
+    auto ifloor = [&](double fl) {
+        return (int)__builtin_fmin(__builtin_fmax(fl, -2.0), (double)(B + 1));
+    };
     double u_prev = u_first, fl_prev = __builtin_floor(u_first);
+    int ifl_prev = ifloor(fl_prev);
     auto step = [&](int kk, int k, int s0, int s1) {
         const double u_next =
             position_at<TILT>(wyz[2 * kk], wyz[2 * kk + 1], py, pz, r, sr, c, e0, invw);
         const double fl_next = __builtin_floor(u_next);
+        const int ifl_next = ifloor(fl_next);
         const float dI = sample_diff<float, NORM>(s0, s1, a.wk, k) * scale;
         // Fast form, taken when every lane of the wave qualifies: the interval
         // lies inside the grid, covers one or two bins, and starts in the open
@@ -231,33 +255,35 @@ __global__ __launch_bounds__(kPixelTile) void pixels_f32_kernel(ScanArgs a, Geom
         // accumulation as the general form below.
         const double lo = __builtin_fmin(u_prev, u_next), hi = __builtin_fmax(u_prev, u_next);
         const double len = hi - lo;
-        const double f = __builtin_fmin(fl_prev, fl_next);
         const double fh = __builtin_fmax(fl_prev, fl_next);
-        const double l = (hi == fh && len > 0.0) ? fh - 1.0 : fh;  // floor(hi) unused at an exact end
+        const int f = min(ifl_prev, ifl_next);
+        // last bin: floor(hi), or the one below when hi is exactly that integer
+        const int l = max(ifl_prev, ifl_next) - ((hi == fh && len > 0.0) ? 1 : 0);
         const bool two = l > f;
-        // first bin visited (direction frame); clamped so that the conversion is defined
-        const double fc = __builtin_fmin(__builtin_fmax(f, -1.0), (double)B);
-        const double lc = __builtin_fmin(__builtin_fmax(l, -1.0), (double)B);
-        const int p1 = dir > 0 ? (int)fc : B - 1 - (int)lc;
-        const bool fast = open && f >= 0.0 && l <= (double)(B - 1) && l <= f + 1.0 &&
-                          (p1 == nxt || p1 == nxt + 1);
+        const int p1 = dir > 0 ? f : B - 1 - l;  // first bin visited (direction frame)
+        const bool fast =
+            open && f >= 0 && l <= B - 1 && l <= f + 1 && (unsigned)(p1 - nxt) <= 1u;
         if (__all(fast)) {
             float fr1 = 1.0f, fr2 = 0.0f;
             if (two) {  // bins f and f + 1, split at bd
-                const double bd = f + 1.0;
+                const double bd = (double)(f + 1);
                 const float rl = __builtin_amdgcn_rcpf((float)len);
                 const float lower = (float)(bd - lo) * rl, upper = (float)(hi - bd) * rl;
                 fr1 = dir > 0 ? lower : upper;
                 fr2 = dir > 0 ? upper : lower;
             }
-            advance(p1 != nxt);
+            const bool one = p1 != nxt;
+            int ba, bb;
+            float va, vb;
+            advance(one, ba, va);
             acc = madd(fr1, dI, acc);
             tacc = madd(fr1, dI, tacc);
-            advance(two);
+            advance(two, bb, vb);
             if (two) {
                 acc = madd(fr2, dI, acc);
                 tacc = madd(fr2, dI, tacc);
             }
+            if (tot) wave_add_totals(one && act, ba, va, two && act, bb, vb);
         } else {
             const PlanF e = plan_f32(u_prev, u_next, fl_prev, fl_next, B);
             if (e.nb > 0) {
@@ -272,6 +298,7 @@ __global__ __launch_bounds__(kPixelTile) void pixels_f32_kernel(ScanArgs a, Geom
         }
         u_prev = u_next;
         fl_prev = fl_next;
+        ifl_prev = ifl_next;
     };
 
     // ring of U samples: slot k % U holds step k; wire chunks are whole rings
