@@ -51,10 +51,13 @@ def algorithmic_bytes(nx, ny, n_steps, n_bins):
 
 
 def measured_traffic(digest: str, shape):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, used
-    only when it was taken on the current kernel source and launch shape."""
-    p = os.path.join(ROOT, "profiles", "traffic_rows_f32_config3.txt")
-    if not os.path.exists(p) or shape is None:
+    """HBM bytes per launch from the committed rocprofv3 counter summary of
+    this launch shape, used only when it was taken on the current kernel
+    source."""
+    if shape is None:
+        return None
+    p = os.path.join(ROOT, "profiles", "traffic_rows_f32_config3_%d_%d_%d.txt" % tuple(shape[:3]))
+    if not os.path.exists(p):
         return None
     d = {}
     for line in open(p):
