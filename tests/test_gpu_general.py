@@ -93,6 +93,19 @@ def make_case(name):
         s = synth.tiny(40, 2, 21, 20000, seed=209, n_src=4, dark=100.0, width=0.002,
                        render_now=False)
         _tilted_detector(s, [200.0, 0.0, 10.0])
+    elif name == "tilted_repeated_steps":  # some wire positions repeated: zero-length intervals
+        s = synth.tiny(90, 3, 23, 61, seed=210, n_src=6, dark=100.0, render_now=False)
+        _tilted_detector(s, [200.0, 8.0, 28.0])
+        c = s.wire.centers
+        idx = np.sort(np.concatenate([np.arange(c.shape[0]), [0, 5, 5, 11, c.shape[0] - 1]]))
+        s.wire = synth.Wire(s.wire.radius, np.ascontiguousarray(c[idx]))
+    elif name == "tilted_partial_grid":  # grid narrower than the sweeps: both ends leave it
+        s = synth.tiny(100, 3, 31, 25, seed=211, n_src=6, dark=100.0, render_now=False)
+        _tilted_detector(s, [200.0, -6.0, 22.0])
+        s.grid = synth.DepthGrid(25, -7.7, 0.6)
+        s.name = name
+        synth.render(s)
+        return s
     elif name.startswith("trailing_") or name.startswith("both_"):
         edge, base = name.split("_", 1)
         s = make_case(base)
@@ -108,6 +121,7 @@ def make_case(name):
 
 CASES = ["tilted_detector", "axis_xz", "axis_xy", "axis_oblique", "pixel_table_jitter",
          "tilted_non_monotone", "tilted_coarse", "tilted_decreasing", "tilted_many_bins",
+         "tilted_repeated_steps", "tilted_partial_grid",
          "trailing_tilted_detector",
          "trailing_axis_xz", "both_axis_xy", "both_tilted_non_monotone", "both_axis_oblique"]
 
