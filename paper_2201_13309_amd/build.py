@@ -15,6 +15,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB_PATH = os.path.join(PKG, "libdr.so")
+PROBE_PATH = os.path.join(PKG, "libdr_probe.so")  # benchmark's streaming reference
 ARCH = os.environ.get("PYTORCH_ROCM_ARCH", "gfx950").split(";")[0] or "gfx950"
 
 # -ffp-contract=off: FP64 geometry must not be contracted into FMAs (bin
@@ -66,6 +67,19 @@ def build_h5(verbose: bool = False) -> str:
     return H5_LIB_PATH
 
 
+def build_probe(verbose: bool = False) -> str:
+    """hipcc build of libdr_probe.so, the benchmark's streaming reference kernel."""
+    tmp = PROBE_PATH + ".tmp"
+    cmd = ["hipcc", *COMMON, *DEVICE, "-shared", os.path.join(CSRC, "dr_probe.hip"), "-o", tmp]
+    r = subprocess.run(cmd, stderr=subprocess.PIPE, stdout=subprocess.PIPE)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed for dr_probe.hip:\n" + r.stderr.decode(errors="replace"))
+    os.replace(tmp, PROBE_PATH)
+    if verbose:
+        print("built", PROBE_PATH)
+    return PROBE_PATH
+
+
 C_CONSUMER_SRC = os.path.join(ROOT, "tests", "c", "abi_consumer.c")
 C_CONSUMER = os.path.join(ROOT, "tests", "c", "abi_consumer")
 
@@ -88,7 +102,8 @@ def build_c_consumer(verbose: bool = False) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(len(SOURCES)) as ex:
+    with ThreadPoolExecutor(len(SOURCES) + 1) as ex:
+        probe = ex.submit(build_probe, verbose)
         futs = [ex.submit(_compile, s, d) for s, d in SOURCES]
         objs = []
         for f in futs:
@@ -104,6 +119,7 @@ def build(verbose: bool = False) -> str:
     os.replace(tmp, LIB_PATH)
     if verbose:
         print("built", LIB_PATH)
+    probe.result()
     build_h5(verbose)
     build_c_consumer(verbose)
     return LIB_PATH
