@@ -149,7 +149,8 @@ dr_status dr_ctx_destroy(dr_ctx ctx);
  * radius <= 0, width <= 0, an unknown edge, a zero or non-finite axis or one
  * along the beam, a pixel inside the wire, a wire position not strictly
  * between beam and pixel in eta (0 < eta_wire < eta_pixel), or any
- * non-finite depth; DR_E_NOMEM / DR_E_DEVICE for allocation or HIP failures.
+ * non-finite depth on the wire edge(s) that wire->edge reconstructs;
+ * DR_E_NOMEM / DR_E_DEVICE for allocation or HIP failures.
  * Synchronous. */
 dr_status dr_geometry_init(dr_ctx ctx, const dr_detector* det, const dr_wire* wire,
                            const dr_depth_grid* grid, dr_geom* out);
@@ -223,8 +224,9 @@ dr_status dr_reconstruct_f64(dr_geom geom, const uint16_t* images_dev, double* o
  * (flat indices j*nx + i): bins_out[n][n_steps] receives floor(u_k) as int32
  * (saturated) and u_out[n][n_steps] the FP64 positions in bin units,
  * u_k = (d_k - e0) * (1/width) with e0 = first_center - width/2; either output
- * may be NULL.  Host buffers; synchronous.  DR_E_INVAL for an out-of-range
- * pixel or edge. */
+ * may be NULL.  Positions of an edge the geometry does not reconstruct were
+ * not checked at dr_geometry_init and may be non-finite.  Host buffers;
+ * synchronous.  DR_E_INVAL for an out-of-range pixel or edge. */
 dr_status dr_debug_plan(dr_geom geom, const int64_t* pixels, int32_t n, int32_t edge,
                         int32_t* bins_out, double* u_out);
 

@@ -140,7 +140,8 @@ hipError_t launch_project_wire(const GeomArgs& g, double* wire_yz, int* d_status
 // bit (flags must be preset to 1)
 hipError_t launch_row_uniform(const GeomArgs& g, int* flags, hipStream_t s);
 // per-pixel geometry checks (status bits as in build_plans_kernel)
-hipError_t launch_validate_pixels(const GeomArgs& g, int* d_status, hipStream_t s);
+// sides: bit 0 leading edge, bit 1 trailing edge (the sides the passes use)
+hipError_t launch_validate_pixels(const GeomArgs& g, int sides, int* d_status, hipStream_t s);
 // per-pixel path: one lane per pixel, positions and bins computed in FP64 on
 // the fly.  side 0/1 = leading/trailing, scale as for the plan tables.
 hipError_t launch_pixels_f32(const ScanArgs& a, const GeomArgs& g, int side, double scale,

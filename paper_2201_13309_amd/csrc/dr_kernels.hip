@@ -187,9 +187,10 @@ __global__ __launch_bounds__(256) void row_uniform_kernel(GeomArgs g, int* flags
         flags[j] = 0;
 }
 
-// every (pixel, step) of a per-pixel geometry: finite positions, wire between
-// beam and pixel (status bits 1 and 2 as in build_plans_kernel)
-__global__ __launch_bounds__(256) void validate_pixels_kernel(GeomArgs g, int* status)
+// every (pixel, step) of a per-pixel geometry: finite positions on the edge
+// sides in `sides` (bit 0 leading, bit 1 trailing), wire between beam and
+// pixel (status bits 1 and 2 as in build_plans_kernel)
+__global__ __launch_bounds__(256) void validate_pixels_kernel(GeomArgs g, int sides, int* status)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= (int64_t)g.nx * g.ny) return;
@@ -200,6 +201,7 @@ __global__ __launch_bounds__(256) void validate_pixels_kernel(GeomArgs g, int* s
     const double invw = 1.0 / g.width;
     int bad = 0;
     for (int side = 0; side < 2; ++side) {
+        if (!(sides & (1 << side))) continue;
         const int s = side ? -leading_sign(g, py, pz) : leading_sign(g, py, pz);
         const double sr = (double)s * g.radius;
         for (int k = 0; k < g.n_steps; ++k) {
@@ -332,11 +334,11 @@ hipError_t launch_row_uniform(const GeomArgs& g, int* flags, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_validate_pixels(const GeomArgs& g, int* d_status, hipStream_t s)
+hipError_t launch_validate_pixels(const GeomArgs& g, int sides, int* d_status, hipStream_t s)
 {
     const int64_t n = (int64_t)g.nx * g.ny;
     hipLaunchKernelGGL(validate_pixels_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                       g, d_status);
+                       g, sides, d_status);
     return hipGetLastError();
 }
 

@@ -376,7 +376,9 @@ dr_status dr_geometry_init(dr_ctx c, const dr_detector* det, const dr_wire* wire
     g->row_mode = row_mode;
 
     if (!row_mode) {
-        DR_HIP(launch_validate_pixels(ga, d_status, c->stream));
+        int sides = 0;  // only the edge sides the passes use
+        for (int p = 0; p < g->passes; ++p) sides |= 1 << g->side[p];
+        DR_HIP(launch_validate_pixels(ga, sides, d_status, c->stream));
         DR_HIP(hipMemcpyAsync(&status, d_status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
         DR_HIP(hipStreamSynchronize(c->stream));
         if (status & 1)
