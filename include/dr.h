@@ -90,8 +90,10 @@ typedef struct dr_list_s* dr_list;   /* a sorted pixel list of one geometry, til
  * that overrides the affine map.  When every pixel of each row projects to
  * the row's first (eta, xi) bit for bit (a detector whose rows run along the
  * wire axis), rows share one set of FP64 bin positions built once; otherwise
- * each pixel computes its own positions on the fly (the per-pixel path: same
- * results, ALU-bound instead of HBM-bound). */
+ * each pixel computes its own positions on the fly (the per-pixel path: the
+ * same positions and bins, FP32 fractions from one reciprocal of the interval
+ * length, so FP32 outputs agree within the FP32 tolerance and the FP64
+ * instance exactly; ALU-bound instead of HBM-bound). */
 typedef struct {
     int32_t nx, ny;
     double origin[3], u[3], v[3];
