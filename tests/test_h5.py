@@ -155,6 +155,21 @@ def test_depth_images_checked_by_dumper(h5, tmp_path):
                           -2.0 + 0.5 * np.arange(5))
 
 
+def test_large_depth_images(h5, tmp_path):
+    """A 30 MB result: every value where the library's own dumper reads it,
+    and the depth axis beside it."""
+    out = np.random.default_rng(8).standard_normal((3, 1500, 1700)).astype(np.float32)
+    p = str(tmp_path / "big.h5")
+    h5.write_depth_images(p, "/r/d", out, first_center=1.0, width=0.25)
+    assert np.array_equal(h5dump(str(tmp_path), p, "/r/d", np.float32), out.ravel())
+    assert np.array_equal(h5dump(str(tmp_path), p, "/r/d_depth", np.float64),
+                          1.0 + 0.25 * np.arange(3))
+    # rewriting a smaller result into the same path truncates the file first
+    small = out[:1, :10, :20].copy()
+    h5.write_depth_images(p, "/r/d", small, first_center=0.0, width=1.0)
+    assert np.array_equal(h5dump(str(tmp_path), p, "/r/d", np.float32), small.ravel())
+
+
 def test_errors(h5, tmp_path):
     from paper_2201_13309_amd.dr import DRError, DR_E_INVAL
     a = [str(tmp_path / f"e_{k}.h5") for k in range(2)]
