@@ -921,7 +921,7 @@ dr_status dr_batch_create(dr_ctx c, int32_t n, const dr_batch_item* items, int32
     TileCfg t = cands.back();
     for (const TileCfg& x : cands)
         if (x.ppl == 2 && x.waves == 4 && x.prefetch == 16) t = x;
-    int gpc = 2;
+    int gpc = 8;  // persistent workgroups per CU (2048 threads of 4-wave groups)
     hipStream_t s = c->stream;
     if (flags & DR_BATCH_AUTOTUNE) {
         hipEvent_t e0, e1;
