@@ -311,7 +311,8 @@ struct Scheduler {
             ba.total_tiles = tiles[gi];
             ba.counter = d_cnt + gi;
             const TileCfg t{kPpl[gi % 3], 4, 16};
-            const int groups = (int)std::max<int64_t>(1, std::min<int64_t>(ctx->cus * 2, tiles[gi]));
+            // 8 persistent 4-wave workgroups per CU (2048 threads); 2 left the GPU a third idle
+            const int groups = (int)std::max<int64_t>(1, std::min<int64_t>(ctx->cus * 8, tiles[gi]));
             e = launch_reset_counter(ba.counter, s);
             // groups 3..5 hold second passes, which add onto the first
             if (e == hipSuccess) e = launch_batch_f32(t, ba, gi >= 3, groups, s);
