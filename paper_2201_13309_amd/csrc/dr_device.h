@@ -93,10 +93,12 @@ __device__ __forceinline__ double tangent_depth(double py, double pz, double cy,
     const double az = cz - pz;
     const double L2 = az * az + ay * ay;
     const double q = L2 - r * r;
+    // q <= 0 (the pixel inside the wire) gives NaN, which the depth inherits
     double kk;
-    if (q >= 0x1p-767 && q < __builtin_inf()) kk = sqrt_newton(q);
-    else if (q > 0.0) kk = __builtin_sqrt(q);  // tiny or infinite: the library's
-    else return __builtin_nan("");
+    if (__builtin_expect(q >= 0x1p-767 && q < __builtin_inf(), 1))
+        kk = sqrt_newton(q);
+    else
+        kk = q > 0.0 ? __builtin_sqrt(q) : __builtin_nan("");  // tiny or infinite: the library's
     const double tz = az * kk - ay * sr;
     const double ty = ay * kk + az * sr;
     return cz - (cy * tz + sr * L2) / ty;

@@ -76,6 +76,7 @@ __device__ __forceinline__ PlanF plan_f32(double u0, double u1, double fl0, doub
 }
 
 constexpr int kWireChunk = 512;  // wire positions staged in LDS at a time
+constexpr int kPixelTotalCopies = 4;  // copies of the LDS partial totals (FP32 kernel)
 
 // FP32 per-pixel kernel: one lane per pixel of a row tile (or of a list tile,
 // as in the FP64 instance below).  Each lane walks its bins in the direction
@@ -121,12 +122,17 @@ __global__ __launch_bounds__(kPixelTile) void pixels_f32_kernel(ScanArgs a, Geom
         op = (float*)a.out + (int64_t)row * a.nx + col;
         slot = (int64_t)row * a.tiles_per_row + tile;
     }
+    // the workgroup's partial totals: in LDS, four copies (one per 16-lane
+    // row of a wave, so that the lanes of a wave adding to one bin meet at
+    // most 16 to an address), summed at the end; in place in the workgroup's
+    // row of the partials buffer when they do not fit
     float* const gp = tot ? (float*)a.partials + slot * B : nullptr;
-    const bool in_lds = (size_t)B * sizeof(float) <= kPixelLdsBytes;
+    const bool in_lds = (size_t)B * kPixelTotalCopies * sizeof(float) <= kPixelLdsBytes;
     float* const ltot = reinterpret_cast<float*>(dyn_lds);
+    const int lane = (int)(threadIdx.x & 63);
     if (tot) {
         if (in_lds)
-            for (int b = tid; b < B; b += kPixelTile) ltot[b] = 0.0f;
+            for (int b = tid; b < kPixelTotalCopies * B; b += kPixelTile) ltot[b] = 0.0f;
         else
             for (int b = tid; b < B; b += kPixelTile) gp[b] = 0.0f;
     }
@@ -150,9 +156,27 @@ __global__ __launch_bounds__(kPixelTile) void pixels_f32_kernel(ScanArgs a, Geom
     auto nat = [&](int p) { return dir > 0 ? p : B - 1 - p; };
     auto add_total = [&](int b, float v) {  // an LDS atomic when the row fits there
         if (in_lds)
-            __hip_atomic_fetch_add(&ltot[b], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add(&ltot[(lane >> 4) * B + b], v, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
         else
             __hip_atomic_fetch_add(&gp[b], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    };
+    // v summed over the wave (every lane active) into bin b: in LDS, per
+    // 16-lane row by DPP, each row's last lane adding into its own copy
+    auto wave_sum_into = [&](int b, float v) {
+        if (in_lds) {
+            v += dpp_shift<0x111, 0xf>(v);  // row_shr:1
+            v += dpp_shift<0x112, 0xf>(v);  // row_shr:2
+            v += dpp_shift<0x114, 0xf>(v);  // row_shr:4
+            v += dpp_shift<0x118, 0xf>(v);  // row_shr:8
+            if ((lane & 15) == 15)
+                __hip_atomic_fetch_add(&ltot[(lane >> 4) * B + b], v, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+        } else {
+            const float sum = wave_total(v);
+            if (lane == 0)
+                __hip_atomic_fetch_add(&gp[b], sum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
     };
     int nxt = 0;                                        // first bin not stored
     int64_t woff = dir > 0 ? 0 : (int64_t)(B - 1) * plane;  // element offset of bin nxt
@@ -192,18 +216,14 @@ __global__ __launch_bounds__(kPixelTile) void pixels_f32_kernel(ScanArgs a, Geom
     // the wave active: when all those lanes close the same bin (neighbouring
     // pixels of a row usually do), their sum is formed with DPP and added by
     // one lane, instead of one LDS atomic per lane on a single address.
-    const int lane = (int)(threadIdx.x & 63);
     auto wave_add_total = [&](bool on, int b, float v) {
         const unsigned long long m = __ballot(on);
         if (m == 0) return;
-        const int lead = __builtin_ctzll(m);
-        const int b0 = __builtin_amdgcn_readlane(b, lead);
-        if (__ballot(on && b != b0) == 0) {
-            const float sum = wave_total(on ? v : 0.0f);
-            if (lane == lead) add_total(b0, sum);
-        } else if (on) {
+        const int b0 = __builtin_amdgcn_readlane(b, __builtin_ctzll(m));
+        if (__ballot(on && b != b0) == 0)
+            wave_sum_into(b0, on ? v : 0.0f);
+        else if (on)
             add_total(b, v);
-        }
     };
     // Lanes with `on` close the open bin nxt and open nxt + 1 (the common
     // step of the walk); the bin closed and the partial total it carries are
@@ -226,11 +246,9 @@ __global__ __launch_bounds__(kPixelTile) void pixels_f32_kernel(ScanArgs a, Geom
     auto wave_add_totals = [&](bool ca, int ba, float va, bool cb, int bb, float vb) {
         const unsigned long long m = __ballot(ca || cb);
         if (m == 0) return;
-        const int lead = __builtin_ctzll(m);
-        const int b0 = __builtin_amdgcn_readlane(ca ? ba : bb, lead);
+        const int b0 = __builtin_amdgcn_readlane(ca ? ba : bb, __builtin_ctzll(m));
         if (__ballot((ca && ba != b0) || (cb && bb != b0)) == 0) {
-            const float sum = wave_total((ca ? va : 0.0f) + (cb ? vb : 0.0f));
-            if (lane == lead) add_total(b0, sum);
+            wave_sum_into(b0, (ca ? va : 0.0f) + (cb ? vb : 0.0f));
         } else {
             wave_add_total(ca, ba, va);
             wave_add_total(cb, bb, vb);
@@ -330,7 +348,8 @@ __global__ __launch_bounds__(kPixelTile) void pixels_f32_kernel(ScanArgs a, Geom
             if (act) stream_store(0.0f, op + woff);
     if (tot && in_lds) {
         __syncthreads();
-        for (int b = tid; b < B; b += kPixelTile) gp[b] = ltot[b];
+        for (int b = tid; b < B; b += kPixelTile)
+            gp[b] = (ltot[b] + ltot[B + b]) + (ltot[2 * B + b] + ltot[3 * B + b]);
     }
 }
 
@@ -491,7 +510,7 @@ static hipError_t launch_pixels(const ScanArgs& a, const GeomArgs& g, int side, 
 {
     const int64_t groups = l ? n_tiles : (int64_t)(a.row_end - a.row_begin) * a.tiles_per_row;
     if (groups <= 0) return hipSuccess;
-    const size_t need = (size_t)a.n_bins * sizeof(Acc);
+    const size_t need = (size_t)a.n_bins * sizeof(Acc) * (sizeof(Acc) == 4 ? kPixelTotalCopies : 1);
     const size_t lds = (a.partials && need <= kPixelLdsBytes) ? need : 0;
     const ListArgs none{};
     const ListArgs& la = l ? *l : none;
