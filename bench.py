@@ -686,7 +686,13 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the oracle on a CPU sample")
         s.images = host.numpy().view(np.uint16)
-        result["cpu_baseline"] = cpu_baseline(s, args.cpu_seconds)
+        cb = cpu_baseline(s, args.cpu_seconds)
+        # the oracle's time for the whole scan over the GPU's, kernel alone and
+        # end to end from pinned host memory
+        cb["oracle_over_gpu_step"] = result["value"] / cb["value"]
+        if "end_to_end" in result:
+            cb["oracle_over_gpu_end_to_end"] = result["end_to_end"]["value"] / cb["value"]
+        result["cpu_baseline"] = cb
     dr.dr_ctx_destroy(ctx)
     print(json.dumps(result), flush=True)
 

@@ -283,8 +283,10 @@ dr_status dr_batch_free(dr_batch batch);
  * which).  Selection rule: the activity of pixel p is
  * A_p = sum_k |I_k - I_{k+1}| over its samples, and the top-k list keeps the k
  * pixels of largest A_p, ties going to the lower index.  Every list is held
- * on the device in increasing pixel index (p = j*nx + i) and cut into tiles of
- * at most 256 entries inside one detector row.  Results for a listed pixel are
+ * on the device in increasing pixel index (p = j*nx + i) and cut into tiles:
+ * with per-row plans, windows of at most 64 entries (one wave each) inside one
+ * detector row; on the per-pixel path, runs of 256 consecutive entries.
+ * Results for a listed pixel are
  * bitwise those of dr_reconstruct / dr_reconstruct_f64 for that pixel. */
 
 /* Image layouts for list reconstruction. */
