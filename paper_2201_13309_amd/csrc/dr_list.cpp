@@ -201,16 +201,25 @@ dr_status dr_select_top(dr_geom g, const uint64_t* activity_dev, int64_t k, dr_l
     dr_status st = new_list(g, k, &l);
     if (st != DR_OK) return st;
     std::unique_ptr<dr_list_s> own(l);
-    if (k > 0) {
-        DevBuf state, bsum;
-        DR_HIP(state.reserve(sizeof(SelectState)));
-        DR_HIP(bsum.reserve((size_t)((npix + kSelectBlock - 1) / kSelectBlock) * sizeof(uint64_t)));
-        DR_HIP(launch_select_top(activity_dev, npix, k, state.as<SelectState>(),
-                                 bsum.as<uint64_t>(), l->pixels.as<int64_t>(), s));
-        DR_HIP(hipStreamSynchronize(s));
+    {
+        // selection state and block sums in one buffer; build_tiles reads the
+        // list back on the same stream (and waits), so the kernels are done
+        // before the buffer is freed
+        DevBuf scratch;
+        if (k > 0) {
+            const size_t nb = (size_t)((npix + kSelectBlock - 1) / kSelectBlock);
+            DR_HIP(scratch.reserve(up256(sizeof(SelectState)) + nb * sizeof(uint64_t)));
+            char* base = scratch.as<char>();
+            DR_HIP(launch_select_top(activity_dev, npix, k, (SelectState*)base,
+                                     (uint64_t*)(base + up256(sizeof(SelectState))),
+                                     l->pixels.as<int64_t>(), s));
+        }
+        st = build_tiles(l, s);
+        if (st != DR_OK) {
+            (void)hipStreamSynchronize(s);
+            return st;
+        }
     }
-    st = build_tiles(l, s);
-    if (st != DR_OK) return st;
     *out = own.release();
     set_error(DR_OK, "");
     return DR_OK;

@@ -99,15 +99,35 @@ __device__ __forceinline__ uint64_t sel_flag(uint64_t a, uint64_t thr)
     return (a > thr ? (uint64_t)1 << 32 : 0) | (a == thr ? 1u : 0u);
 }
 
+// The block's kSelectBlock keys, read in address order (coalesced) into LDS,
+// key j at keys[j + j/16] so that thread t's sixteen keys (16t .. 16t+15)
+// sit 17 apart between threads (few bank conflicts); keys past the end read
+// as 0.
+constexpr int kKeysLds = (int)(kSelectBlock + kSelectBlock / 16);
+__device__ __forceinline__ int key_slot(int j) { return j + (j >> 4); }
+
+__device__ __forceinline__ void stage_keys(const uint64_t* act, int64_t npix, uint64_t* keys)
+{
+    const int64_t b0 = (int64_t)blockIdx.x * kSelectBlock;
+#pragma unroll
+    for (int i = 0; i < (int)(kSelectBlock / 256); ++i) {
+        const int j = i * 256 + (int)threadIdx.x;
+        keys[key_slot(j)] = b0 + j < npix ? act[b0 + j] : 0;
+    }
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(256) void select_reduce_kernel(const uint64_t* act, int64_t npix,
                                                             const SelectState* st, uint64_t* bsum)
 {
+    __shared__ uint64_t keys[kKeysLds];
     __shared__ uint64_t s[256];
     const uint64_t thr = st->prefix;
+    stage_keys(act, npix, keys);
     const int64_t base = (int64_t)blockIdx.x * kSelectBlock + threadIdx.x * 16;
     uint64_t c = 0;
     for (int i = 0; i < 16; ++i)
-        if (base + i < npix) c += sel_flag(act[base + i], thr);
+        if (base + i < npix) c += sel_flag(keys[key_slot((int)threadIdx.x * 16 + i)], thr);
     s[threadIdx.x] = c;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
@@ -143,13 +163,15 @@ __global__ __launch_bounds__(256) void select_scatter_kernel(const uint64_t* act
                                                              const SelectState* st,
                                                              const uint64_t* bsum, int64_t* list)
 {
+    __shared__ uint64_t keys[kKeysLds];
     __shared__ uint64_t s[256];
     const uint64_t thr = st->prefix;
     const int64_t need = st->need;
+    stage_keys(act, npix, keys);
     const int64_t base = (int64_t)blockIdx.x * kSelectBlock + threadIdx.x * 16;
     uint64_t c = 0;
     for (int i = 0; i < 16; ++i)
-        if (base + i < npix) c += sel_flag(act[base + i], thr);
+        if (base + i < npix) c += sel_flag(keys[key_slot((int)threadIdx.x * 16 + i)], thr);
     s[threadIdx.x] = c;
     __syncthreads();
     for (int w = 1; w < 256; w <<= 1) {
@@ -162,7 +184,7 @@ __global__ __launch_bounds__(256) void select_scatter_kernel(const uint64_t* act
     for (int i = 0; i < 16; ++i) {
         const int64_t p = base + i;
         if (p >= npix) break;
-        const uint64_t f = sel_flag(act[p], thr);
+        const uint64_t f = sel_flag(keys[key_slot((int)threadIdx.x * 16 + i)], thr);
         const int64_t gt = (int64_t)(run >> 32), eq = (int64_t)(run & 0xffffffffu);
         if ((f >> 32) || ((f & 1) && eq < need)) list[gt + (eq < need ? eq : need)] = p;
         run += f;
