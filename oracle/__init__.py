@@ -45,13 +45,13 @@ def load(path: Optional[str] = None):
         lib.oracle_tangent_depth.restype = d
         lib.oracle_edge_sign.argtypes = [d, d, i32, p, d]
         lib.oracle_edge_sign.restype = i32
-        lib.oracle_bin_profile.argtypes = [p, p, i32, i32, i32, d, p, i64]
+        lib.oracle_bin_profile.argtypes = [p, p, i32, i32, i32, p, i64]
         lib.oracle_bin_profile.restype = None
         lib.oracle_reconstruct.argtypes = [i32, i32, p, p, p, p, d, p, i32, p, i32, d, d, i32,
                                            p, p, i32, i32, p, p, p, i32]
         lib.oracle_reconstruct.restype = i32
         lib.oracle_reconstruct_pixels.argtypes = [i32, i32, p, p, p, p, d, p, i32, p, i32, d, d,
-                                                  i32, p, p, p, p, i64, p, p, p, i32]
+                                                  i32, p, p, p, i64, p, p, p, i32]
         lib.oracle_reconstruct_pixels.restype = i32
         lib.oracle_activity.argtypes = [p, i32, i64, p]
         lib.oracle_activity.restype = None
@@ -89,16 +89,15 @@ def edge_sign(py, pz, centers, r, lib=None) -> int:
 EDGE_LEADING, EDGE_TRAILING, EDGE_BOTH = 0, 1, 2
 
 
-def bin_profile(u, intensities, n_bins: int, trailing: bool = False, weight: float = 1.0,
-                lib=None) -> np.ndarray:
+def bin_profile(u, intensities, n_bins: int, trailing: bool = False, lib=None) -> np.ndarray:
     """Binning of one pixel given its positions u_k (bin units) and counts;
-    trailing=True takes dI_k = I_{k+1} - I_k; weight scales the fractions."""
+    trailing=True takes dI_k = I_{k+1} - I_k."""
     u = _f64(u)
     I = _f64(intensities)
     assert u.shape == I.shape and u.ndim == 1
     out = np.zeros(n_bins, dtype=np.float64)
     (lib or load()).oracle_bin_profile(_p(u), _p(I), u.shape[0], int(n_bins), 1 if trailing else 0,
-                                       float(weight), _p(out), 1)
+                                       _p(out), 1)
     return out
 
 
@@ -144,27 +143,23 @@ def reconstruct(scan, images: Optional[np.ndarray] = None, row0: int = 0,
 
 
 def reconstruct_pixels(scan, pixels, images: Optional[np.ndarray] = None,
-                       series: Optional[np.ndarray] = None, want_bins: bool = True,
-                       want_u: bool = False, nthreads: int = 0, lib=None):
-    """FP64 profiles of listed pixels (flat j*nx+i).
+                       want_bins: bool = True, want_u: bool = False, nthreads: int = 0,
+                       lib=None):
+    """FP64 profiles of listed pixels (flat j*nx+i); with no images (neither
+    given nor held by the scan) only the positions.
 
     Returns (out [npix][n_bins], bins [npix][N] or None, u [npix][N] or None)."""
     pix = np.ascontiguousarray(np.asarray(pixels, dtype=np.int64))
     N = scan.wire.centers.shape[0]
     B = scan.grid.n_bins
-    if series is not None:
-        series = np.ascontiguousarray(series, dtype=np.uint16)
-        assert series.shape == (pix.shape[0], N)
-        images = None
-    else:
-        images = scan.images if images is None else images
-        if images is not None:
-            images = np.ascontiguousarray(images, dtype=np.uint16)
+    images = scan.images if images is None else images
+    if images is not None:
+        images = np.ascontiguousarray(images, dtype=np.uint16)
     out = np.empty((pix.shape[0], B), dtype=np.float64)
     bins = np.empty((pix.shape[0], N), dtype=np.int32) if want_bins else None
     upos = np.empty((pix.shape[0], N), dtype=np.float64) if want_u else None
     args, keep = _geom_args(scan)
-    rc = (lib or load()).oracle_reconstruct_pixels(*args, _p(images), _p(series), _p(pix),
+    rc = (lib or load()).oracle_reconstruct_pixels(*args, _p(images), _p(pix),
                                                    pix.shape[0], _p(out), _p(bins), _p(upos),
                                                    int(nthreads))
     del keep

@@ -35,14 +35,12 @@
  *              side s_p and dI_k = I_k - I_{k+1} (intensity lost as the edge
  *              covers the slice); the trailing edge uses side -s_p and
  *              dI_k = I_{k+1} - I_k (intensity regained as it uncovers it);
- *              "both" is the average of the two reconstructions, accumulated
- *              as the leading contributions at weight 1/2 followed by the
- *              trailing contributions at weight 1/2, each bin in step order.
+ *              "both" is the average 0.5 * (L + T) of the leading (L) and
+ *              trailing (T) reconstructions, each built on its own.
  *   binning    u_k = (d_k - e0) * (1/width), e0 = first_center - width/2.
  *              For k = 0..N-2 the difference dI_k is spread over
  *              [lo, hi] = [min, max](u_k, u_{k+1}): bin b gets
- *              dI_k * (w * (ov/len)) (edge weight w) with
- *              ov = min(hi, b+1) - max(lo, b) > 0 and
+ *              dI_k * (ov/len) with ov = min(hi, b+1) - max(lo, b) > 0 and
  *              len = hi - lo; parts outside [0, n_bins) are dropped; a
  *              zero-length interval puts dI_k into bin floor(lo).
  *   weights    optional per-step weights w_k (beam-monitor normalisation, a
@@ -192,11 +190,10 @@ static int pixel_positions(double py, double pz, int n_steps, const double* wyz,
  *   u        [n_steps] edge positions in bin units
  *   I        [n_steps] intensities (counts), read as doubles
  *   trailing 0: dI_k = I_k - I_{k+1}; 1: dI_k = I_{k+1} - I_k
- *   w        weight of this edge (1, or 1/2 for each edge of "both")
  *   out      [n_bins] accumulated in place (caller zeroes it)
  *   stride   distance between consecutive bins of out */
 void oracle_bin_profile(const double* u, const double* I, int n_steps, int n_bins, int trailing,
-                        double w, double* out, int64_t stride)
+                        double* out, int64_t stride)
 {
     for (int k = 0; k + 1 < n_steps; ++k) {
         double dI = trailing ? I[k + 1] - I[k] : I[k] - I[k + 1];
@@ -211,11 +208,11 @@ void oracle_bin_profile(const double* u, const double* I, int n_steps, int n_bin
                 double top = hi < bd + 1.0 ? hi : bd + 1.0;
                 double bot = lo > bd ? lo : bd;
                 double ov = top - bot;
-                if (ov > 0.0) out[(int64_t)bd * stride] += dI * (w * (ov / len));
+                if (ov > 0.0) out[(int64_t)bd * stride] += dI * (ov / len);
             }
         } else {
             double bd = floor(lo);
-            if (bd >= 0.0 && bd < (double)n_bins) out[(int64_t)bd * stride] += dI * w;
+            if (bd >= 0.0 && bd < (double)n_bins) out[(int64_t)bd * stride] += dI;
         }
     }
 }
@@ -223,25 +220,30 @@ void oracle_bin_profile(const double* u, const double* I, int n_steps, int n_bin
 /* Profile of one pixel for edge LEADING, TRAILING or BOTH into o (stride
  * between bins; the caller zeroes it).  uk [n_steps] is scratch; the
  * positions of the reported edge (trailing for TRAILING, else leading) are
- * left in uk. */
+ * left in uk.  lt [2 * n_bins] is scratch for BOTH: the leading profile L and
+ * the trailing profile T, each accumulated on its own from zero, then
+ * o = 0.5 * (L + T) bin by bin. */
 static int pixel_profile(double py, double pz, const double* Ik, int n_steps,
                          const double* wyz, double r, double c, double e0, double invw,
-                         int n_bins, int edge, double* o, int64_t stride, double* uk)
+                         int n_bins, int edge, double* o, int64_t stride, double* uk, double* lt)
 {
     if (edge == EDGE_BOTH) {
-        if (pixel_positions(py, pz, n_steps, wyz, r, c, e0, invw, 0, uk) != ORACLE_OK)
-            return ORACLE_EINVAL;
-        oracle_bin_profile(uk, Ik, n_steps, n_bins, 0, 0.5, o, stride);
+        double* L = lt;
+        double* T = lt + n_bins;
+        for (int b = 0; b < n_bins; ++b) L[b] = T[b] = 0.0;
         if (pixel_positions(py, pz, n_steps, wyz, r, c, e0, invw, 1, uk) != ORACLE_OK)
             return ORACLE_EINVAL;
-        oracle_bin_profile(uk, Ik, n_steps, n_bins, 1, 0.5, o, stride);
-        /* report the leading positions */
-        return pixel_positions(py, pz, n_steps, wyz, r, c, e0, invw, 0, uk);
+        oracle_bin_profile(uk, Ik, n_steps, n_bins, 1, T, 1);
+        if (pixel_positions(py, pz, n_steps, wyz, r, c, e0, invw, 0, uk) != ORACLE_OK)
+            return ORACLE_EINVAL;
+        oracle_bin_profile(uk, Ik, n_steps, n_bins, 0, L, 1);
+        for (int b = 0; b < n_bins; ++b) o[(int64_t)b * stride] = 0.5 * (L[b] + T[b]);
+        return ORACLE_OK;
     }
     const int trailing = edge == EDGE_TRAILING;
     if (pixel_positions(py, pz, n_steps, wyz, r, c, e0, invw, trailing, uk) != ORACLE_OK)
         return ORACLE_EINVAL;
-    oracle_bin_profile(uk, Ik, n_steps, n_bins, trailing, 1.0, o, stride);
+    oracle_bin_profile(uk, Ik, n_steps, n_bins, trailing, o, stride);
     return ORACLE_OK;
 }
 
@@ -285,6 +287,7 @@ int oracle_reconstruct(int nx, int ny, const double* origin, const double* u, co
     {
         double* uk = (double*)malloc(sizeof(double) * (size_t)n_steps);
         double* Ik = (double*)malloc(sizeof(double) * (size_t)n_steps);
+        double* lt = (double*)malloc(sizeof(double) * 2 * (size_t)n_bins);
 #pragma omp for schedule(dynamic, 1)
         for (int jr = 0; jr < nrows; ++jr) {
             for (int i = 0; i < nx; ++i) {
@@ -297,7 +300,7 @@ int oracle_reconstruct(int nx, int ny, const double* origin, const double* u, co
                     if (step_weight) Ik[k] = Ik[k] * step_weight[k];
                 }
                 if (pixel_profile(py, pz, Ik, n_steps, wyz, radius, fr.c, e0, invw, n_bins, edge,
-                                  out + q, plane_out, uk) != ORACLE_OK) {
+                                  out + q, plane_out, uk, lt) != ORACLE_OK) {
 #pragma omp atomic write
                     status = ORACLE_EINVAL;
                     continue;
@@ -308,6 +311,7 @@ int oracle_reconstruct(int nx, int ny, const double* origin, const double* u, co
         }
         free(uk);
         free(Ik);
+        free(lt);
     }
     free(wyz);
     if (status != ORACLE_OK) return status;
@@ -324,8 +328,7 @@ int oracle_reconstruct(int nx, int ny, const double* origin, const double* u, co
 /*
  * Reconstruction of an explicit list of pixels (flat indices j*nx + i), for
  * sampled checks of large scans.  Intensities come from `images`
- * ([n_steps][ny][nx]) or, when `series` is not NULL, from series[n][n_steps]
- * (the time series of the n-th listed pixel); with neither, only positions.
+ * ([n_steps][ny][nx]); with NULL images only the positions are computed.
  *   out   [npix][n_bins] FP64 profile of each listed pixel
  *   bins  [npix][n_steps] int32 floor(u_k) of the reported edge, or NULL
  *   upos  [npix][n_steps] FP64 u_k of the reported edge, or NULL
@@ -335,8 +338,7 @@ int oracle_reconstruct_pixels(int nx, int ny, const double* origin, const double
                               const double* axis, int n_steps, const double* centers, int n_bins,
                               double first_center, double width, int edge,
                               const double* step_weight,
-                              const uint16_t* images, const uint16_t* series,
-                              const int64_t* pixels, int64_t npix, double* out, int32_t* bins,
+                              const uint16_t* images, const int64_t* pixels, int64_t npix, double* out, int32_t* bins,
                               double* upos, int nthreads)
 {
     if (nx <= 0 || ny <= 0 || n_steps < 2 || n_bins <= 0 || !(width > 0.0) || !(radius > 0.0))
@@ -358,6 +360,7 @@ int oracle_reconstruct_pixels(int nx, int ny, const double* origin, const double
     {
         double* uk = (double*)malloc(sizeof(double) * (size_t)n_steps);
         double* Ik = (double*)malloc(sizeof(double) * (size_t)n_steps);
+        double* lt = (double*)malloc(sizeof(double) * 2 * (size_t)n_bins);
 #pragma omp for schedule(dynamic, 16)
         for (int64_t n = 0; n < npix; ++n) {
             int64_t p = pixels[n];
@@ -371,17 +374,16 @@ int oracle_reconstruct_pixels(int nx, int ny, const double* origin, const double
             double py, pz;
             pixel_center(&fr, nx, origin, u, v, pixel_xyz, p, &py, &pz);
             for (int k = 0; k < n_steps; ++k) {
-                Ik[k] = series ? (double)series[n * n_steps + k]
-                               : (images ? (double)images[(int64_t)k * plane_in + p] : 0.0);
+                Ik[k] = images ? (double)images[(int64_t)k * plane_in + p] : 0.0;
                 if (step_weight) Ik[k] = Ik[k] * step_weight[k];
             }
             if (pixel_profile(py, pz, Ik, n_steps, wyz, radius, fr.c, e0, invw, n_bins, edge, o,
-                              1, uk) != ORACLE_OK) {
+                              1, uk, lt) != ORACLE_OK) {
 #pragma omp atomic write
                 status = ORACLE_EINVAL;
                 continue;
             }
-            if (!series && !images)
+            if (!images)
                 for (int b = 0; b < n_bins; ++b) o[b] = 0.0;
             if (bins)
                 for (int k = 0; k < n_steps; ++k) bins[n * n_steps + k] = floor_to_i32(uk[k]);
@@ -390,6 +392,7 @@ int oracle_reconstruct_pixels(int nx, int ny, const double* origin, const double
         }
         free(uk);
         free(Ik);
+        free(lt);
     }
     free(wyz);
     return status;

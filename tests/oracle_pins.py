@@ -225,14 +225,19 @@ def brute_force_pixel(py, pz, centers, r, grid, I, samples_per_bin=4000, edge=0)
 
 def pin_brute_force(lib):
     """Tiny scans (4x4 px, 9 steps, 15 bins) against brute-force integration,
-    for the leading edge, the trailing edge and their average."""
+    for the leading edge, the trailing edge and their average: every pixel's
+    profile, and the per-depth totals bin by bin against the sum of the
+    brute-force profiles over the pixels (within the summed bounds)."""
+    shaped = 0
     for seed, step, width, edge in ((21, 1.0, 1.0, 0), (22, 0.5, 0.5, 0), (23, 2.0, 1.0, 0),
                                     (24, 1.0, 1.0, 1), (25, 2.0, 1.0, 2)):
         s = synth.tiny(4, 4, 9, 15, seed=seed, pitch=3000.0, step=step, width=width,
                        n_src=6, dark=50.0, sigma=1.0)
         s.wire.edge = edge
-        out, _, _ = oracle.reconstruct(s, lib=lib)
+        out, tot, _ = oracle.reconstruct(s, lib=lib)
         py, pz = s.detector.pixel_yz()
+        tot_bf = np.zeros(s.grid.n_bins)
+        tot_err = np.zeros(s.grid.n_bins)
         for j in range(4):
             for i in range(4):
                 prof, err = brute_force_pixel(py[j, i], pz[j, i], s.wire.centers,
@@ -240,6 +245,50 @@ def pin_brute_force(lib):
                                               edge=edge)
                 got = out[:, j, i]
                 assert np.all(np.abs(got - prof) <= err + 1e-9), (seed, j, i, got, prof, err)
+                tot_bf += prof
+                tot_err += err
+        assert np.all(np.abs(tot - tot_bf) <= tot_err + 1e-8), (seed, tot, tot_bf, tot_err)
+        # totals far from flat, so that a shifted or permuted bin index fails
+        shaped += np.abs(np.diff(tot_bf)).max() > 100.0 * tot_err.max() + 1e-6
+    assert shaped >= 3, shaped
+
+
+def pin_totals_planted(lib):
+    """Per-depth totals against planted sources: noise-free single-pixel
+    sources with integer amplitudes, one source per pixel, at four depths far
+    apart.  The leading edge covers each source once during the scan, so the
+    totals over the three bins around a depth hold exactly the summed
+    amplitude of the sources at that depth, and every other bin holds none."""
+    s = synth.tiny(40, 40, 61, 121, seed=51, step=1.0, width=1.0, n_src=48, dark=0.0,
+                   noise=False, sigma=0.0, integer_amp=True, render_now=False)
+    depths = np.array([-16.0, -5.5, 5.5, 16.0]) + 0.25
+    src = s.sources
+    n = len(src.zs)
+    # one source per pixel, depths cycled over the four values
+    rng = np.random.default_rng(52)
+    flat = rng.choice(40 * 40, n, replace=False)
+    src.ci[:] = (flat % 40).astype(np.float64)
+    src.cj[:] = (flat // 40).astype(np.float64)
+    src.zs[:] = depths[np.arange(n) % 4]
+    synth.render(s)
+    I = s.images.reshape(s.wire.n_steps, -1).astype(np.int64)
+    out, tot, _ = oracle.reconstruct(s, lib=lib)
+    e0 = s.grid.first_center - 0.5 * s.grid.width
+    seen = np.zeros(s.grid.n_bins, dtype=bool)
+    for z in depths:
+        b = int(math.floor((z - e0) / s.grid.width))
+        on = np.isclose(src.zs, z)
+        # amplitude of the sources at this depth that the scan covers: the
+        # count of the pixel drops by it once and never comes back
+        covered = [int(src.amp[m]) for m in np.nonzero(on)[0]
+                   if I[0, flat[m]] - I[-1, flat[m]] == int(src.amp[m])]
+        assert len(covered) >= 8, (z, len(covered))
+        want = float(sum(covered))
+        got = float(tot[b - 1:b + 2].sum())
+        assert abs(got - want) <= 1e-9 * want, (z, got, want)
+        seen[b - 1:b + 2] = True
+    # pixels without a source, or whose source is not covered, add nothing
+    assert np.all(np.abs(tot[~seen]) <= 1e-9 * float(src.amp.sum())), tot[~seen]
 
 
 def pin_planted_sources(lib):
@@ -574,6 +623,6 @@ def pin_step_weights(lib):
 ALL_PINS = [
     pin_closed_form_level, pin_zero_radius, pin_bisection, pin_mirror, pin_edge_sign,
     pin_hand_profiles, pin_conservation_random, pin_conservation_scan, pin_brute_force,
-    pin_planted_sources, pin_poisson_recovery, pin_tilted_axis_bisection,
+    pin_totals_planted, pin_planted_sources, pin_poisson_recovery, pin_tilted_axis_bisection,
     pin_tilted_axis_brute_force, pin_activity, pin_select_top, pin_step_weights,
 ]

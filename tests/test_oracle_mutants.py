@@ -31,16 +31,18 @@ MUTANTS = [
     ("trailing_dI_sign", "double dI = trailing ? I[k + 1] - I[k] : I[k] - I[k + 1];",
      "double dI = trailing ? I[k] - I[k + 1] : I[k] - I[k + 1];"),
     ("trailing_side", "if (trailing) s = -s;", "if (trailing) s = s;"),
-    ("both_not_averaged", "oracle_bin_profile(uk, Ik, n_steps, n_bins, 1, 0.5, o, stride);",
-     "oracle_bin_profile(uk, Ik, n_steps, n_bins, 1, 1.0, o, stride);"),
-    ("both_drops_trailing", "oracle_bin_profile(uk, Ik, n_steps, n_bins, 1, 0.5, o, stride);",
-     "oracle_bin_profile(uk, Ik, n_steps, n_bins, 0, 0.5, o, stride);"),
-    ("weight_ignored", "out[(int64_t)bd * stride] += dI * (w * (ov / len));",
-     "out[(int64_t)bd * stride] += dI * (ov / len);"),
+    ("both_not_averaged", "o[(int64_t)b * stride] = 0.5 * (L[b] + T[b]);",
+     "o[(int64_t)b * stride] = L[b] + T[b];"),
+    ("both_leading_twice", "o[(int64_t)b * stride] = 0.5 * (L[b] + T[b]);",
+     "o[(int64_t)b * stride] = 0.5 * (L[b] + L[b]);"),
+    ("both_trailing_dI_sign", "oracle_bin_profile(uk, Ik, n_steps, n_bins, 1, T, 1);",
+     "oracle_bin_profile(uk, Ik, n_steps, n_bins, 0, T, 1);"),
+    ("totals_bin_shift", "totals[b] = t;", "totals[(b + 1) % n_bins] = t;"),
+    ("totals_reversed", "totals[b] = t;", "totals[n_bins - 1 - b] = t;"),
     ("top_swap", "double top = hi < bd + 1.0 ? hi : bd + 1.0;",
      "double top = hi < bd + 1.0 ? bd + 1.0 : hi;"),
-    ("no_normalise", "out[(int64_t)bd * stride] += dI * (w * (ov / len));",
-     "out[(int64_t)bd * stride] += dI * (w * ov);"),
+    ("no_normalise", "if (ov > 0.0) out[(int64_t)bd * stride] += dI * (ov / len);",
+     "if (ov > 0.0) out[(int64_t)bd * stride] += dI * ov;"),
     ("ceil_first", "double first = floor(lo), last = floor(hi);",
      "double first = ceil(lo), last = floor(hi);"),
     ("pixel_transposed", "for (int q = 0; q < 3; ++q) X[q] = (origin[q] + i * u[q]) + j * v[q];",
@@ -53,8 +55,8 @@ MUTANTS = [
      "*xi = (X[0] * f->e1[0] + X[1] * f->e1[1]);"),
     ("step_reversed", "Ik[k] = (double)images[(int64_t)k * plane_in + p];",
      "Ik[k] = (double)images[(int64_t)(n_steps - 1 - k) * plane_in + p];"),
-    ("point_mass_sign", "if (bd >= 0.0 && bd < (double)n_bins) out[(int64_t)bd * stride] += dI * w;",
-     "if (bd >= 0.0 && bd < (double)n_bins) out[(int64_t)bd * stride] -= dI * w;"),
+    ("point_mass_sign", "if (bd >= 0.0 && bd < (double)n_bins) out[(int64_t)bd * stride] += dI;",
+     "if (bd >= 0.0 && bd < (double)n_bins) out[(int64_t)bd * stride] -= dI;"),
     ("lo_hi_swap", "double lo = u[k] < u[k + 1] ? u[k] : u[k + 1];",
      "double lo = u[k];"),
     ("activity_no_abs", "a += (uint64_t)(d < 0 ? -d : d);", "a += (uint64_t)d;"),
@@ -64,7 +66,7 @@ MUTANTS = [
      "return g_sel_act[a] < g_sel_act[b] ? -1 : 1;"),
     ("weight_wrong_step", "if (step_weight) Ik[k] = Ik[k] * step_weight[k];",
      "if (step_weight) Ik[k] = Ik[k] * step_weight[n_steps - 1 - k];"),
-    ("weight_ignored", "if (step_weight) Ik[k] = Ik[k] * step_weight[k];",
+    ("step_weight_ignored", "if (step_weight) Ik[k] = Ik[k] * step_weight[k];",
      "if (step_weight) Ik[k] = Ik[k];"),
     ("select_ties_high", "    return a < b ? -1 : (a > b ? 1 : 0);\n}\nstatic int idx_cmp",
      "    return a > b ? -1 : (a < b ? 1 : 0);\n}\nstatic int idx_cmp"),
