@@ -71,11 +71,12 @@ typedef int32_t dr_status;
 /* Wire edges (dr_wire.edge).  Leading: the side whose shadow advances with
  * the scan, I_k - I_{k+1} spread over its interval (intensity lost as the edge
  * covers a depth slice).  Trailing: the opposite side, I_{k+1} - I_k
- * (intensity regained as it uncovers the slice).  Both: the average of the
- * two reconstructions (a true source keeps its amplitude, the mirrored
- * negative ghosts of the two edges are halved): half of every leading-edge
- * contribution is added first, then half of every trailing-edge one, each
- * bin in step order. */
+ * (intensity regained as it uncovers the slice).  Both: the average
+ * (L + T)/2 of the two reconstructions, each formed on its own (a true source
+ * keeps its amplitude, the mirrored negative ghosts of the two edges are
+ * halved).  The FP32 path stores L/2 in a first pass and adds T/2, summed
+ * from zero, in a second; the FP64 instance forms T/2 in a buffer of its own
+ * and adds the two buffers. */
 #define DR_EDGE_LEADING 0
 #define DR_EDGE_TRAILING 1
 #define DR_EDGE_BOTH 2

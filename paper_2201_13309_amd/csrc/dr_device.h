@@ -600,23 +600,29 @@ __device__ __forceinline__ void process_tile_mono(const ScanArgs& a, int row,
     for (int q = 0; q < PPL; ++q) acc[q] = (Acc)0;
     int cb = -1;  // open bin (uniform), -1 = none
 
-    // ADD (second pass of two): an opened bin starts from the first pass's
-    // value and the contributions are added one by one in step order (the
-    // oracle's sequential accumulation); cacc keeps this pass's own sum for
-    // the totals
-    constexpr bool add_on = ADD;
-    Acc cacc[PPL];
+    // ADD (second pass of two edges): the open bin accumulates this pass's own
+    // contributions from zero, in step order, and is stored as the first
+    // pass's value plus that sum, so that the output is the first pass's
+    // reconstruction plus the second's, each formed on its own; base holds the
+    // first pass's value of the open bin
+    Acc base[PPL];
 #pragma unroll
-    for (int q = 0; q < PPL; ++q) cacc[q] = (Acc)0;
+    for (int q = 0; q < PPL; ++q) base[q] = (Acc)0;
     auto put = [&]() {
-        if (act) store_bins<Acc, PPL>(outp(cb), acc);
+        if (act) {
+            if constexpr (ADD) {
+                Acc v[PPL];
+#pragma unroll
+                for (int q = 0; q < PPL; ++q) v[q] = base[q] + acc[q];
+                store_bins<Acc, PPL>(outp(cb), v);
+            } else {
+                store_bins<Acc, PPL>(outp(cb), acc);
+            }
+        }
         if (pwin.row) {
             Acc s = (Acc)0;
 #pragma unroll
-            for (int q = 0; q < PPL; ++q) {
-                if constexpr (ADD) s += cacc[q];
-                else s += acc[q];
-            }
+            for (int q = 0; q < PPL; ++q) s += acc[q];
             pwin.add(cb, wave_total(act ? s : (Acc)0), lane);
         }
     };
@@ -641,20 +647,13 @@ __device__ __forceinline__ void process_tile_mono(const ScanArgs& a, int row,
                 if constexpr (ADD) {
                     const Acc* o = outp(b);
 #pragma unroll
-                    for (int q = 0; q < PPL; ++q) {
-                        acc[q] = madd(f, dI[q], act ? o[q] : (Acc)0);
-                        cacc[q] = madd(f, dI[q], (Acc)0);
-                    }
-                } else {
-#pragma unroll
-                    for (int q = 0; q < PPL; ++q) acc[q] = madd(f, dI[q], (Acc)0);
+                    for (int q = 0; q < PPL; ++q) base[q] = act ? o[q] : (Acc)0;
                 }
+#pragma unroll
+                for (int q = 0; q < PPL; ++q) acc[q] = madd(f, dI[q], (Acc)0);
             } else {
 #pragma unroll
                 for (int q = 0; q < PPL; ++q) acc[q] = madd(f, dI[q], acc[q]);
-                if constexpr (ADD)
-#pragma unroll
-                    for (int q = 0; q < PPL; ++q) cacc[q] = madd(f, dI[q], cacc[q]);
             }
         };
         if constexpr (NB2) {
@@ -706,7 +705,7 @@ __device__ __forceinline__ void process_tile_mono(const ScanArgs& a, int row,
     if (cb >= 0) put();
     // bins outside the row's touched range are zero; stored after the last load
     const int blo = a.row_lo[row], bhi = a.row_hi[row];
-    if (act && !add_on) {
+    if (act && !ADD) {
         Acc z[PPL];
 #pragma unroll
         for (int q = 0; q < PPL; ++q) z[q] = (Acc)0;
@@ -748,13 +747,17 @@ __global__ __launch_bounds__(64 * WAVES) void rows_f32_kernel(ScanArgs a)
                                              L);
 }
 
-template <bool ADD, bool NORM>
+// FP64 instance: every pass is launched as a pass of its own (a two-edge
+// reconstruction forms its second pass in a buffer of its own and adds the two
+// afterwards), so there is no adding variant.
+template <bool NORM>
 __global__ __launch_bounds__(256) void rows_f64_kernel(ScanArgs a)
 {
     __shared__ PlanLds<double> L;
     const int row = a.row_begin + (int)(blockIdx.x / (unsigned)a.tiles_per_row);
     const int tile = (int)(blockIdx.x % (unsigned)a.tiles_per_row);
-    process_tile<double, 1, 4, 4, ADD, NORM>(a, row, row_tile_addr<double, 1, 4>(a, row, tile), L);
+    process_tile<double, 1, 4, 4, false, NORM>(a, row, row_tile_addr<double, 1, 4>(a, row, tile),
+                                               L);
 }
 
 // Scans with per-step sample weights: one launch shape (a pixel per lane,
@@ -792,11 +795,11 @@ __global__ __launch_bounds__(256) void list_f32_kernel(ScanArgs a, ListArgs l)
     list_wave_tile<float, PF, ADD, NORM>(a, l, L);
 }
 
-template <bool ADD, bool NORM>
+template <bool NORM>
 __global__ __launch_bounds__(256) void list_f64_kernel(ScanArgs a, ListArgs l)
 {
     __shared__ PlanLds<double, kWaveChunk> L[4];
-    list_wave_tile<double, 4, ADD, NORM>(a, l, L);
+    list_wave_tile<double, 4, false, NORM>(a, l, L);
 }
 
 // Persistent grid: workgroups pull (scan, tile) items until the queue is dry.

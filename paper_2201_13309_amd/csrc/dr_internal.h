@@ -115,7 +115,11 @@ hipError_t launch_build_plans(const GeomArgs& g, const PlanTables& t, int side, 
 // rows generic in either of two plans become generic in both
 hipError_t launch_unify_classes(int8_t* a, int8_t* b, int ny, hipStream_t s);
 hipError_t launch_rows_f32(const TileCfg& t, const ScanArgs& a, hipStream_t s);
+// FP64 instance: a.pass must not be 2 (each pass of a two-edge reconstruction
+// is launched as a pass of its own, the second into a buffer of its own)
 hipError_t launch_rows_f64(const ScanArgs& a, hipStream_t s);
+// out[i] = out[i] + other[i], i < n (adds the FP64 second pass onto the first)
+hipError_t launch_add_f64(double* out, const double* other, int64_t n, hipStream_t s);
 // add: every scan of the launch is the second pass of two (pass 2)
 hipError_t launch_batch_f32(const TileCfg& t, const BatchArgs& b, bool add, int groups,
                             hipStream_t s);

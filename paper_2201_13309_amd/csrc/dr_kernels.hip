@@ -3,6 +3,8 @@
 // (the row-tile and batch instantiations are in dr_tiles_*.hip).
 #include "dr_device.h"
 
+#include <algorithm>
+
 #pragma clang fp contract(off)
 
 namespace dr {
@@ -266,18 +268,27 @@ hipError_t launch_rows_f64(const ScanArgs& a, hipStream_t s)
 {
     const int64_t rows = a.row_end - a.row_begin;
     if (rows <= 0) return hipSuccess;
+    if (a.pass == 2) return hipErrorInvalidValue;  // FP64 passes are each launched on their own
     const dim3 grid((unsigned)(rows * a.tiles_per_row));
-    if (a.wk) {
-        if (a.pass == 2)
-            hipLaunchKernelGGL((rows_f64_kernel<true, true>), grid, dim3(256), 0, s, a);
-        else
-            hipLaunchKernelGGL((rows_f64_kernel<false, true>), grid, dim3(256), 0, s, a);
-    } else {
-        if (a.pass == 2)
-            hipLaunchKernelGGL((rows_f64_kernel<true, false>), grid, dim3(256), 0, s, a);
-        else
-            hipLaunchKernelGGL((rows_f64_kernel<false, false>), grid, dim3(256), 0, s, a);
-    }
+    if (a.wk)
+        hipLaunchKernelGGL((rows_f64_kernel<true>), grid, dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((rows_f64_kernel<false>), grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void add_into_kernel(double* out, const double* other, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = out[i] + other[i];
+}
+
+hipError_t launch_add_f64(double* out, const double* other, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t groups = std::min<int64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(add_into_kernel, dim3((unsigned)groups), dim3(256), 0, s, out, other, n);
     return hipGetLastError();
 }
 
@@ -361,16 +372,14 @@ hipError_t launch_list_f32(const ScanArgs& a, const ListArgs& lt, int64_t n_tile
 hipError_t launch_list_f64(const ScanArgs& a, const ListArgs& lt, int64_t n_tiles, hipStream_t s)
 {
     if (n_tiles <= 0) return hipSuccess;
+    if (a.pass == 2) return hipErrorInvalidValue;  // FP64 passes are each launched on their own
     ListArgs l = lt;
     l.tile_end = l.tile_first + n_tiles;
     const dim3 grid((unsigned)((n_tiles + 3) / 4));  // four wave tiles per workgroup
-    const int v = (a.pass == 2 ? 1 : 0) + (a.wk ? 2 : 0);
-    switch (v) {
-    case 0: hipLaunchKernelGGL((list_f64_kernel<false, false>), grid, dim3(256), 0, s, a, l); break;
-    case 1: hipLaunchKernelGGL((list_f64_kernel<true, false>), grid, dim3(256), 0, s, a, l); break;
-    case 2: hipLaunchKernelGGL((list_f64_kernel<false, true>), grid, dim3(256), 0, s, a, l); break;
-    default: hipLaunchKernelGGL((list_f64_kernel<true, true>), grid, dim3(256), 0, s, a, l); break;
-    }
+    if (a.wk)
+        hipLaunchKernelGGL((list_f64_kernel<true>), grid, dim3(256), 0, s, a, l);
+    else
+        hipLaunchKernelGGL((list_f64_kernel<false>), grid, dim3(256), 0, s, a, l);
     return hipGetLastError();
 }
 

@@ -401,10 +401,25 @@ dr_status dr_reconstruct_list_f64(dr_list l, const uint16_t* images_dev, int32_t
     }
     const int64_t step = compact ? l->n : (int64_t)g->nx * g->ny;
     const ListArgs la = list_args(l, compact);
-    for (int p = 0; p < g->passes; ++p) {
-        const ScanArgs a = list_scan_args(l, p, images_dev, step, out, part, 8, slots);
-        DR_HIP(launch_list_pass(l, p, a, la, groups, true, s));
+    // two edges: the second pass is formed in a buffer of its own and added
+    // onto the first (as in dr_reconstruct_f64)
+    const int64_t n_out = (int64_t)g->n_bins * l->n;
+    double* second = nullptr;
+    if (g->passes == 2 && n_out > 0)
+        DR_HIP(hipMallocAsync((void**)&second, (size_t)n_out * sizeof(double), s));
+    hipError_t e = hipSuccess;
+    for (int p = 0; p < g->passes && e == hipSuccess; ++p) {
+        ScanArgs a = list_scan_args(l, p, images_dev, step, p == 0 ? out : second, part, 8,
+                                    slots);
+        a.pass = 0;
+        e = launch_list_pass(l, p, a, la, groups, true, s);
     }
+    if (e == hipSuccess && second) e = launch_add_f64(out, second, n_out, s);
+    if (second) {
+        const hipError_t ef = hipFreeAsync(second, s);
+        if (e == hipSuccess) e = ef;
+    }
+    DR_HIP(e);
     if (totals) {
         if (groups == 0) {
             DR_HIP(hipMemsetAsync(totals, 0, (size_t)g->n_bins * sizeof(double), s));

@@ -1,9 +1,11 @@
 // Per-pixel path (gfx950): geometries whose detector rows do not share one
 // projected position (a tilted detector, a wire axis not along x, an explicit
 // pixel table), so every pixel computes its own FP64 edge positions, one per
-// wire step, in the operation order of the tangent construction (Sec. III-B,
-// the depth of each pixel at each wire position) without contraction, and
-// spreads each intensity difference over the bins its interval overlaps.
+// wire step, in the fixed operation order of the tangent construction (the
+// paper leaves the geometry to the wire-scan method it cites; the construction
+// here is the reading stated in the library header) without contraction, and
+// spreads each intensity difference over the bins its interval overlaps
+// (Sec. III-C: each pixel's differences are added into depth arrays).
 //
 //   pixels_f32_kernel  FP32 accumulation.  ALU-bound: per (pixel, step) one
 //                      FP64 square root and one FP64 division; the interval's
@@ -354,7 +356,8 @@ __global__ __launch_bounds__(kPixelTile) void pixels_f32_kernel(ScanArgs a, Geom
 }
 
 // FP64 instance of the per-pixel path: one lane per pixel of a row tile of
-// kPixelTile pixels.  Each
+// kPixelTile pixels; every pass is launched as a pass of its own (the second
+// pass of two edges writes into a buffer of its own).  Each
 // lane computes its own FP64 positions step by step, plans the interval, and
 // streams its bins in the direction its edge moves (bins are visited in order
 // then; a bin already stored and visited again is read, added to and
@@ -371,7 +374,6 @@ __global__ __launch_bounds__(kPixelTile) void pixels_kernel(ScanArgs a, GeomArgs
     extern __shared__ __align__(16) unsigned char dyn_lds[];
     const int tid = threadIdx.x;
     const int N = a.n_steps, B = a.n_bins;
-    const bool add_on = a.pass == 2;
     const bool tot = a.partials != nullptr;
     bool act;
     int64_t pixel, slot;              // pixel index; partial-total row of the workgroup
@@ -442,13 +444,11 @@ __global__ __launch_bounds__(kPixelTile) void pixels_kernel(ScanArgs a, GeomArgs
             tacc = madd(fr, dI, tacc);
         } else if (bp >= nxt) {
             close_open();
-            if (!add_on)
-                for (int z = nxt; z < bp; ++z) store(z, (Acc)0);
+            for (int z = nxt; z < bp; ++z) store(z, (Acc)0);
             cbp = bp;
             nxt = bp;
-            Acc* o = op + (int64_t)b * plane;
-            acc = madd(fr, dI, (add_on && act) ? *o : (Acc)0);
-            tacc = madd(fr, dI, (Acc)0);
+            acc = madd(fr, dI, (Acc)0);
+            tacc = acc;
         } else if (act) {  // stored already: read, add, rewrite
             Acc* o = op + (int64_t)b * plane;
             *o = madd(fr, dI, *o);
@@ -494,8 +494,7 @@ __global__ __launch_bounds__(kPixelTile) void pixels_kernel(ScanArgs a, GeomArgs
         }
     }
     close_open();
-    if (!add_on)
-        for (int z = nxt; z < B; ++z) store(z, (Acc)0);
+    for (int z = nxt; z < B; ++z) store(z, (Acc)0);
     if (tot && in_lds) {
         __syncthreads();
         for (int b = tid; b < B; b += kPixelTile) gp[b] = ltot[b];

@@ -129,7 +129,7 @@ hipError_t launch_scan_f32(const dr_geom g, const TileCfg& t, int p, const ScanA
     return launch_pixels_f32(a, g->g, g->side[p], g->scale[p], s);
 }
 
-static TileCfg choose_tile(dr_geom g, const void* img, const void* out)
+TileCfg choose_tile(dr_geom g, const void* img, const void* out)
 {
     std::lock_guard<std::mutex> lk(g->mu);
     if (g->weighted) return TileCfg{1, 4, 16};  // the weighted kernel's one shape
@@ -144,6 +144,35 @@ static dr_status ensure_scratch(dr_geom g, const TileCfg& t, float** part)
     DR_HIP(g->part32.reserve(need));
     DR_HIP(g->work.reserve((size_t)kTotalsWorkRows * g->n_bins * sizeof(double)));
     *part = g->part32.as<float>();
+    return DR_OK;
+}
+
+size_t partials_bytes(const dr_geom g, const TileCfg& t)
+{
+    const size_t b = (size_t)g->passes * partial_slots(g, t) * g->n_bins * sizeof(float);
+    return (b + 255) & ~(size_t)255;
+}
+
+size_t totals_work_bytes(const dr_geom g)
+{
+    return (size_t)kTotalsWorkRows * g->n_bins * sizeof(double);
+}
+
+dr_status reconstruct_device_into(dr_geom g, const TileCfg& t, const uint16_t* images, float* out,
+                                  float* totals, float* part, double* work, hipStream_t s)
+{
+    if (g->timing) DR_HIP(hipEventRecord(g->ev[0], s));
+    for (int p = 0; p < g->passes; ++p) {
+        ScanArgs a = scan_args(g, t, p, images, (int64_t)g->nx * g->ny, 0, 0, g->ny, out,
+                               totals ? part : nullptr);
+        DR_HIP(launch_scan_f32(g, t, p, a, s));
+    }
+    if (g->timing) DR_HIP(hipEventRecord(g->ev[1], s));
+    if (totals) DR_HIP(enqueue_totals(g, part, partial_slots(g, t), work, totals, s));
+    if (g->timing) {
+        DR_HIP(hipEventRecord(g->ev[2], s));
+        g->timed = true;
+    }
     return DR_OK;
 }
 
@@ -516,19 +545,7 @@ static dr_status reconstruct_device(dr_geom g, const TileCfg& t, const uint16_t*
         dr_status st = ensure_scratch(g, t, &part);
         if (st != DR_OK) return st;
     }
-    if (g->timing) DR_HIP(hipEventRecord(g->ev[0], s));
-    for (int p = 0; p < g->passes; ++p) {
-        ScanArgs a = scan_args(g, t, p, images, (int64_t)g->nx * g->ny, 0, 0, g->ny, out, part);
-        DR_HIP(launch_scan_f32(g, t, p, a, s));
-    }
-    if (g->timing) DR_HIP(hipEventRecord(g->ev[1], s));
-    if (totals)
-        DR_HIP(enqueue_totals(g, part, partial_slots(g, t), g->work.as<double>(), totals, s));
-    if (g->timing) {
-        DR_HIP(hipEventRecord(g->ev[2], s));
-        g->timed = true;
-    }
-    return DR_OK;
+    return reconstruct_device_into(g, t, images, out, totals, part, g->work.as<double>(), s);
 }
 
 static int slab_rows(const dr_geom g)
@@ -630,16 +647,29 @@ dr_status dr_reconstruct_f64(dr_geom g, const uint16_t* images, double* out, dou
         part = g->part64.as<double>();
     }
     const int64_t slots = partial_slots(g, t);
-    for (int p = 0; p < g->passes; ++p) {
+    // two edges: each pass is a reconstruction of its own (halved fractions),
+    // the second formed in a stream-ordered buffer of its own and then added
+    // onto the first, so that out = L/2 + T/2
+    const int64_t n_out = (int64_t)g->n_bins * g->nx * g->ny;
+    double* second = nullptr;
+    if (g->passes == 2)
+        DR_HIP(hipMallocAsync((void**)&second, (size_t)n_out * sizeof(double), s));
+    hipError_t e = hipSuccess;
+    for (int p = 0; p < g->passes && e == hipSuccess; ++p) {
         ScanArgs a = scan_args(g, t, p, images, (int64_t)g->nx * g->ny, 0, 0, g->ny, nullptr,
                                nullptr);
-        a.out = out;
+        a.pass = 0;
+        a.out = p == 0 ? (void*)out : (void*)second;
         a.partials = part ? part + (size_t)p * slots * g->n_bins : nullptr;
-        if (g->row_mode)
-            DR_HIP(launch_rows_f64(a, s));
-        else
-            DR_HIP(launch_pixels_f64(a, g->g, g->side[p], g->scale[p], s));
+        e = g->row_mode ? launch_rows_f64(a, s)
+                        : launch_pixels_f64(a, g->g, g->side[p], g->scale[p], s);
     }
+    if (e == hipSuccess && second) e = launch_add_f64(out, second, n_out, s);
+    if (second) {
+        const hipError_t ef = hipFreeAsync(second, s);
+        if (e == hipSuccess) e = ef;
+    }
+    DR_HIP(e);
     if (totals)
         DR_HIP(launch_totals_f64(part, slots * g->passes, g->n_bins, g->work.as<double>(),
                                  kTotalsWorkRows, totals, s));

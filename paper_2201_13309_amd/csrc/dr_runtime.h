@@ -150,6 +150,17 @@ TileCfg solo_tile(const dr_geom g);
 hipError_t launch_scan_f32(const dr_geom g, const TileCfg& t, int pass, const ScanArgs& a,
                            hipStream_t s);
 
+// launch shape dr_reconstruct uses for these buffers (forced, tuned or default)
+TileCfg choose_tile(dr_geom g, const void* img, const void* out);
+// scratch of a device-image reconstruction with totals: the partial-total rows
+// of every pass (rounded up to 256 bytes), then the totals reduction workspace
+size_t partials_bytes(const dr_geom g, const TileCfg& t);
+size_t totals_work_bytes(const dr_geom g);
+// every pass of a device-image reconstruction and its totals, with the
+// caller's scratch (part and work are unused when totals is null)
+dr_status reconstruct_device_into(dr_geom g, const TileCfg& t, const uint16_t* images, float* out,
+                                  float* totals, float* part, double* work, hipStream_t s);
+
 Scheduler* make_scheduler(dr_ctx ctx);
 void destroy_scheduler(Scheduler* s);
 
