@@ -1,304 +1,178 @@
-// Serving: a request queue with admission by device-memory footprint and
-// continuous batching.  One scheduler thread per context:
+// Serving: dr_submit / dr_poll / dr_wait.  The scheduling policy (admission
+// by footprint, slab interleaving, epochs, failure handling) is the Core of
+// dr_sched.cpp; this file is its executor on one GPU and the thread that
+// drives it.
 //
-//   admit    FIFO; the head request is admitted when the memory it needs
-//            (device copy of host images, partial totals) fits the budget;
-//   copy     host images travel in row slabs on the copy stream, slabs of all
-//            admitted requests interleaved (shortest remaining first), at most
-//            two slabs in flight, so a small request never queues behind a
-//            full-frame copy;
-//   epoch    every pass launches one persistent kernel (per pixels-per-lane
-//            group) over the resident, not yet processed row tiles of every
-//            admitted request; at most two epochs are in flight, so requests
-//            that arrive while others run join the next one;
-//   finish   after a request's last rows: totals, a completion event and the
-//            stream-ordered release of its buffers.
-//
-// Each output element is produced by the same tile code as dr_reconstruct.
+//   allocate   stream-ordered allocations: the staging copy of host images on
+//              the copy stream (its first user), partial totals on the compute
+//              stream;
+//   copy       rows [r0, r0 + rows) of every step with one 2D copy on the copy
+//              stream, then an event;
+//   epoch      per pass and pixels-per-lane group, one persistent launch of
+//              the batch kernel over the epoch's row segments (the same tile
+//              code as dr_reconstruct); requests on the per-pixel path or with
+//              step weights get launches of their own kernel; then the totals
+//              of the finishing requests and an event on the compute stream;
+//   release    stream-ordered frees once the core has seen every copy and
+//              epoch of the request complete.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
-#include <deque>
 #include <thread>
-#include <unordered_map>
 
 #include "dr_runtime.h"
+#include "dr_sched.h"
 
 namespace dr {
 
 namespace {
 
-constexpr int kEpochSlots = 3;     // epoch argument buffers in rotation
-constexpr int kEpochsInFlight = 2;
-constexpr int kCopiesInFlight = 2;
-constexpr int kMaxActive = 64;     // admitted requests at a time
-constexpr int kMaxSegs = 256;      // request segments per epoch and group
-constexpr int kGroups = 6;         // (pass 1 or 2) x (4, 2 or 1 pixels per lane)
+constexpr int kMaxSegs = sched::kMaxActive;  // segments per epoch and group
+constexpr int kGroups = 6;                   // (pass 1 or 2) x (4, 2 or 1 pixels per lane)
 
-struct Request {
-    uint64_t id = 0;
+// HIP state of one request
+struct Work {
     dr_geom g = nullptr;
     const uint16_t* images = nullptr;  // caller's (host or device)
     bool on_device = false;
     float* out = nullptr;
     float* totals = nullptr;
-    size_t footprint = 0;
     TileCfg tile{4, 4, 16};
-    uint16_t* staged = nullptr;        // device copy of host images
+    uint16_t* staged = nullptr;  // device copy of host images
     float* parts = nullptr;
     double* work = nullptr;
-    int rows_copied = 0;               // rows whose copy has been enqueued
-    int rows_ready = 0;                // rows resident on the device
-    int rows_next = 0;                 // rows handed to an epoch
-    std::deque<std::pair<hipEvent_t, int>> copies;  // in-flight slab copies
-    hipEvent_t done = nullptr;
-    bool finishing = false;            // totals/done enqueued
-    int state = 0;                     // 0 queued, 1 admitted, 2 complete, 3 failed
-    dr_status result = DR_PENDING;
 };
 
-struct EpochSlot {
-    DevBuf args;   // ScanArgs[kGroups][kMaxSegs] + starts[kGroups][kMaxSegs+1] + counters
+Work* work_of(sched::Req& r) { return static_cast<Work*>(r.user); }
+
+size_t image_bytes(const dr_geom g) { return (size_t)g->nx * g->ny * g->n_steps * sizeof(uint16_t); }
+
+size_t parts_bytes(const dr_geom g, const TileCfg& t)
+{
+    return (size_t)g->passes * partial_slots(g, t) * g->n_bins * sizeof(float);
+}
+
+struct EpochArgs {
+    DevBuf args;  // ScanArgs[kGroups][kMaxSegs], starts[kGroups][kMaxSegs+1], counters[kGroups]
     ScanArgs* h_args = nullptr;  // pinned staging
     int64_t* h_starts = nullptr;
-    hipEvent_t uploaded = nullptr;
-    hipEvent_t finished = nullptr;
-    bool busy = false;
 };
 
-}  // namespace
-
-struct Scheduler {
-    dr_ctx ctx;
-    std::mutex mu;
-    std::condition_variable cv;       // wakes the scheduler thread
-    std::condition_variable done_cv;  // wakes dr_wait
-    bool stop = false;
-    uint64_t next_id = 1;
-    std::deque<Request*> queue;       // not yet admitted
-    std::vector<Request*> active;     // admitted, not complete
-    std::unordered_map<uint64_t, Request*> all;
-    size_t in_use = 0;
-    int copies_in_flight = 0;
-    EpochSlot slots[kEpochSlots];
-    int slot_next = 0;
-    dr_stats stats{};
-    std::thread th;
-    std::vector<hipEvent_t> event_pool;
-
-    hipEvent_t get_event()
+class HipExecutor : public sched::Executor {
+public:
+    explicit HipExecutor(dr_ctx c) : ctx_(c) {}
+    ~HipExecutor() override
     {
-        if (!event_pool.empty()) {
-            hipEvent_t e = event_pool.back();
-            event_pool.pop_back();
-            return e;
+        for (auto& es : slots_) {
+            if (es.h_args) (void)hipHostFree(es.h_args);
+            if (es.h_starts) (void)hipHostFree(es.h_starts);
         }
-        hipEvent_t e = nullptr;
-        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
-        return e;
-    }
-    void put_event(hipEvent_t e)
-    {
-        if (e) event_pool.push_back(e);
+        for (hipEvent_t e : pool_) (void)hipEventDestroy(e);
     }
 
-    void fail(Request* r, dr_status code)
+    bool init()
     {
-        r->state = 3;
-        r->result = code;
-        done_cv.notify_all();
-    }
-
-    static size_t staging_bytes(const Request* r)
-    {
-        return r->on_device ? 0
-                            : (size_t)r->g->nx * r->g->ny * r->g->n_steps * sizeof(uint16_t);
-    }
-    static size_t parts_bytes(const Request* r)
-    {
-        return r->totals ? (size_t)r->g->passes * partial_slots(r->g, r->tile) * r->g->n_bins *
-                                   sizeof(float) +
-                               (size_t)kTotalsWorkRows * r->g->n_bins * sizeof(double)
-                         : 0;
-    }
-
-    // ---------------------------------------------------------------- steps
-
-    void admit()
-    {
-        while (!queue.empty() && (int)active.size() < kMaxActive) {
-            Request* r = queue.front();
-            if (in_use + r->footprint > ctx->budget) break;
-            const size_t sb = staging_bytes(r);
-            hipError_t e = hipSuccess;
-            if (sb) e = hipMallocAsync((void**)&r->staged, sb, ctx->copy);
-            if (e == hipSuccess && r->totals) {
-                const size_t pb =
-                    (size_t)r->g->passes * partial_slots(r->g, r->tile) * r->g->n_bins * sizeof(float);
-                e = hipMallocAsync((void**)&r->parts, pb, ctx->copy);
-                if (e == hipSuccess)
-                    e = hipMallocAsync((void**)&r->work,
-                                       (size_t)kTotalsWorkRows * r->g->n_bins * sizeof(double),
-                                       ctx->copy);
-            }
-            queue.pop_front();
-            if (e != hipSuccess) {
-                fail(r, e == hipErrorOutOfMemory ? DR_E_NOMEM : DR_E_DEVICE);
-                r->g->inflight--;
-                continue;
-            }
-            in_use += r->footprint;
-            r->state = 1;
-            if (r->on_device) {
-                r->rows_copied = r->rows_ready = r->g->ny;
-            } else {
-                // buffers allocated on the copy stream are ready for its copies;
-                // the compute stream sees them through the slab events
-            }
-            active.push_back(r);
-            stats.admitted++;
+        for (auto& es : slots_) {
+            const size_t bytes = sizeof(ScanArgs) * kGroups * kMaxSegs +
+                                 sizeof(int64_t) * kGroups * (kMaxSegs + 1) +
+                                 sizeof(unsigned long long) * kGroups;
+            if (es.args.reserve(bytes) != hipSuccess ||
+                hipHostMalloc((void**)&es.h_args, sizeof(ScanArgs) * kGroups * kMaxSegs, 0) !=
+                    hipSuccess ||
+                hipHostMalloc((void**)&es.h_starts, sizeof(int64_t) * kGroups * (kMaxSegs + 1),
+                              0) != hipSuccess)
+                return false;
         }
+        return true;
     }
 
-    void issue_copies()
+    uint64_t tiles_launched = 0;
+
+    dr_status allocate(sched::Req& r) override
     {
-        while (copies_in_flight < kCopiesInFlight) {
-            Request* best = nullptr;
-            int64_t best_left = 0;
-            for (Request* r : active) {
-                if (r->on_device || r->rows_copied >= r->g->ny) continue;
-                const int64_t left = (int64_t)(r->g->ny - r->rows_copied) * r->g->nx * r->g->n_steps;
-                if (!best || left < best_left) {
-                    best = r;
-                    best_left = left;
-                }
-            }
-            if (!best) return;
-            Request* r = best;
-            const size_t row_bytes = (size_t)r->g->nx * r->g->n_steps * sizeof(uint16_t);
-            const int R = std::max(1, std::min(r->g->ny, (int)(((size_t)64 << 20) / row_bytes)));
-            const int r0 = r->rows_copied, rs = std::min(R, r->g->ny - r0);
-            const size_t plane = (size_t)r->g->nx * r->g->ny;
-            // rows [r0, r0+rs) of every step, into the same place of the device copy
-            hipError_t e = hipMemcpy2DAsync(r->staged + (size_t)r0 * r->g->nx, plane * 2,
-                                            r->images + (size_t)r0 * r->g->nx, plane * 2,
-                                            (size_t)rs * r->g->nx * 2, (size_t)r->g->n_steps,
-                                            hipMemcpyHostToDevice, ctx->copy);
-            hipEvent_t ev = get_event();
-            if (e == hipSuccess && ev) e = hipEventRecord(ev, ctx->copy);
-            if (e != hipSuccess || !ev) {
-                fail(r, DR_E_DEVICE);
-                return;
-            }
-            r->copies.push_back({ev, r0 + rs});
-            r->rows_copied = r0 + rs;
-            copies_in_flight++;
-            stats.bytes_h2d += (uint64_t)rs * row_bytes;
+        Work* w = work_of(r);
+        hipError_t e = hipSuccess;
+        if (!w->on_device) e = hipMallocAsync((void**)&w->staged, image_bytes(w->g), ctx_->copy);
+        if (e == hipSuccess && w->totals) {
+            e = hipMallocAsync((void**)&w->parts, parts_bytes(w->g, w->tile), ctx_->stream);
+            if (e == hipSuccess)
+                e = hipMallocAsync((void**)&w->work,
+                                   (size_t)kTotalsWorkRows * w->g->n_bins * sizeof(double),
+                                   ctx_->stream);
         }
-    }
-
-    void poll_copies()
-    {
-        for (Request* r : active) {
-            while (!r->copies.empty()) {
-                hipError_t q = hipEventQuery(r->copies.front().first);
-                if (q == hipErrorNotReady) break;
-                if (q != hipSuccess) {
-                    fail(r, DR_E_DEVICE);
-                    break;
-                }
-                r->rows_ready = r->copies.front().second;
-                put_event(r->copies.front().first);
-                r->copies.pop_front();
-                copies_in_flight--;
-            }
+        if (e != hipSuccess) {  // nothing stays allocated
+            free_buffers(*w);
+            return e == hipErrorOutOfMemory ? DR_E_NOMEM : DR_E_DEVICE;
         }
+        return DR_OK;
     }
 
-    int epochs_in_flight()
+    dr_status copy_rows(sched::Req& r, int r0, int rows, sched::Event* ev) override
     {
-        int n = 0;
-        for (auto& s : slots)
-            if (s.busy) {
-                hipError_t q = hipEventQuery(s.finished);
-                if (q == hipErrorNotReady) n++;
-                else s.busy = false;
-            }
-        return n;
-    }
-
-    bool launch_epoch()
-    {
-        if (epochs_in_flight() >= kEpochsInFlight) return false;
-        EpochSlot* es = nullptr;
-        for (int i = 0; i < kEpochSlots && !es; ++i) {
-            EpochSlot& s = slots[(slot_next + i) % kEpochSlots];
-            if (!s.busy) {
-                es = &s;
-                slot_next = (slot_next + i + 1) % kEpochSlots;
-            }
+        Work* w = work_of(r);
+        const dr_geom g = w->g;
+        const size_t plane = (size_t)g->nx * g->ny;
+        hipEvent_t he = get_event();
+        if (!he) return DR_E_DEVICE;
+        // rows [r0, r0+rows) of every step, into the same place of the device copy
+        hipError_t e = hipMemcpy2DAsync(w->staged + (size_t)r0 * g->nx, plane * 2,
+                                        w->images + (size_t)r0 * g->nx, plane * 2,
+                                        (size_t)rows * g->nx * 2, (size_t)g->n_steps,
+                                        hipMemcpyHostToDevice, ctx_->copy);
+        if (e == hipSuccess) e = hipEventRecord(he, ctx_->copy);
+        if (e != hipSuccess) {
+            put_event(he);
+            // a copy already enqueued before the failure may still run
+            (void)hipStreamSynchronize(ctx_->copy);
+            return DR_E_DEVICE;
         }
-        if (!es) return false;
-        // segments: resident, unprocessed rows of every admitted request,
-        // grouped by pass and pixels per lane (one launch per group; every
-        // second-pass launch follows every first-pass launch of the epoch)
+        *ev = reinterpret_cast<sched::Event>(he);
+        return DR_OK;
+    }
+
+    dr_status launch_epoch(int slot, const std::vector<sched::Segment>& segs,
+                           const std::vector<sched::Req*>& finishing, sched::Event* ev) override
+    {
+        EpochArgs& es = slots_[slot];
+        hipStream_t s = ctx_->stream;
         static const int kPpl[3] = {4, 2, 1};
         int nseg[kGroups] = {0, 0, 0, 0, 0, 0};
         int64_t tiles[kGroups] = {0, 0, 0, 0, 0, 0};
-        std::vector<Request*> finishing;
-        struct Solo {
-            Request* r;
-            int row_begin, row_end;
-        };
-        std::vector<Solo> solos;  // per-pixel and weighted requests: launched on their own
-        for (Request* r : active) {
-            if (r->state != 1 || r->finishing) continue;
-            if (batch_solo(r->g)) {
-                if (r->rows_ready > r->rows_next) {
-                    solos.push_back({r, r->rows_next, r->rows_ready});
-                    r->rows_next = r->rows_ready;
-                }
-                if (r->rows_next == r->g->ny) finishing.push_back(r);
+        std::vector<const sched::Segment*> solos;  // per-pixel and weighted requests
+        for (const sched::Segment& sg : segs) {
+            Work* w = work_of(*sg.r);
+            if (batch_solo(w->g)) {
+                solos.push_back(&sg);
                 continue;
             }
-            const int pi = r->tile.ppl == 4 ? 0 : (r->tile.ppl == 2 ? 1 : 2);
-            const int passes = r->g->passes;
-            bool room = true;
-            for (int p = 0; p < passes; ++p) room = room && nseg[p * 3 + pi] < kMaxSegs;
-            if (r->rows_ready > r->rows_next && room) {
-                const uint16_t* img = r->on_device ? r->images : r->staged;
-                for (int p = 0; p < passes; ++p) {
-                    const int gi = p * 3 + pi;
-                    ScanArgs a = scan_args(r->g, r->tile, p, img, (int64_t)r->g->nx * r->g->ny,
-                                           0, r->rows_next, r->rows_ready, r->out, r->parts);
-                    const int sg = nseg[gi]++;
-                    es->h_args[gi * kMaxSegs + sg] = a;
-                    int64_t* st = es->h_starts + gi * (kMaxSegs + 1);
-                    if (sg == 0) st[0] = 0;
-                    st[sg + 1] = st[sg] + (int64_t)(r->rows_ready - r->rows_next) * a.tiles_per_row;
-                    tiles[gi] = st[sg + 1];
-                }
-                r->rows_next = r->rows_ready;
+            const int pi = w->tile.ppl == 4 ? 0 : (w->tile.ppl == 2 ? 1 : 2);
+            const uint16_t* img = w->on_device ? w->images : w->staged;
+            for (int p = 0; p < w->g->passes; ++p) {
+                const int gi = p * 3 + pi;
+                if (nseg[gi] >= kMaxSegs) return DR_E_DEVICE;  // cannot happen: one per request
+                const ScanArgs a = scan_args(w->g, w->tile, p, img,
+                                             (int64_t)w->g->nx * w->g->ny, 0, sg.row_begin,
+                                             sg.row_end, w->out, w->parts);
+                const int k = nseg[gi]++;
+                es.h_args[gi * kMaxSegs + k] = a;
+                int64_t* st = es.h_starts + gi * (kMaxSegs + 1);
+                if (k == 0) st[0] = 0;
+                st[k + 1] = st[k] + (int64_t)(sg.row_end - sg.row_begin) * a.tiles_per_row;
+                tiles[gi] = st[k + 1];
             }
-            if (r->rows_next == r->g->ny) finishing.push_back(r);
         }
-        int nall = (int)solos.size();
-        for (int gi = 0; gi < kGroups; ++gi) nall += nseg[gi];
-        if (nall == 0 && finishing.empty()) return false;
-        hipStream_t s = ctx->stream;
-        char* dbase = es->args.as<char>();
+        char* dbase = es.args.as<char>();
         ScanArgs* d_args = (ScanArgs*)dbase;
         int64_t* d_starts = (int64_t*)(dbase + sizeof(ScanArgs) * kGroups * kMaxSegs);
         unsigned long long* d_cnt =
             (unsigned long long*)(dbase + sizeof(ScanArgs) * kGroups * kMaxSegs +
                                   sizeof(int64_t) * kGroups * (kMaxSegs + 1));
-        hipError_t e = hipSuccess;
-        // the pinned staging of this slot was last read by an upload that has
-        // completed (the slot is not busy), so it can be rewritten and sent
-        e = hipMemcpyAsync(d_args, es->h_args, sizeof(ScanArgs) * kGroups * kMaxSegs,
-                           hipMemcpyHostToDevice, s);
+        // the pinned staging of this slot was last read by an epoch that has
+        // completed (the core reuses a slot only then)
+        hipError_t e = hipMemcpyAsync(d_args, es.h_args, sizeof(ScanArgs) * kGroups * kMaxSegs,
+                                      hipMemcpyHostToDevice, s);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(d_starts, es->h_starts, sizeof(int64_t) * kGroups * (kMaxSegs + 1),
+            e = hipMemcpyAsync(d_starts, es.h_starts, sizeof(int64_t) * kGroups * (kMaxSegs + 1),
                                hipMemcpyHostToDevice, s);
         // rows are handed out only after the host has seen their copy event
         // complete, so the kernels below read finished copies
@@ -311,109 +185,119 @@ struct Scheduler {
             ba.total_tiles = tiles[gi];
             ba.counter = d_cnt + gi;
             const TileCfg t{kPpl[gi % 3], 4, 16};
-            // 8 persistent 4-wave workgroups per CU (2048 threads); 2 left the GPU a third idle
-            const int groups = (int)std::max<int64_t>(1, std::min<int64_t>(ctx->cus * 8, tiles[gi]));
+            // 8 persistent 4-wave workgroups per CU (2048 threads)
+            const int groups =
+                (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)ctx_->cus * 8, tiles[gi]));
             e = launch_reset_counter(ba.counter, s);
             // groups 3..5 hold second passes, which add onto the first
             if (e == hipSuccess) e = launch_batch_f32(t, ba, gi >= 3, groups, s);
-            stats.tiles_launched += (uint64_t)tiles[gi];
+            tiles_launched += (uint64_t)tiles[gi];
         }
-        for (const Solo& so : solos) {
-            Request* r = so.r;
-            const uint16_t* img = r->on_device ? r->images : r->staged;
-            for (int p = 0; p < r->g->passes && e == hipSuccess; ++p) {
-                const ScanArgs a = scan_args(r->g, r->tile, p, img, (int64_t)r->g->nx * r->g->ny,
-                                             0, so.row_begin, so.row_end, r->out, r->parts);
-                e = launch_scan_f32(r->g, r->tile, p, a, s);
-                stats.tiles_launched += (uint64_t)(so.row_end - so.row_begin) * a.tiles_per_row;
+        for (const sched::Segment* sg : solos) {
+            Work* w = work_of(*sg->r);
+            const uint16_t* img = w->on_device ? w->images : w->staged;
+            for (int p = 0; p < w->g->passes && e == hipSuccess; ++p) {
+                const ScanArgs a = scan_args(w->g, w->tile, p, img,
+                                             (int64_t)w->g->nx * w->g->ny, 0, sg->row_begin,
+                                             sg->row_end, w->out, w->parts);
+                e = launch_scan_f32(w->g, w->tile, p, a, s);
+                tiles_launched += (uint64_t)(sg->row_end - sg->row_begin) * a.tiles_per_row;
             }
         }
-        for (Request* r : finishing) {
+        for (sched::Req* r : finishing) {
             if (e != hipSuccess) break;
-            if (r->totals)
-                e = enqueue_totals(r->g, r->parts, partial_slots(r->g, r->tile), r->work,
-                                   r->totals, s);
-            r->done = get_event();
-            if (e == hipSuccess && r->done) e = hipEventRecord(r->done, s);
-            if (e == hipSuccess && r->staged) e = hipFreeAsync(r->staged, s);
-            if (e == hipSuccess && r->parts) e = hipFreeAsync(r->parts, s);
-            if (e == hipSuccess && r->work) e = hipFreeAsync(r->work, s);
-            r->staged = nullptr;
-            r->parts = nullptr;
-            r->work = nullptr;
-            r->finishing = true;
+            Work* w = work_of(*r);
+            if (w->totals)
+                e = enqueue_totals(w->g, w->parts, partial_slots(w->g, w->tile), w->work,
+                                   w->totals, s);
         }
-        if (e == hipSuccess) e = hipEventRecord(es->finished, s);
+        hipEvent_t he = nullptr;
+        if (e == hipSuccess) {
+            he = get_event();
+            if (!he) e = hipErrorOutOfMemory;
+        }
+        if (e == hipSuccess) e = hipEventRecord(he, s);
         if (e != hipSuccess) {
-            for (Request* r : active) fail(r, DR_E_DEVICE);
-            return false;
+            if (he) put_event(he);
+            // what this call enqueued before the failure has finished
+            (void)hipStreamSynchronize(s);
+            return DR_E_DEVICE;
         }
-        es->busy = true;
-        stats.epochs++;
-        return true;
+        *ev = reinterpret_cast<sched::Event>(he);
+        return DR_OK;
     }
 
-    void poll_done()
+    sched::Poll query(sched::Event ev) override
     {
-        for (size_t i = 0; i < active.size();) {
-            Request* r = active[i];
-            bool remove = false;
-            if (r->state == 3) {
-                remove = true;
-            } else if (r->finishing && r->done) {
-                hipError_t q = hipEventQuery(r->done);
-                if (q == hipSuccess) {
-                    r->state = 2;
-                    r->result = DR_OK;
-                    stats.completed++;
-                    remove = true;
-                } else if (q != hipErrorNotReady) {
-                    fail(r, DR_E_DEVICE);
-                    remove = true;
-                }
-            }
-            if (remove) {
-                in_use -= r->footprint;
-                for (void* p : {(void*)r->staged, (void*)r->parts, (void*)r->work})
-                    if (p) (void)hipFreeAsync(p, ctx->stream);
-                r->staged = nullptr;
-                r->parts = nullptr;
-                r->work = nullptr;
-                put_event(r->done);
-                r->done = nullptr;
-                r->g->inflight--;
-                active.erase(active.begin() + i);
-                done_cv.notify_all();
-            } else {
-                ++i;
-            }
-        }
+        const hipError_t q = hipEventQuery(reinterpret_cast<hipEvent_t>(ev));
+        if (q == hipErrorNotReady) return sched::kPending;
+        return q == hipSuccess ? sched::kDone : sched::kFailed;
     }
 
-    bool busy_gpu()
+    void forget(sched::Event ev) override { put_event(reinterpret_cast<hipEvent_t>(ev)); }
+
+    void release(sched::Req& r) override { free_buffers(*work_of(r)); }
+
+    void finished(sched::Req& r) override { work_of(r)->g->inflight--; }
+
+private:
+    // stream-ordered frees: the staging buffer on the copy stream, the partial
+    // totals on the compute stream (each after its last user there)
+    void free_buffers(Work& w)
     {
-        if (copies_in_flight > 0) return true;
-        for (auto& s : slots)
-            if (s.busy) return true;
-        for (Request* r : active)
-            if (r->finishing) return true;
-        return false;
+        if (w.staged) (void)hipFreeAsync(w.staged, ctx_->copy);
+        if (w.parts) (void)hipFreeAsync(w.parts, ctx_->stream);
+        if (w.work) (void)hipFreeAsync(w.work, ctx_->stream);
+        w.staged = nullptr;
+        w.parts = nullptr;
+        w.work = nullptr;
     }
+    hipEvent_t get_event()
+    {
+        if (!pool_.empty()) {
+            hipEvent_t e = pool_.back();
+            pool_.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+        return e;
+    }
+    void put_event(hipEvent_t e)
+    {
+        if (e) pool_.push_back(e);
+    }
+
+    dr_ctx ctx_;
+    EpochArgs slots_[sched::kEpochSlots];
+    std::vector<hipEvent_t> pool_;
+};
+
+}  // namespace
+
+struct Scheduler {
+    explicit Scheduler(dr_ctx c) : ctx(c), ex(c), core(ex, c->budget) {}
+    dr_ctx ctx;
+    HipExecutor ex;
+    sched::Core core;
+    std::mutex mu;
+    std::condition_variable cv;       // wakes the scheduler thread
+    std::condition_variable done_cv;  // wakes dr_wait
+    bool stop = false;
+    uint64_t next_id = 1;
+    std::thread th;
 
     void run()
     {
         (void)hipSetDevice(ctx->device);
         std::unique_lock<std::mutex> lk(mu);
-        while (!stop || !queue.empty() || !active.empty()) {
-            admit();
-            // copies must follow the allocations made on the copy stream
-            issue_copies();
-            poll_copies();
-            while (launch_epoch()) {
-            }
-            poll_done();
-            if (stop && queue.empty() && active.empty()) break;
-            if (busy_gpu())
+        for (;;) {
+            const uint64_t ended = core.counters().completed + core.counters().failed;
+            const bool busy = core.step();
+            if (core.counters().completed + core.counters().failed != ended)
+                done_cv.notify_all();
+            if (stop && core.idle()) break;
+            if (busy)
                 cv.wait_for(lk, std::chrono::microseconds(100));
             else
                 cv.wait_for(lk, std::chrono::milliseconds(20));
@@ -423,27 +307,16 @@ struct Scheduler {
 
 Scheduler* make_scheduler(dr_ctx ctx)
 {
-    auto* s = new Scheduler();
-    s->ctx = ctx;
-    for (auto& es : s->slots) {
-        const size_t bytes = sizeof(ScanArgs) * kGroups * kMaxSegs +
-                             sizeof(int64_t) * kGroups * (kMaxSegs + 1) +
-                             sizeof(unsigned long long) * kGroups;
-        if (es.args.reserve(bytes) != hipSuccess ||
-            hipHostMalloc((void**)&es.h_args, sizeof(ScanArgs) * kGroups * kMaxSegs, 0) != hipSuccess ||
-            hipHostMalloc((void**)&es.h_starts, sizeof(int64_t) * kGroups * (kMaxSegs + 1), 0) != hipSuccess ||
-            hipEventCreateWithFlags(&es.uploaded, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&es.finished, hipEventDisableTiming) != hipSuccess) {
-            destroy_scheduler(s);
-            return nullptr;
-        }
+    auto* s = new Scheduler(ctx);
+    if (!s->ex.init()) {
+        delete s;
+        return nullptr;
     }
     hipMemPool_t pool;
     if (hipDeviceGetDefaultMemPool(&pool, ctx->device) == hipSuccess) {
         uint64_t thr = UINT64_MAX;
         (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
     }
-    s->stats.hbm_budget = ctx->budget;
     s->th = std::thread([s] { s->run(); });
     return s;
 }
@@ -459,14 +332,14 @@ void destroy_scheduler(Scheduler* s)
     if (s->th.joinable()) s->th.join();
     (void)hipStreamSynchronize(s->ctx->stream);
     (void)hipStreamSynchronize(s->ctx->copy);
-    for (auto& kv : s->all) delete kv.second;
-    for (auto& es : s->slots) {
-        if (es.h_args) (void)hipHostFree(es.h_args);
-        if (es.h_starts) (void)hipHostFree(es.h_starts);
-        if (es.uploaded) (void)hipEventDestroy(es.uploaded);
-        if (es.finished) (void)hipEventDestroy(es.finished);
+    // requests never collected by dr_poll / dr_wait
+    for (;;) {
+        sched::Req* r = nullptr;
+        for (uint64_t id = 1; id < s->next_id && !r; ++id) r = s->core.take(id);
+        if (!r) break;
+        delete work_of(*r);
+        delete r;
     }
-    for (hipEvent_t e : s->event_pool) (void)hipEventDestroy(e);
     delete s;
 }
 
@@ -482,38 +355,50 @@ dr_status dr_submit(dr_ctx c, dr_geom g, const uint16_t* images, int images_on_d
     if (!c || !g || !images || !out || !ticket)
         return set_error(DR_E_INVAL, "dr_submit: NULL argument");
     if (g->ctx != c) return set_error(DR_E_INVAL, "dr_submit: geometry of another context");
-    auto r = std::make_unique<Request>();
-    r->g = g;
-    r->images = images;
-    r->on_device = images_on_device != 0;
-    r->out = out;
-    r->totals = totals;
+    auto w = std::make_unique<Work>();
+    w->g = g;
+    w->images = images;
+    w->on_device = images_on_device != 0;
+    w->out = out;
+    w->totals = totals;
     if (batch_solo(g)) {
-        r->tile = solo_tile(g);
+        w->tile = solo_tile(g);
     } else {
-        r->tile = default_tile(g, r->on_device ? (const void*)images : nullptr, out);
-        r->tile.waves = 4;
-        r->tile.prefetch = 16;
+        w->tile = default_tile(g, w->on_device ? (const void*)images : nullptr, out);
+        w->tile.waves = 4;
+        w->tile.prefetch = 16;
     }
-    if (!tile_fits(g, r->tile, r->on_device ? (const void*)images : nullptr, out))
+    if (!tile_fits(g, w->tile, w->on_device ? (const void*)images : nullptr, out))
         return set_error(DR_E_INVAL, "dr_submit: misaligned buffer");
-    r->footprint = Scheduler::staging_bytes(r.get()) + Scheduler::parts_bytes(r.get());
+    auto r = std::make_unique<sched::Req>();
+    r->ny = g->ny;
+    r->row_bytes = (size_t)g->nx * g->n_steps * sizeof(uint16_t);
+    r->on_device = w->on_device;
+    // device bytes the request occupies while in flight: its images (the
+    // caller's on the device, or the staging copy), its output, and the
+    // partial totals with their reduction workspace
+    r->footprint = image_bytes(g) + (size_t)g->n_bins * g->nx * g->ny * sizeof(float) +
+                   (totals ? parts_bytes(g, w->tile) +
+                                 (size_t)kTotalsWorkRows * g->n_bins * sizeof(double)
+                           : 0);
     if (!c->sched) {
         std::lock_guard<std::mutex> lk(c->mu);
         if (!c->sched) c->sched = make_scheduler(c);
         if (!c->sched) return set_error(DR_E_DEVICE, "dr_submit: cannot start the scheduler");
     }
     Scheduler* s = c->sched;
-    if (r->footprint > c->budget)
-        return set_error(DR_E_NOMEM, "dr_submit: request larger than the device-memory budget");
     {
         std::lock_guard<std::mutex> lk(s->mu);
-        r->id = s->next_id++;
+        r->id = s->next_id;
+        r->user = w.get();
+        const dr_status st = s->core.submit(r.get());
+        if (st != DR_OK)
+            return set_error(st, "dr_submit: request larger than the device-memory budget");
+        s->next_id++;
         *ticket = r->id;
         g->inflight++;
-        s->stats.submitted++;
-        s->all[r->id] = r.get();
-        s->queue.push_back(r.release());
+        w.release();
+        r.release();
     }
     s->cv.notify_all();
     return DR_OK;
@@ -522,13 +407,13 @@ dr_status dr_submit(dr_ctx c, dr_geom g, const uint16_t* images, int images_on_d
 static dr_status collect(Scheduler* s, uint64_t ticket, bool wait)
 {
     std::unique_lock<std::mutex> lk(s->mu);
-    auto it = s->all.find(ticket);
-    if (it == s->all.end()) return set_error(DR_E_NOTFOUND, "unknown or collected ticket");
-    Request* r = it->second;
-    if (wait) s->done_cv.wait(lk, [r] { return r->state >= 2; });
-    if (r->state < 2) return DR_PENDING;
+    sched::Req* r = s->core.find(ticket);
+    if (!r) return set_error(DR_E_NOTFOUND, "unknown or collected ticket");
+    if (wait) s->done_cv.wait(lk, [r] { return r->state >= sched::kComplete; });
+    if (r->state < sched::kComplete) return DR_PENDING;
+    r = s->core.take(ticket);
     const dr_status res = r->result;
-    s->all.erase(it);
+    delete work_of(*r);
     delete r;
     if (res != DR_OK) return set_error(res, "request failed on the device");
     return DR_OK;
@@ -555,8 +440,14 @@ dr_status dr_ctx_stats(dr_ctx c, dr_stats* out)
     out->hbm_budget = c->budget;
     if (!c->sched) return DR_OK;
     std::lock_guard<std::mutex> lk(c->sched->mu);
-    *out = c->sched->stats;
-    out->hbm_in_use = c->sched->in_use;
+    const sched::Counters& k = c->sched->core.counters();
+    out->submitted = k.submitted;
+    out->admitted = k.admitted;
+    out->completed = k.completed;
+    out->epochs = k.epochs;
+    out->tiles_launched = c->sched->ex.tiles_launched;
+    out->bytes_h2d = k.bytes_h2d;
+    out->hbm_in_use = k.in_use;
     out->hbm_budget = c->budget;
     return DR_OK;
 }

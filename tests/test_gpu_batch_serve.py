@@ -155,7 +155,10 @@ def test_serving_tight_budget_queues(dr):
     admission and still produce the same results; an oversized request is
     refused at submission."""
     scans = uneven_scans(10)
-    biggest = max(s.images.nbytes for s in scans)
+    # a request's footprint: its images, its output, its partial totals (at
+    # most an eighth of the output here) and their workspace
+    biggest = max(s.images.nbytes + 4 * s.grid.n_bins * s.detector.nx * s.detector.ny
+                  for s in scans)
     small_ctx = dr.dr_ctx_create(0, int(biggest * 1.5) + (8 << 20))
     try:
         singles = [alone(dr, small_ctx, s) for s in scans]
