@@ -80,7 +80,8 @@ def stream_probe(torch, dev, out, stream, ev0, ev1):
     if not os.path.exists(path) or out.numel() < dev.numel() or dev.dim() != 3:
         return None
     lib = ctypes.CDLL(path)
-    for f in (lib.dr_probe_stream, lib.dr_probe_planes):
+    for f in (lib.dr_probe_stream, lib.dr_probe_planes, lib.dr_probe_planes_read,
+              lib.dr_probe_planes_write):
         f.restype = ctypes.c_int
         f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
                       ctypes.c_void_p]
@@ -89,7 +90,11 @@ def stream_probe(torch, dev, out, stream, ev0, ev1):
     n = dev.numel() - dev.numel() % 8
     runs = {"planes": (lib.dr_probe_planes, (src, dst, dev.shape[1] * dev.shape[2],
                                               dev.shape[0], sp), 1.0),
-            "linear": (lib.dr_probe_stream, (src, dst, n, 0, sp), dev.numel() / n)}
+            "linear": (lib.dr_probe_stream, (src, dst, n, 0, sp), dev.numel() / n),
+            "read": (lib.dr_probe_planes_read, (src, dst, dev.shape[1] * dev.shape[2],
+                                                dev.shape[0], sp), 1.0),
+            "write": (lib.dr_probe_planes_write, (src, dst, dev.shape[1] * dev.shape[2],
+                                                  dev.shape[0], sp), 1.0)}
     res = {}
     for name, (fn, args, scale) in runs.items():
         if fn(*args) != 0:
@@ -104,37 +109,77 @@ def stream_probe(torch, dev, out, stream, ev0, ev1):
     return res
 
 
+def host_threads() -> int:
+    """Threads the oracle runs on: the OpenMP thread count this process is
+    given (the host's CPU share), else every CPU in its affinity mask."""
+    try:
+        n = int(os.environ.get("OMP_NUM_THREADS", "0"))
+    except ValueError:
+        n = 0
+    return n if n > 0 else len(os.sched_getaffinity(0))
+
+
+def host_cpu() -> dict:
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"model": model, "cpus_visible": len(os.sched_getaffinity(0)),
+            "threads_used": host_threads()}
+
+
+def oracle_slabs(scan, target_s: float, rows_per_slab: int = 128, nthreads: int = 0):
+    """The oracle over slabs of rows of a scan (FP64 output per slab), until
+    the whole frame is done or `target_s` of CPU wall time is spent.  Returns
+    (rows done, seconds, FP64 totals over the rows done)."""
+    import oracle
+    det = scan.detector
+    rows, spent = 0, 0.0
+    tot = np.zeros(scan.grid.n_bins, dtype=np.float64)
+    while rows < det.ny and spent < target_s:
+        n = min(rows_per_slab, det.ny - rows)
+        t0 = time.perf_counter()
+        _, t, _ = oracle.reconstruct(scan, row0=rows, nrows=n, nthreads=nthreads or host_threads())
+        spent += time.perf_counter() - t0
+        tot += t
+        rows += n
+    return rows, spent, tot
+
+
 def cpu_baseline(scan, target_s: float):
     """The oracle as it stands, timed on slabs of 128 rows of the same scan
-    (the whole frame when it fits the time budget; FP64 output per slab)."""
-    import oracle
-    cores = min(16, os.cpu_count() or 1)
+    (the whole frame when it fits the time budget; FP64 output per slab).
+    Also returns the oracle's totals when the whole frame was done."""
     det, N = scan.detector, scan.wire.n_steps
-    rows = 0
-    spent = 0.0
-    while rows < det.ny and spent < target_s:
-        n = min(128, det.ny - rows)
-        t0 = time.perf_counter()
-        oracle.reconstruct(scan, row0=rows, nrows=n, nthreads=cores)
-        spent += time.perf_counter() - t0
-        rows += n
+    rows, spent, tot = oracle_slabs(scan, target_s)
     work = rows * det.nx * N
     what = "the whole" if rows == det.ny else f"rows 0..{rows - 1} of the"
-    return {"value": work / spent, "unit": UNIT, "cores": cores, "kind": "oracle",
-            "sample": f"{what} {det.nx}x{det.ny}x{N}-step scan in 128-row slabs "
-                      f"({work:.3e} pixel-wire-steps, FP64, {spent:.1f} s)"}
+    cpu = host_cpu()
+    res = {"value": work / spent, "unit": UNIT, "cores": cpu["threads_used"], "kind": "oracle",
+           "cpu": cpu,
+           "sample": f"{what} {det.nx}x{det.ny}x{N}-step scan in 128-row slabs "
+                     f"({work:.3e} pixel-wire-steps, FP64, {spent:.1f} s)"}
+    return res, (tot if rows == det.ny else None)
 
 
-def run_size_sweep(torch, synth, dr, ctx, s, host, dev, out, tot, stream, steps: int):
+def run_size_sweep(torch, synth, dr, ctx, s, host, dev, out, tot, stream, steps: int,
+                   cpu_s_budget: float):
     """The paper's data-size experiment on this machine: stacks of 2.1, 2.7,
     3.6 and 5.2 GB (the first 250, 322, 429 and 620 steps of the 2048x2048
     scan, same detector and depth grid), GPU time from HBM and from pinned
-    host memory, and the oracle's time estimated from a 64-row sample on the
-    host's cores; the ratio GPU / CPU is the paper's metric."""
-    import oracle
+    host memory, and the oracle's wall time on the whole frame of each (128-row
+    slabs on the host's cores, every pixel and step); the ratio GPU / CPU is
+    the paper's metric.  When the oracle's total time would pass
+    `cpu_s_budget` the remaining sizes are timed on their first rows and
+    scaled, and the entry says so."""
     d, grid = s.detector, s.grid
-    cores = min(16, os.cpu_count() or 1)
+    cores = host_threads()
     res = []
+    spent = 0.0
     for n_steps in (250, 322, 429, 620):
         wire = synth.Wire(s.wire.radius, np.ascontiguousarray(s.wire.centers[:n_steps]))
         g = dr.dr_geometry_init(ctx, d, wire, grid)
@@ -156,24 +201,136 @@ def run_size_sweep(torch, synth, dr, ctx, s, host, dev, out, tot, stream, steps:
         finally:
             dr.dr_geometry_free(g)
         scan = synth.Scan("sweep", d, wire, grid, None, 0.0, False, 0)
-        img = hv.numpy().view(np.uint16)
-        t0 = time.perf_counter()
-        oracle.reconstruct(scan, images=img, row0=0, nrows=64, nthreads=cores)
-        cpu_rate = 64 * d.nx * n_steps / (time.perf_counter() - t0)
+        scan.images = hv.numpy().view(np.uint16)
+        rows, cpu_s, _ = oracle_slabs(scan, max(1.0, cpu_s_budget - spent))
+        spent += cpu_s
+        whole = rows == d.ny
+        if not whole:
+            cpu_s *= d.ny / rows
         work = d.nx * d.ny * n_steps
-        cpu_s = work / cpu_rate
         res.append({"input_GB": 2 * work / 1e9, "steps": n_steps, "gpu_ms": gpu_ms,
-                    "gpu_from_host_ms": host_ms, "cpu_s_estimate": cpu_s,
+                    "gpu_from_host_ms": host_ms, "cpu_s": cpu_s,
+                    "cpu_rows_timed": rows, "cpu_whole_frame": whole,
                     "gpu_over_cpu": gpu_ms * 1e-3 / cpu_s,
                     "gpu_from_host_over_cpu": host_ms * 1e-3 / cpu_s})
         log(f"size {2 * work / 1e9:.1f} GB: GPU {gpu_ms:.2f} ms (from host {host_ms:.0f} ms), "
-            f"CPU oracle ~{cpu_s:.1f} s on {cores} threads")
+            f"CPU oracle {cpu_s:.1f} s on {cores} threads"
+            + ("" if whole else f" (scaled from {rows} rows)"))
     return {"note": "the paper's dataset sizes; GPU / CPU time is its metric (25-30% on its "
-                    "Fermi GPU against a 4-core Xeon); CPU time from a 64-row oracle sample",
+                    "Fermi GPU against a 4-core Xeon); CPU time is the oracle's over the whole "
+                    "frame unless cpu_whole_frame is false",
             "cores": cores, "sizes": res}
 
 
-def run_per_pixel(torch, synth, dr, ctx, s, dev, out, tot, stream, steps: int):
+def sampled_error(scan, out_dev, pix):
+    """max over the listed pixels and every bin of |gpu - oracle| divided by
+    the pixel's sum_k |I_k - I_{k+1}| (pixels with no change skipped), with
+    the number of elements compared."""
+    import torch
+    import oracle
+    N, B = scan.wire.n_steps, scan.grid.n_bins
+    ref, _, _ = oracle.reconstruct_pixels(scan, pix, want_bins=False, nthreads=host_threads())
+    got = out_dev.reshape(B, -1)[:, torch.from_numpy(pix).to(out_dev.device)].T.cpu().numpy()
+    series = scan.images.reshape(N, -1)[:, pix].T.astype(np.int64)
+    scale = np.abs(np.diff(series, axis=1)).sum(1).astype(np.float64)
+    keep = scale > 0
+    err = np.abs(got.astype(np.float64) - ref)[keep] / scale[keep, None]
+    return (float(err.max()) if err.size else 0.0), int(err.size)
+
+
+def totals_error(tot_gpu, tot_ref, scale_total):
+    """max over bins of |gpu - oracle| over sum_p sum_k |I_k - I_{k+1}|."""
+    t = tot_gpu.double().cpu().numpy() if hasattr(tot_gpu, "cpu") else np.asarray(tot_gpu)
+    return float(np.abs(t - tot_ref).max() / max(scale_total, 1e-300))
+
+
+def stack_scale(torch, images, rows=64):
+    """sum over pixels and steps of |I_k - I_{k+1}| of an int16 tensor of
+    uint16 counts [N][ny][nx] (host or device), on the device."""
+    total = 0.0
+    for r0 in range(0, images.shape[1], rows):
+        blk = images[:, r0:r0 + rows].to("cuda").to(torch.int32) & 0xFFFF
+        total += float((blk[1:] - blk[:-1]).abs().sum(dtype=torch.float64))
+    return total
+
+
+def sample_pixels(nx, ny, n, seed):
+    rng = np.random.default_rng(seed)
+    edge = [0, nx - 1, (ny - 1) * nx, ny * nx - 1]
+    return np.unique(np.concatenate([edge, rng.integers(0, nx * ny, n)]))
+
+
+def run_small_configs(torch, synth, dr, ctx, stream, steps: int):
+    """The 64x64 px, 41-step, 101-bin scan and the 1024x1024 px, 401-step,
+    501-bin scan, each in full: GPU time per call (images resident in HBM,
+    autotuned shape, kernel and totals), the oracle's wall time on the host's
+    cores (best of 3) and on one core, and the FP32 path's error against the
+    oracle over every element and every total."""
+    import oracle
+    res = {}
+    threads = host_threads()
+    for name, gen in (("config1", synth.config1), ("config2", synth.config2)):
+        sc = gen()
+        det, grid, N = sc.detector, sc.grid, sc.wire.n_steps
+        dev = torch.from_numpy(sc.images.view(np.int16)).to("cuda")
+        out = torch.empty((grid.n_bins, det.ny, det.nx), dtype=torch.float32, device="cuda")
+        tot = torch.empty((grid.n_bins,), dtype=torch.float32, device="cuda")
+        g = dr.dr_geometry_init(ctx, det, sc.wire, grid)
+        try:
+            dr.dr_autotune(g, dev, out)
+            for _ in range(2):
+                dr.dr_reconstruct(g, dev, True, out, tot, stream)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(steps):
+                dr.dr_reconstruct(g, dev, True, out, tot, stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            gpu_ms = e0.elapsed_time(e1) / steps
+        finally:
+            dr.dr_geometry_free(g)
+        times = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            ref, tref, _ = oracle.reconstruct(sc, nthreads=threads)
+            times.append(time.perf_counter() - t0)
+        t_multi = min(times)
+        t1 = []
+        for _ in range(3 if name == "config1" else 1):
+            t0 = time.perf_counter()
+            oracle.reconstruct(sc, nthreads=1)
+            t1.append(time.perf_counter() - t0)
+        t_single = min(t1)
+        o = out.cpu().numpy()
+        I = sc.images
+        err = 0.0
+        scale_total = 0.0
+        for r0 in range(0, det.ny, 128):  # row blocks keep the FP64 temporaries small
+            blk = I[:, r0:r0 + 128].astype(np.int32)
+            scale = np.abs(np.diff(blk, axis=0)).sum(0).astype(np.float64)
+            scale_total += float(scale.sum())
+            d = np.abs(o[:, r0:r0 + 128].astype(np.float64) - ref[:, r0:r0 + 128])
+            keep = scale > 0
+            if keep.any():
+                err = max(err, float((d[:, keep] / scale[keep][None]).max()))
+        del ref, o, dev, out
+        work = det.nx * det.ny * N
+        res[name] = {
+            "workload": f"{det.nx}x{det.ny} px, {N} steps, {grid.n_bins} bins, whole scan",
+            "gpu_ms": gpu_ms, "gpu_value": work / (gpu_ms * 1e-3),
+            "oracle_s": t_multi, "oracle_threads": threads, "oracle_single_core_s": t_single,
+            "oracle_over_gpu": t_multi / (gpu_ms * 1e-3),
+            "precision": {"max_rel_elem": err, "elements": int(grid.n_bins * det.nx * det.ny),
+                          "max_rel_totals": totals_error(tot, tref, scale_total)}}
+        log(f"{name}: GPU {gpu_ms:.3f} ms, oracle {t_multi:.2f} s on {threads} threads, "
+            f"{t_single:.2f} s on one core; FP32 error {err:.2e} of sum|dI|")
+        torch.cuda.empty_cache()
+    return res
+
+
+def run_per_pixel(torch, synth, dr, ctx, s, dev, out, tot, stream, steps: int,
+                  precision: bool = True, scale_total: float = 0.0):
     """The per-pixel path at the same size: the detector's columns tilted 0.3
     degrees out of the x axis (u gains a z part), so no two pixels of a row
     share a projected position.  The images are the flat-detector stack,
@@ -193,18 +350,33 @@ def run_per_pixel(torch, synth, dr, ctx, s, dev, out, tot, stream, steps: int):
         ev1.record(stream)
         torch.cuda.synchronize()
         ms = ev0.elapsed_time(ev1) / steps
+        kl = []
         dr.dr_enable_timing(g, True)
-        dr.dr_reconstruct(g, dev, True, out, tot, stream)
-        kms, _ = dr.dr_last_timing(g)
+        for _ in range(steps):
+            dr.dr_reconstruct(g, dev, True, out, tot, stream)
+            kl.append(dr.dr_last_timing(g)[0])
         dr.dr_enable_timing(g, False)
+        kms = float(np.mean(kl))
     finally:
         dr.dr_geometry_free(g)
     work = d.nx * d.ny * s.wire.n_steps
-    log(f"per-pixel path: {ms:.2f} ms/step")
-    return {"value": work / (ms * 1e-3), "unit": UNIT, "ms_per_step": ms, "kernel_ms": kms,
-            "kernel": "pixels_f32_kernel", "steps": steps,
-            "geometry": "detector columns tilted 0.3 deg out of x (u = (200, 0, 1) um): "
-                        "positions computed per pixel in FP64 on the fly"}
+    log(f"per-pixel path: {ms:.2f} ms/step (kernel {kms:.2f} ms)")
+    res = {"value": work / (ms * 1e-3), "unit": UNIT, "ms_per_step": ms, "kernel_ms": kms,
+           "kernel": "pixels_f32_kernel", "steps": steps,
+           "geometry": "detector columns tilted 0.3 deg out of x (u = (200, 0, 1) um): "
+                       "positions computed per pixel in FP64 on the fly"}
+    if precision:
+        ts = synth.Scan("tilted", det, s.wire, s.grid, None, 0.0, False, 0)
+        ts.images = s.images
+        e, n = sampled_error(ts, out, sample_pixels(d.nx, d.ny, 2000, 34))
+        rows, cpu_s, tref = oracle_slabs(ts, 1e9)
+        res["precision"] = {"max_rel_elem": e, "elements": n,
+                            "sample": "2000 random pixels plus the corners, every bin",
+                            "max_rel_totals": totals_error(tot, tref, scale_total),
+                            "totals_oracle_s": cpu_s}
+        log(f"per-pixel path: FP32 error {e:.2e} of sum|dI| on the sample, totals "
+            f"{res['precision']['max_rel_totals']:.2e}")
+    return res
 
 
 def run_pixel_fraction(torch, dr, ctx, s, host, dev, stream, steps: int):
@@ -368,7 +540,6 @@ def run_batched(torch, synth, dr, ctx, steps: int):
         items.append((g, img, out, tot))
         work += det.nx * det.ny * N
         alg += algorithmic_bytes(det.nx, det.ny, N, grid.n_bins)
-        sc.images = None
     torch.cuda.synchronize()
     b = dr.dr_batch_create(ctx, items, dr.DR_BATCH_AUTOTUNE | dr.DR_BATCH_GRAPH)
     tile = dr.dr_batch_tile(b)
@@ -392,25 +563,43 @@ def run_batched(torch, synth, dr, ctx, steps: int):
     ev1.record(stream)
     torch.cuda.synchronize()
     ms_seq = ev0.elapsed_time(ev1) / steps
+    # precision: the batch's own output (run once more), sampled per scan
+    dr.dr_batch_run(b, stream)
+    torch.cuda.synchronize()
+    errs, n_el = [], 0
+    for n, (sc, (img, out, tot)) in enumerate(zip(scans, keep)):
+        e, m = sampled_error(sc, out, sample_pixels(sc.detector.nx, sc.detector.ny, 2000, 40 + n))
+        errs.append(e)
+        n_el += m
+        sc.images = None
     dr.dr_batch_free(b)
     for g in geoms:
         dr.dr_geometry_free(g)
     del keep, items
     torch.cuda.empty_cache()
-    log(f"batched: {ms_batch:.3f} ms per batch, one call per scan {ms_seq:.3f} ms")
+    log(f"batched: {ms_batch:.3f} ms per batch, one call per scan {ms_seq:.3f} ms; "
+        f"FP32 error {max(errs):.2e} of sum|dI| on the sample")
     return {"workload": "16 scans: ROI side in {256,512,768,1024} px, steps U{101..801}, "
                         "bins U{201..801}, seed 4",
             "value": work / (ms_batch * 1e-3), "unit": UNIT, "ms_per_batch": ms_batch,
             "single_scan_calls_ms": ms_seq, "speedup_vs_single_scan_calls": ms_seq / ms_batch,
             "achieved_GBps": alg / (ms_batch * 1e-3) / 1e9,
             "frac_of_hbm_peak": alg / (ms_batch * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "launch_shape": list(tile), "graph_captured": True}
+            "launch_shape": list(tile), "graph_captured": True,
+            "precision": {"max_rel_elem": max(errs), "per_scan": errs, "elements": n_el,
+                          "sample": "2000 random pixels plus the corners of each scan, every "
+                                    "bin, from the batch's output"}}
 
 
 def run_served(torch, synth, dr, full_scan, full_host, seconds: float, rate: float):
     """Poisson arrivals of reconstruction requests (95% of the batched size mix,
     5% full 2048^2 x 1001 scans), host images in pinned memory, continuous
-    batching by the library's scheduler; latency = completion - arrival."""
+    batching by the library's scheduler; latency = completion - arrival.
+    Beside it, on the same GPU: each request alone through the plain
+    single-scan call (synchronous, from the same pinned memory), giving the
+    latency the same request sequence would see with no queueing and no
+    mixing, and the throughput of one call after another; and the scheduler
+    at saturation (every request offered at once)."""
     small = synth.config4(render_now=False)
     pool = []
     for sc in small:
@@ -433,64 +622,97 @@ def run_served(torch, synth, dr, full_scan, full_host, seconds: float, rate: flo
             for k, v in outs.items()}
     # the scheduler's device-memory budget is taken from what is free now
     sctx = dr.dr_ctx_create(0, 0)
-    geoms = [dr.dr_geometry_init(sctx, sc.detector, sc.wire, sc.grid) for sc, _ in pool]
-    gfull = dr.dr_geometry_init(sctx, full_scan.detector, full_scan.wire, full_scan.grid)
-    use = {k: 0 for k in outs}
-    busy = {}
-    torch.cuda.synchronize()
-    lat, done_t, work = {}, [], 0
-    pending = {}
-    t_start = time.perf_counter()
-    i = 0
-    while i < n_req or pending:
-        now = time.perf_counter() - t_start
-        while i < n_req and arrivals[i] <= now:
-            k = kinds[i]
-            slot = use[k] % 2
-            if (k, slot) in busy:  # both buffers of this entry in flight: next arrival waits
-                break
-            use[k] += 1
-            if k < 0:
-                g, img, px = gfull, full_host, 2048 * 2048 * full_scan.wire.n_steps
-            else:
-                sc, img = pool[k]
-                g, px = geoms[k], sc.detector.nx * sc.detector.ny * sc.wire.n_steps
-            t = dr.dr_submit(sctx, g, img, False, outs[k][slot], tots[k][slot])
-            pending[t] = (i, px, (k, slot))
-            busy[(k, slot)] = t
-            i += 1
-        for t in list(pending):
-            if dr.dr_poll(sctx, t) == dr.DR_OK:
-                idx, px, key = pending.pop(t)
-                fin = time.perf_counter() - t_start
-                lat[idx] = fin - arrivals[idx]
-                done_t.append(fin)
-                work += px
-                busy.pop(key, None)
-        time.sleep(0.0002)
-    makespan = max(done_t) - arrivals[0]
+    geoms = {k: dr.dr_geometry_init(sctx, sc.detector, sc.wire, sc.grid)
+             for k, (sc, _) in enumerate(pool)}
+    geoms[-1] = dr.dr_geometry_init(sctx, full_scan.detector, full_scan.wire, full_scan.grid)
+    imgs = {k: h for k, (_, h) in enumerate(pool)}
+    imgs[-1] = full_host
+    px_of = {k: sc.detector.nx * sc.detector.ny * sc.wire.n_steps for k, (sc, _) in enumerate(pool)}
+    px_of[-1] = 2048 * 2048 * full_scan.wire.n_steps
+
+    def serve(arr):
+        use = {k: 0 for k in outs}
+        busy, lat, done_t, pending = {}, {}, [], {}
+        work = 0
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        i = 0
+        while i < n_req or pending:
+            now = time.perf_counter() - t_start
+            while i < n_req and arr[i] <= now:
+                k = kinds[i]
+                slot = use[k] % 2
+                if (k, slot) in busy:  # both buffers of this entry in flight: next arrival waits
+                    break
+                use[k] += 1
+                t = dr.dr_submit(sctx, geoms[k], imgs[k], False, outs[k][slot], tots[k][slot])
+                pending[t] = (i, px_of[k], (k, slot))
+                busy[(k, slot)] = t
+                i += 1
+            for t in list(pending):
+                if dr.dr_poll(sctx, t) == dr.DR_OK:
+                    idx, px, key = pending.pop(t)
+                    fin = time.perf_counter() - t_start
+                    lat[idx] = fin - arr[idx]
+                    done_t.append(fin)
+                    work += px
+                    busy.pop(key, None)
+            time.sleep(0.0002)
+        makespan = max(done_t) - arr[0]
+        return np.array([lat[j] for j in range(n_req)]) * 1e3, makespan, work
+
+    lat_ms, makespan, work = serve(arrivals)
     stats = dr.dr_ctx_stats(sctx)
-    for g in geoms + [gfull]:
+    sat_ms, sat_makespan, sat_work = serve(np.zeros(n_req))
+    # each kind alone: the plain single-scan call from pinned host memory
+    alone_ms = {}
+    stream = torch.cuda.current_stream()
+    for k in outs:
+        ts = []
+        for _ in range(3 if k >= 0 else 2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            dr.dr_reconstruct(geoms[k], imgs[k], False, outs[k][0], tots[k][0], stream)
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+        alone_ms[k] = float(np.median(ts))
+    alone_lat = np.array([alone_ms[kinds[j]] for j in range(n_req)])
+    for g in geoms.values():
         dr.dr_geometry_free(g)
     dr.dr_ctx_destroy(sctx)
     del outs, tots
     torch.cuda.empty_cache()
-    lat_ms = np.array([lat[j] for j in range(n_req)]) * 1e3
     full_ms = [lat_ms[j] for j in range(n_req) if kinds[j] < 0]
     small_ms = [lat_ms[j] for j in range(n_req) if kinds[j] >= 0]
-    log(f"served {n_req} requests: p50 {np.percentile(lat_ms, 50):.1f} ms, "
-        f"p99 {np.percentile(lat_ms, 99):.1f} ms")
+    p = lambda a, q: float(np.percentile(a, q))
+    log(f"served {n_req} requests: p50 {p(lat_ms, 50):.1f} ms, p99 {p(lat_ms, 99):.1f} ms; "
+        f"alone p50 {p(alone_lat, 50):.1f} ms, p99 {p(alone_lat, 99):.1f} ms; saturated "
+        f"{sat_work / sat_makespan:.3e} vs one call after another "
+        f"{sat_work / (alone_lat.sum() * 1e-3):.3e} pixel-wire-steps/s")
     return {"workload": f"Poisson arrivals at {rate:g}/s for {seconds:g} s: 95% batched size mix, "
                         f"5% 2048x2048x1001 scans; host images in pinned memory",
-            "requests": n_req, "p50_ms": float(np.percentile(lat_ms, 50)),
-            "p99_ms": float(np.percentile(lat_ms, 99)), "mean_ms": float(lat_ms.mean()),
+            "requests": n_req, "p50_ms": p(lat_ms, 50), "p99_ms": p(lat_ms, 99),
+            "mean_ms": float(lat_ms.mean()),
             "full_scan_requests": len(full_ms),
-            "full_scan_p50_ms": float(np.percentile(full_ms, 50)) if full_ms else None,
+            "full_scan_p50_ms": p(full_ms, 50) if full_ms else None,
             "full_scan_max_ms": float(np.max(full_ms)) if full_ms else None,
-            "small_scan_p50_ms": float(np.percentile(small_ms, 50)) if small_ms else None,
-            "small_scan_p99_ms": float(np.percentile(small_ms, 99)) if small_ms else None,
+            "small_scan_p50_ms": p(small_ms, 50) if small_ms else None,
+            "small_scan_p99_ms": p(small_ms, 99) if small_ms else None,
             "value": work / makespan, "unit": UNIT, "epochs": int(stats["epochs"]),
-            "h2d_GB": stats["bytes_h2d"] / 1e9}
+            "h2d_GB": stats["bytes_h2d"] / 1e9,
+            "single_scan_alone": {
+                "note": "each request's kind run alone through dr_reconstruct from the same "
+                        "pinned host memory, synchronously (median of 2-3); latency of the "
+                        "same request sequence with no queueing",
+                "p50_ms": p(alone_lat, 50), "p99_ms": p(alone_lat, 99),
+                "full_scan_ms": alone_ms[-1],
+                "small_scan_p50_ms": p([alone_ms[kinds[j]] for j in range(n_req) if kinds[j] >= 0], 50)
+                if small_ms else None,
+                "value_one_after_another": sat_work / (alone_lat.sum() * 1e-3)},
+            "saturated": {"note": "the same requests all offered at time 0 (two output buffers "
+                                  "per kind bound what is in flight)",
+                          "value": sat_work / sat_makespan, "makespan_ms": sat_makespan * 1e3,
+                          "p50_ms": p(sat_ms, 50), "p99_ms": p(sat_ms, 99)}}
 
 
 def main():
@@ -508,6 +730,8 @@ def main():
     ap.add_argument("--no-files", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--no-small-configs", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--workload", default="config3", choices=["config2", "config3"])
@@ -547,6 +771,7 @@ def main():
     host = torch.empty((N, ny, nx), dtype=torch.int16, pin_memory=True)
     synth.render(s, out=host.numpy().view(np.uint16))
     log(f"rendered {host.numel() * 2 / 1e9:.2f} GB in {time.perf_counter() - t0:.1f} s")
+    s.images = host.numpy().view(np.uint16)
     dev = host.to("cuda", non_blocking=False)
     out = torch.empty((B, ny, nx), dtype=torch.float32, device="cuda")
     tot = torch.empty((B,), dtype=torch.float32, device="cuda")
@@ -589,6 +814,7 @@ def main():
     dr.dr_enable_timing(g, False)
     k_avg = float(np.mean(kms))
     alg = algorithmic_bytes(nx, ny, N, B)
+    alg_survey = 2 * nx * ny * N + 4 * nx * ny * B + 16 * nx * ny + 16 * N
     achieved = alg / (k_avg * 1e-3) / 1e9
     digest = kernel_source_digest()
     traffic = measured_traffic(digest, tile)
@@ -614,6 +840,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "rows_f32_kernel", "kernel_ms": k_avg,
                      "totals_ms": float(np.mean(tms)), "algorithmic_bytes": alg,
+                     "algorithmic_bytes_with_pixel_table": alg_survey,
                      "kernel_source_sha256_16": digest},
     }
     # reference for the byte mix: torch's int16 -> float32 conversion of the same
@@ -643,10 +870,18 @@ def main():
                 "kernel_over_reference": achieved / gbps["planes"],
                 "linear": {"op": "the same bytes in address order (16-byte accesses, grid-stride)",
                            "ms": probe["linear"], "GBps": gbps["linear"]},
+                "read_only": {"op": "the reconstruction-order kernel's reads alone (the stack)",
+                              "ms": probe["read"], "bytes": dev.numel() * 2},
+                "write_only": {"op": "its writes alone (the output planes)",
+                               "ms": probe["write"], "bytes": dev.numel() * 4},
+                "read_plus_write_ms": probe["read"] + probe["write"],
+                "kernel_over_read_plus_write": (probe["read"] + probe["write"]) / k_avg,
                 "torch_conversion": torch_ref}
             log(f"stream reference: {probe['planes']:.3f} ms, {gbps['planes']:.0f} GB/s "
                 f"(address order {gbps['linear']:.0f} GB/s); kernel at "
-                f"{achieved / gbps['planes']:.2f} of it")
+                f"{achieved / gbps['planes']:.2f} of it; read alone {probe['read']:.3f} ms, "
+                f"write alone {probe['write']:.3f} ms, kernel at "
+                f"{(probe['read'] + probe['write']) / k_avg:.2f} of their sum")
         else:
             result["roofline"]["stream_reference"] = dict(torch_ref, bytes=ref_bytes)
     if not args.no_e2e:
@@ -661,12 +896,28 @@ def main():
                                 "note": "pinned host images streamed in row slabs; PCIe-bound"}
         log(f"end-to-end (PCIe) {dt * 1e3:.1f} ms")
     dr.dr_geometry_free(g)
+    precision = {"bar": "|gpu - oracle| <= 1e-5 * sum_k |I_k - I_{k+1}| per pixel and bin; "
+                        "totals within 1e-5 of sum_p sum_k |I_k - I_{k+1}|",
+                 "metric": "max |gpu - oracle| / sum_k |I_k - I_{k+1}| over the elements "
+                           "compared (FP32 path against the FP64 oracle); totals: max over bins "
+                           "of |gpu - oracle| / sum_p sum_k |I_k - I_{k+1}|"}
+    scale_total = stack_scale(torch, dev)
+    tot_main = tot.double().cpu().numpy()
+    if not args.no_precision:
+        e, n = sampled_error(s, out, sample_pixels(nx, ny, 3000, 33))
+        precision[args.workload] = {"max_rel_elem": e, "elements": n,
+                                    "sample": "3000 random pixels plus the corners, every bin",
+                                    "max_rel_totals": None}
+        log(f"{args.workload}: FP32 error {e:.2e} of sum|dI| on the sample")
     if not args.no_sweep and args.workload == "config3":
         result["size_sweep"] = run_size_sweep(torch, synth, dr, ctx, s, host, dev, out, tot,
-                                              stream, max(2, args.steps // 2))
+                                              stream, max(2, args.steps // 2), 4 * args.cpu_seconds)
     if not args.no_per_pixel:
         result["per_pixel"] = run_per_pixel(torch, synth, dr, ctx, s, dev, out, tot, stream,
-                                            max(2, args.steps // 2))
+                                            max(2, args.steps // 2), not args.no_precision,
+                                            scale_total)
+        if "precision" in result["per_pixel"]:
+            precision["per_pixel"] = result["per_pixel"]["precision"]
     del out
     torch.cuda.empty_cache()
     if not args.no_fraction:
@@ -676,6 +927,7 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_batch and args.workload == "config3":
         result["batched"] = run_batched(torch, synth, dr, ctx, max(3, args.steps // 2))
+        precision["batched"] = result["batched"]["precision"]
     if not args.no_serve and args.workload == "config3":
         result["serving"] = run_served(torch, synth, dr, s, host, args.serve_seconds,
                                        args.serve_rate)
@@ -683,16 +935,25 @@ def main():
         res = run_h5_files(torch, synth, dr, ctx, stream)
         if res is not None:
             result["files"] = res
+    if not args.no_small_configs:
+        small = run_small_configs(torch, synth, dr, ctx, stream, max(5, args.steps))
+        result["small_configs"] = small
+        for k, v in small.items():
+            precision[k] = v["precision"]
     if not args.no_cpu_baseline:
         log("timing the oracle on a CPU sample")
-        s.images = host.numpy().view(np.uint16)
-        cb = cpu_baseline(s, args.cpu_seconds)
+        cb, tot_ref = cpu_baseline(s, args.cpu_seconds)
+        if tot_ref is not None and args.workload in precision:
+            precision[args.workload]["max_rel_totals"] = totals_error(tot_main, tot_ref,
+                                                                      scale_total)
         # the oracle's time for the whole scan over the GPU's, kernel alone and
         # end to end from pinned host memory
         cb["oracle_over_gpu_step"] = result["value"] / cb["value"]
         if "end_to_end" in result:
             cb["oracle_over_gpu_end_to_end"] = result["end_to_end"]["value"] / cb["value"]
         result["cpu_baseline"] = cb
+    if not args.no_precision:
+        result["precision"] = precision
     dr.dr_ctx_destroy(ctx)
     print(json.dumps(result), flush=True)
 

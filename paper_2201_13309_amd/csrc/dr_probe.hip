@@ -4,7 +4,8 @@
 // float written, non-temporal), so the benchmark can report the HBM rate plain
 // kernels with the same 1:2 read:write mix reach on the box it runs on: in
 // address order (16-byte accesses, grid-stride) and in the reconstruction's
-// order (tiles of pixels walking the step and bin planes).
+// order (tiles of pixels walking the step and bin planes); and the read and
+// the write half of the latter on their own.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -44,6 +45,36 @@ __global__ __launch_bounds__(256) void planes_kernel(const unsigned int* __restr
     }
 }
 
+// The two halves of that traffic on their own, same order and access width:
+// every plane of the input read (one sum per lane pair written at the end), and
+// every plane of the output written.
+__global__ __launch_bounds__(256) void planes_read_kernel(const unsigned int* __restrict__ in,
+                                                          f32x2* __restrict__ out, int64_t plane2,
+                                                          int planes)
+{
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= plane2) return;
+    unsigned int a = 0u, b = 0u;
+    for (int k = 0; k < planes; ++k) {
+        const unsigned int v = __builtin_nontemporal_load(in + (int64_t)k * plane2 + j);
+        a += v & 0xffffu;
+        b += v >> 16;
+    }
+    const f32x2 o = {(float)a, (float)b};
+    __builtin_nontemporal_store(o, out + j);
+}
+
+__global__ __launch_bounds__(256) void planes_write_kernel(f32x2* __restrict__ out, int64_t plane2,
+                                                           int planes)
+{
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= plane2) return;
+    for (int k = 0; k < planes; ++k) {
+        const f32x2 o = {(float)k, (float)j};
+        __builtin_nontemporal_store(o, out + (int64_t)k * plane2 + j);
+    }
+}
+
 }  // namespace
 
 // out[i] = (float)in[i] for i < n.  in: device uint16 [n], out: device float
@@ -73,5 +104,32 @@ extern "C" int dr_probe_planes(const void* in, void* out, int64_t plane, int pla
     const int64_t plane2 = plane / 2;
     hipLaunchKernelGGL(planes_kernel, dim3((unsigned)((plane2 + 255) / 256)), dim3(256), 0,
                        (hipStream_t)stream, (const unsigned int*)in, (f32x2*)out, plane2, planes);
+    return (int)hipGetLastError();
+}
+
+// The read half of dr_probe_planes: in[k][p] read for planes k < planes of
+// `plane` elements, out[p] = per-pixel sum (float, plane elements written).
+// The write half: out[k][p] written for every plane.  Same arguments,
+// alignment and return values as dr_probe_planes (write: in unused).
+extern "C" int dr_probe_planes_read(const void* in, void* out, int64_t plane, int planes,
+                                    void* stream)
+{
+    if (!in || !out || plane <= 0 || plane % 2 != 0 || planes <= 0 || ((uintptr_t)in & 7) ||
+        ((uintptr_t)out & 7))
+        return -1;
+    const int64_t plane2 = plane / 2;
+    hipLaunchKernelGGL(planes_read_kernel, dim3((unsigned)((plane2 + 255) / 256)), dim3(256), 0,
+                       (hipStream_t)stream, (const unsigned int*)in, (f32x2*)out, plane2, planes);
+    return (int)hipGetLastError();
+}
+
+extern "C" int dr_probe_planes_write(const void* in, void* out, int64_t plane, int planes,
+                                     void* stream)
+{
+    (void)in;
+    if (!out || plane <= 0 || plane % 2 != 0 || planes <= 0 || ((uintptr_t)out & 7)) return -1;
+    const int64_t plane2 = plane / 2;
+    hipLaunchKernelGGL(planes_write_kernel, dim3((unsigned)((plane2 + 255) / 256)), dim3(256), 0,
+                       (hipStream_t)stream, (f32x2*)out, plane2, planes);
     return (int)hipGetLastError();
 }

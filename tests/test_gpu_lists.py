@@ -123,6 +123,36 @@ def test_select_top_matches_rule(dr, ctx):
         dr.dr_geometry_free(g)
 
 
+def test_select_top_across_blocks(dr, ctx):
+    """A detector of 300 x 47 pixels: the selection's key blocks (4096 keys)
+    number three and a partial tail, so the scan carries between blocks, the
+    padded last block and tie runs that straddle block boundaries are all
+    exercised; k values cut tie runs in the middle of a block and at block
+    edges."""
+    s = synth.tiny(300, 47, 5, 9, seed=307, n_src=2)
+    npix = 300 * 47
+    g = dr.dr_geometry_init(ctx, s.detector, s.wire, s.grid)
+    try:
+        rng = np.random.default_rng(307)
+        two = rng.integers(0, 2, npix).astype(np.uint64)
+        steps = np.repeat(np.arange(7, dtype=np.uint64), npix // 7 + 1)[:npix][::-1].copy()
+        acts = [rng.integers(0, 4, npix).astype(np.uint64),       # heavy ties
+                np.full(npix, 9, dtype=np.uint64),                 # all equal
+                two,                                               # one long tie run per value
+                steps,                                             # runs ending inside blocks
+                rng.integers(0, 1 << 62, npix).astype(np.uint64)]
+        n_ones = int(two.sum())
+        ks = sorted({0, 1, 4095, 4096, 4097, 8191, 8192, 12288, npix - 1, npix,
+                     n_ones - 2500, n_ones - 1, n_ones, n_ones + 1, n_ones + 3000,
+                     npix // 7 * 3 + 5})
+        for a_i, act in enumerate(acts):
+            for k in ks:
+                got = _select(dr, g, act, k)
+                assert np.array_equal(got, oracle.select_top(act, k)), (a_i, k)
+    finally:
+        dr.dr_geometry_free(g)
+
+
 def _top_list(dr, g, s, frac):
     import torch
     npix = s.detector.nx * s.detector.ny
