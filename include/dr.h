@@ -348,7 +348,10 @@ dr_status dr_reconstruct_list_f64(dr_list list, const uint16_t* images_dev, int3
  * request whose images are resident, so requests that arrive while others
  * run join the next epoch.  Each pixel's result is bitwise the same as with
  * dr_reconstruct.  images: host (pinned) or device per images_on_device;
- * out/totals: device, as in dr_reconstruct.  The caller keeps every buffer
+ * out/totals: device, as in dr_reconstruct.  The request's device work is
+ * not ordered after any stream of the caller: work that writes images, out
+ * or totals (an initialising fill, the copy that produces the images) must
+ * have completed when dr_submit is called.  The caller keeps every buffer
  * valid until dr_poll reports DR_OK or an error for the ticket.
  * Requests on the per-pixel path or with step weights get launches of their
  * own kernel in each epoch.

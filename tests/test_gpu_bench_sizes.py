@@ -192,6 +192,9 @@ def test_serving_mix_with_full_frame(dr, ctx, full_frame):
         torch.cuda.synchronize()
         outs = [torch.full_like(o, float("nan")) for o, _ in alone]
         tots = [torch.full_like(t, float("nan")) for _, t in alone]
+        # the requests' work is not ordered after torch's stream: the fills
+        # above must be complete before submission
+        torch.cuda.synchronize()
         tickets = [dr.dr_submit(ctx, g, im, not h, o, t)
                    for g, im, h, o, t in zip(geoms, imgs, host_mask, outs, tots)]
         pending, t0 = set(tickets), time.time()
