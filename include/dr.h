@@ -222,6 +222,26 @@ dr_status dr_reconstruct(dr_geom geom, const uint16_t* images, int images_on_dev
 dr_status dr_reconstruct_f64(dr_geom geom, const uint16_t* images_dev, double* out,
                              double* totals, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * operation of dr_reconstruct on device-resident images, with its scratch
+ * (the per-wave partial totals and the totals workspace) taken from one fixed
+ * device array of 128 MiB that the library holds on each GPU it runs on until
+ * the process ends, instead of the geometry's scratch buffers that
+ * dr_reconstruct grows on demand.  No hipMalloc, hipFree or other allocating
+ * call is made; images_dev, out and totals are the caller's, as in
+ * dr_reconstruct (out [n_bins][ny][nx] FP32, totals [n_bins] FP32 or NULL;
+ * stream NULL = the HIP null stream; returns after enqueueing).  Every call on
+ * one GPU shares that GPU's array, so calls whose work overlaps in time on one
+ * GPU (other streams, other host threads) race and must be serialized by the
+ * caller; each call writes every scratch element it reads before reading it.
+ * Errors: DR_E_INVAL for NULL or misaligned pointers, and for a scan whose
+ * totals need more scratch than the array holds (the message gives both
+ * sizes; pass totals = NULL, which needs none, or use dr_reconstruct);
+ * DR_E_DEVICE for HIP failures. */
+dr_status dr_reconstruct_noalloc(dr_geom geom, const uint16_t* images_dev, float* out,
+                                 float* totals, void* stream);
+
 /* Positions of one wire edge (edge: DR_EDGE_LEADING or DR_EDGE_TRAILING),
  * computed by the device code the kernels use, for a host list of pixels
  * (flat indices j*nx + i): bins_out[n][n_steps] receives floor(u_k) as int32

@@ -27,6 +27,7 @@ DEVICE = ["-x", "hip", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "
 SOURCES = [("dr_tiles_rows.hip", True), ("dr_tiles_rows_add.hip", True),
            ("dr_tiles_batch.hip", True), ("dr_tiles_batch_add.hip", True),
            ("dr_kernels.hip", True), ("dr_pixels.hip", True), ("dr_select.hip", True),
+           ("dr_noalloc.hip", True),
            ("dr_runtime.cpp", False),
            ("dr_list.cpp", False), ("dr_serve.cpp", False), ("dr_sched.cpp", False)]
 

@@ -264,6 +264,10 @@ dr_status dr_ctx_create(int device, size_t hbm_budget_bytes, dr_ctx* out)
         DR_HIP(hipEventCreateWithFlags(&c->slab_ready[i], hipEventDisableTiming));
         DR_HIP(hipEventCreateWithFlags(&c->slab_free[i], hipEventDisableTiming));
     }
+    {
+        const dr_status st = noalloc_scratch_init(device);
+        if (st != DR_OK) return st;
+    }
     if (const char* f = std::getenv("DR_TUNE_CACHE")) c->tune_file = f;
     load_tune_file(c.get());
     *out = c.release();

@@ -161,6 +161,13 @@ size_t totals_work_bytes(const dr_geom g);
 dr_status reconstruct_device_into(dr_geom g, const TileCfg& t, const uint16_t* images, float* out,
                                   float* totals, float* part, double* work, hipStream_t s);
 
+// fixed device scratch of dr_reconstruct_noalloc (dr_noalloc.hip): its size,
+// the per-device address lookup (called with `device` current), and the bytes
+// a reconstruction with this launch shape takes from it
+constexpr size_t kNoAllocScratchBytes = (size_t)128 << 20;
+dr_status noalloc_scratch_init(int device);
+size_t noalloc_scratch_need(const dr_geom g, const TileCfg& t, bool totals);
+
 Scheduler* make_scheduler(dr_ctx ctx);
 void destroy_scheduler(Scheduler* s);
 

@@ -36,7 +36,7 @@ ABI_SYMBOLS = (
     "dr_last_timing", "dr_batch_create", "dr_batch_run", "dr_batch_tile", "dr_batch_free",
     "dr_submit", "dr_poll", "dr_wait", "dr_ctx_stats", "dr_last_error", "dr_pixel_activity",
     "dr_select_top", "dr_list_create", "dr_list_size", "dr_list_pixels", "dr_list_free",
-    "dr_reconstruct_list", "dr_reconstruct_list_f64",
+    "dr_reconstruct_list", "dr_reconstruct_list_f64", "dr_reconstruct_noalloc",
 )
 
 
@@ -108,6 +108,7 @@ def load(path: Optional[str] = None):
         "dr_autotune": [vp, vp, vp, P(dr_tile_config)],
         "dr_reconstruct": [vp, vp, ctypes.c_int, vp, vp, vp],
         "dr_reconstruct_f64": [vp, vp, vp, vp, vp],
+        "dr_reconstruct_noalloc": [vp, vp, vp, vp, vp],
         "dr_debug_plan": [vp, vp, i32, i32, vp, vp],
         "dr_enable_timing": [vp, ctypes.c_int],
         "dr_last_timing": [vp, P(ctypes.c_double), P(ctypes.c_double)],
@@ -277,6 +278,11 @@ def dr_reconstruct(geom: int, images, images_on_device: bool, out, totals=None, 
 def dr_reconstruct_f64(geom: int, images_dev, out, totals=None, stream=None):
     _check(load().dr_reconstruct_f64(geom, ptr(images_dev), ptr(out), ptr(totals),
                                      stream_handle(stream)))
+
+
+def dr_reconstruct_noalloc(geom: int, images_dev, out, totals=None, stream=None):
+    _check(load().dr_reconstruct_noalloc(geom, ptr(images_dev), ptr(out), ptr(totals),
+                                         stream_handle(stream)))
 
 
 def dr_debug_plan(geom: int, pixels, n_steps: int, want_bins: bool = True, want_u: bool = True,

@@ -38,6 +38,7 @@ def test_null_arguments_rejected_without_device(lib):
     assert lib.dr_reconstruct(None, None, 1, None, None, None) == dr.DR_E_INVAL
     assert "NULL" in dr.dr_last_error()
     assert lib.dr_reconstruct_f64(None, None, None, None, None) == dr.DR_E_INVAL
+    assert lib.dr_reconstruct_noalloc(None, None, None, None, None) == dr.DR_E_INVAL
     assert lib.dr_geometry_init(None, None, None, None, None) == dr.DR_E_INVAL
     assert lib.dr_geometry_free(None) == dr.DR_E_INVAL
     assert lib.dr_ctx_destroy(None) == dr.DR_E_INVAL
