@@ -209,11 +209,15 @@ __global__ __launch_bounds__(256) void validate_pixels_kernel(GeomArgs g, int si
         for (int k = 0; k < g.n_steps; ++k) {
             const double u = edge_position(g, py, pz, k, sr, f.c, e0, invw);
             if (!__builtin_isfinite(u)) bad |= 1;
+            else if (!(__builtin_fabs(u) < 0x1p30)) bad |= 4;
         }
     }
     for (int k = 0; k < g.n_steps; ++k) {
         const double cy = g.wire_yz[2 * k];
         if (!(cy > 0.0 && cy < py)) bad |= 2;
+        // the per-pixel kernels take the square root's Newton form unguarded
+        const double ay = cy - py, az = g.wire_yz[2 * k + 1] - pz;
+        if (!((az * az + ay * ay) - g.radius * g.radius >= 0x1p-767)) bad |= 1;
     }
     if (bad) atomicOr(status, bad);
 }

@@ -8,28 +8,49 @@
 // (Sec. III-C: each pixel's differences are added into depth arrays).
 //
 //   pixels_f32_kernel  FP32 accumulation.  ALU-bound: per (pixel, step) one
-//                      FP64 square root and one FP64 division; the interval's
-//                      plan is straight-line code and its fractions come from
-//                      one FP32 reciprocal; wire positions are staged in LDS.
+//                      FP64 square root and one FP64 division; a step inside
+//                      one bin costs an integer add, a step across a bin
+//                      boundary one FP32 reciprocal and one FP64 fma; wire
+//                      positions come through scalar loads; totals are summed
+//                      in a fixed order through per-wave LDS rings.
 //   pixels_kernel      FP64 instance (validation): each overlap divided by the
 //                      length in FP64, the oracle's order of accumulation.
+#include <type_traits>
+
 #include "dr_device.h"
 
 #pragma clang fp contract(off)
 
 namespace dr {
 
-// Edge position in bin units; TILT: the wire axis has a z component, so the
-// tangent point's xi is divided by c = e1.z; otherwise c is exactly 1 and the
-// division (t / 1 == t) is left out.
+// tangent_depth for the per-pixel kernels: the square root always in its
+// Newton form.  dr_geometry_init checks for these geometries that
+// L2 - r^2 >= 2^-767 at every pixel and wire step, where the Newton form and
+// the guarded one in tangent_depth give the same bits.
+__device__ __forceinline__ double tangent_depth_checked(double py, double pz, double cy,
+                                                       double cz, double r, double sr)
+{
+    const double ay = cy - py;
+    const double az = cz - pz;
+    const double L2 = az * az + ay * ay;
+    const double kk = sqrt_newton(L2 - r * r);
+    const double tz = az * kk - ay * sr;
+    const double ty = ay * kk + az * sr;
+    return cz - (cy * tz + sr * L2) / ty;
+}
+
+// Edge position in bin units times `sinvw` = (+-1) / width: the position u,
+// or -u for a walk that runs the other way (exact: a sign); TILT: the wire
+// axis has a z component, so the tangent point's xi is divided by c = e1.z;
+// otherwise c is exactly 1 and the division (t / 1 == t) is left out.
 template <bool TILT>
 __device__ __forceinline__ double position_at(double cy, double cz, double py, double pz,
                                               double r, double sr, double c, double e0,
-                                              double invw)
+                                              double sinvw)
 {
-    const double t = tangent_depth(py, pz, cy, cz, r, sr);
+    const double t = tangent_depth_checked(py, pz, cy, cz, r, sr);
     const double d = TILT ? t / c : t;
-    return (d - e0) * invw;
+    return (d - e0) * sinvw;
 }
 
 struct PlanF {
@@ -77,29 +98,92 @@ __device__ __forceinline__ PlanF plan_f32(double u0, double u1, double fl0, doub
     return e;
 }
 
-constexpr int kWireChunk = 512;  // wire positions staged in LDS at a time
-constexpr int kPixelTotalCopies = 4;  // copies of the LDS partial totals (FP32 kernel)
+constexpr int kPixelWaves = kPixelTile / 64;
+static_assert(kPixelWaves == 4, "the per-workgroup totals add four wave rows");
+
+// Totals of the FP32 kernel, summed in a fixed order.  Each wave owns a ring
+// of kRingBins bins x 64 lanes in LDS: the lane that closes bin p (counted in
+// its walk direction) writes its value into slot (p mod kRingBins, lane)
+// while p lies in the ring's window [F, F + kRingBins).  At the start of each
+// block of steps the bins below the wave's lowest open bin are complete; each
+// is summed over the 64 lanes in a fixed tree into the wave's own totals row,
+// and the window moves up.  At the end the workgroup adds its four rows in
+// wave order.  A close outside the window (a walk that turns back, lanes of
+// one wave far apart, lanes walking opposite ways) adds into the wave's row
+// with an LDS atomic instead.
+constexpr int kRingBins = 16;
+constexpr size_t kRingBytes = (size_t)kPixelWaves * kRingBins * 64 * sizeof(float);
+
+__host__ __device__ constexpr bool pixel_totals_in_lds(int B)
+{
+    return kRingBytes + (size_t)kPixelWaves * (size_t)B * sizeof(float) <= kPixelLdsBytes;
+}
+
+// v from the DPP source lane; lanes without one (or in rows outside ROW_MASK)
+// keep their own v
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int dpp_keep(int v)
+{
+    return __builtin_amdgcn_update_dpp(v, v, CTRL, ROW_MASK, 0xf, false);
+}
+
+// minimum over the 64 lanes of a wave, as a uniform value
+__device__ __forceinline__ int wave_min(int v)
+{
+    v = min(v, dpp_keep<0x111, 0xf>(v));  // row_shr:1
+    v = min(v, dpp_keep<0x112, 0xf>(v));  // row_shr:2
+    v = min(v, dpp_keep<0x114, 0xf>(v));  // row_shr:4
+    v = min(v, dpp_keep<0x118, 0xf>(v));  // row_shr:8
+    v = min(v, dpp_keep<0x142, 0xa>(v));  // row_bcast:15 into rows 1 and 3
+    v = min(v, dpp_keep<0x143, 0xc>(v));  // row_bcast:31 into rows 2 and 3
+    return __builtin_amdgcn_readlane(v, 63);
+}
 
 // FP32 per-pixel kernel: one lane per pixel of a row tile (or of a list tile,
-// as in the FP64 instance below).  Each lane walks its bins in the direction
-// its edge moves (direction frame p: p = b when the positions increase, else
-// p = B-1-b): bins below `nxt` are stored; when `open`, bin `nxt` is
-// accumulating in `acc` (and this pass's part of it in `tacc`, for the
-// totals).  A bin behind `nxt` that is visited again (a position sequence that
-// turns back) is read, added to and rewritten.  Untouched bins are stored as
-// zeros, except in the second pass of a two-edge reconstruction, which only
-// adds.  Partial totals are summed per workgroup in LDS when they fit, else in
-// the workgroup's own row of the partials buffer.
+// as in the FP64 instance below).  The lane's FP64 positions u_k (bin units,
+// the fixed operation order of the tangent construction) are turned into its
+// walk direction by v = sgn*u, with sgn = +1 when its positions rise over the
+// scan and -1 otherwise (negation is exact); bin p = floor(v) + off (off = 0,
+// or B for sgn = -1) counts bins in the order the walk meets them (p = b, or
+// B - 1 - b).  Bins below the open bin `nxt` are stored; bin nxt accumulates.
+//
+// Fast form: the step starts in the open bin and ends in it or in the next
+// one.  Let C(x) be the mass of
+// the intervals so far below x; a bin holds C(upper boundary) - C(lower
+// boundary).  In a walk of this kind every earlier interval lies below the
+// open bin's upper boundary bd, so C(bd) is the mass before the step (the sum
+// of the differences so far, kept exactly: an integer, or FP64 with step
+// weights) plus the step's part below bd, dI_k (bd - v_k) / (v_{k+1} - v_k).
+// A step that stays inside the open bin costs one integer add; one that
+// crosses bd costs one FP64 fma and stores the closed bin.  The values differ
+// from the per-step sums only by rounding: the fraction carries an FP32
+// reciprocal of the length (relative error 2^-23), each C one FP64 rounding,
+// the stored difference one FP32 rounding.
+//
+// General form, for any other step (entering or leaving the grid, more than
+// one boundary in a step, a walk that turns back): the interval's bins and
+// fractions (plan_f32) are visited one
+// by one, the open bin's value `acc` in FP32.  acc is taken from C as the mass
+// so far minus the mass below the open bin (`clast`), and given back the same
+// way; nothing lies above the open bin, so the two agree.  A bin behind nxt
+// that is visited again is read, added to and rewritten.
+//
+// Untouched bins are stored as zeros, except in the second pass of a
+// two-edge reconstruction (ADD), whose values are added onto the first
+// pass's.  Values are scaled (by +-1 or +-1/2, exactly) as they are stored.
 template <int PF, bool NORM, bool TILT, bool ADD>
 __global__ __launch_bounds__(kPixelTile) void pixels_f32_kernel(ScanArgs a, GeomArgs g, int side,
                                                                 float scale, ListArgs l)
 {
-    __shared__ double wyz[2 * kWireChunk];
+    using Cum = typename std::conditional<NORM, double, int>::type;
     extern __shared__ __align__(16) unsigned char dyn_lds[];
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
     const int N = a.n_steps, B = a.n_bins, nint = N - 1;
-    constexpr bool add_on = ADD;  // the second pass of two (compile-time: no output reads otherwise)
     const bool tot = a.partials != nullptr;
+    // wire positions: the same for every lane, read with scalar loads
+    typedef const __attribute__((address_space(4))) double cdouble;
+    const cdouble* const wire = (const cdouble*)g.wire_yz;
     bool act;
     int64_t pixel, slot;
     const uint16_t* ip;
@@ -119,24 +203,27 @@ __global__ __launch_bounds__(kPixelTile) void pixels_f32_kernel(ScanArgs a, Geom
         const int tile = (int)(blockIdx.x % (unsigned)a.tiles_per_row);
         const int col = tile * kPixelTile + tid;
         act = col < a.nx;
-        pixel = (int64_t)row * a.nx + (act ? col : 0);
-        ip = a.img + (int64_t)(row - a.row_base) * a.img_row + (act ? col : 0);
+        const int ccol = act ? col : a.nx - 1;  // lanes past the row's end follow its last pixel
+        pixel = (int64_t)row * a.nx + ccol;
+        ip = a.img + (int64_t)(row - a.row_base) * a.img_row + ccol;
         op = (float*)a.out + (int64_t)row * a.nx + col;
         slot = (int64_t)row * a.tiles_per_row + tile;
     }
-    // the workgroup's partial totals: in LDS, four copies (one per 16-lane
-    // row of a wave, so that the lanes of a wave adding to one bin meet at
-    // most 16 to an address), summed at the end; in place in the workgroup's
-    // row of the partials buffer when they do not fit
+    // totals: the rings and the four wave rows in LDS, or, for rows too long
+    // for LDS, device atomics into the workgroup's row of the partials buffer
     float* const gp = tot ? (float*)a.partials + slot * B : nullptr;
-    const bool in_lds = (size_t)B * kPixelTotalCopies * sizeof(float) <= kPixelLdsBytes;
-    float* const ltot = reinterpret_cast<float*>(dyn_lds);
-    const int lane = (int)(threadIdx.x & 63);
+    const bool in_lds = pixel_totals_in_lds(B);
+    float* const ring = reinterpret_cast<float*>(dyn_lds) + wave * (kRingBins * 64);
+    float* const trows = reinterpret_cast<float*>(dyn_lds + kRingBytes);
+    float* const wrow = trows + wave * B;
     if (tot) {
-        if (in_lds)
-            for (int b = tid; b < kPixelTotalCopies * B; b += kPixelTile) ltot[b] = 0.0f;
-        else
+        if (in_lds) {  // each wave clears its own ring and row
+            for (int i = lane; i < kRingBins * 64; i += 64) ring[i] = 0.0f;
+            for (int b = lane; b < B; b += 64) wrow[b] = 0.0f;
+        } else {
             for (int b = tid; b < B; b += kPixelTile) gp[b] = 0.0f;
+            __syncthreads();  // cleared before any wave adds
+        }
     }
 
     const Frame f = axis_frame(g);
@@ -152,206 +239,188 @@ __global__ __launch_bounds__(kPixelTile) void pixels_f32_kernel(ScanArgs a, Geom
     const double u_last = position_at<TILT>(g.wire_yz[2 * (N - 1)], g.wire_yz[2 * (N - 1) + 1],
                                             py, pz, r, sr, c, e0, invw);
     const int dir = (u_last >= u_first) ? 1 : -1;
-
+    const double sgn = (double)dir, sinvw = sgn * invw;
+    const int off = dir > 0 ? 0 : B;
+    // |u| < 2^30 and B <= 2^30 (checked when the geometry is built): exact in int
+    auto pbin = [&](double v) { return (int)__builtin_floor(v) + off; };
+    const bool up_w = __all(dir > 0), down_w = __all(dir < 0);  // wave-uniform
+    const bool uni = up_w || down_w;
+    const bool ring_on = tot && in_lds && uni;
     const int64_t plane = a.out_plane;
     const int64_t ostep = dir > 0 ? plane : -plane;
     auto nat = [&](int p) { return dir > 0 ? p : B - 1 - p; };
-    auto add_total = [&](int b, float v) {  // an LDS atomic when the row fits there
+
+    int F = 0;  // the ring's window [F, F + kRingBins) (wave-uniform)
+    auto atomic_total = [&](int b, float v) {  // b: natural bin
         if (in_lds)
-            __hip_atomic_fetch_add(&ltot[(lane >> 4) * B + b], v, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add(&wrow[b], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         else
             __hip_atomic_fetch_add(&gp[b], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     };
-    // v summed over the wave (every lane active) into bin b: in LDS, per
-    // 16-lane row by DPP, each row's last lane adding into its own copy
-    auto wave_sum_into = [&](int b, float v) {
-        if (in_lds) {
-            v += dpp_shift<0x111, 0xf>(v);  // row_shr:1
-            v += dpp_shift<0x112, 0xf>(v);  // row_shr:2
-            v += dpp_shift<0x114, 0xf>(v);  // row_shr:4
-            v += dpp_shift<0x118, 0xf>(v);  // row_shr:8
-            if ((lane & 15) == 15)
-                __hip_atomic_fetch_add(&ltot[(lane >> 4) * B + b], v, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP);
-        } else {
-            const float sum = wave_total(v);
-            if (lane == 0)
-                __hip_atomic_fetch_add(&gp[b], sum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+    auto put_total = [&](int p, float v) {  // this lane closed bin p with value v
+        if (!tot || !act) return;
+        if (ring_on && (unsigned)(p - F) < (unsigned)kRingBins)
+            ring[(p & (kRingBins - 1)) * 64 + lane] = v;
+        else
+            atomic_total(nat(p), v);
     };
-    int nxt = 0;                                        // first bin not stored
+    // bins [F, upto) are complete for every lane of the wave: sum their ring
+    // slots over the lanes (16 lanes per quarter in order, then the quarters
+    // pairwise) into the wave's row, clear them, and move the window
+    auto flush = [&](int upto) {
+        const int n = min(upto, F + kRingBins) - F;
+        if (n > 0) {
+            const int si = lane & (kRingBins - 1), q = lane >> 4;
+            float v = 0.0f;
+            if (si < n) {
+                f32x4* rs = reinterpret_cast<f32x4*>(
+                    ring + ((F + si) & (kRingBins - 1)) * 64 + 16 * q);
+                const f32x4 r0 = rs[0], r1 = rs[1], r2 = rs[2], r3 = rs[3];
+                v = (((r0.x + r0.y) + (r0.z + r0.w)) + ((r1.x + r1.y) + (r1.z + r1.w))) +
+                    (((r2.x + r2.y) + (r2.z + r2.w)) + ((r3.x + r3.y) + (r3.z + r3.w)));
+                const f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+                rs[0] = z;
+                rs[1] = z;
+                rs[2] = z;
+                rs[3] = z;
+            }
+            v += __shfl_xor(v, 16, 64);
+            v += __shfl_xor(v, 32, 64);
+            if (q == 0 && si < n) {
+                const int p = F + si;
+                wrow[up_w ? p : B - 1 - p] += v;
+            }
+        }
+        F = max(F, upto);
+    };
+    if (ring_on) {  // start the window just below the lowest first bin of the wave
+        const int p0 = min(max(pbin(sgn * u_first), 0), B);
+        F = max(0, wave_min(act ? p0 : B) - 1);
+    }
+
+    int nxt = 0;  // first bin (walk order) not stored
     int64_t woff = dir > 0 ? 0 : (int64_t)(B - 1) * plane;  // element offset of bin nxt
     bool open = false;
-    float acc = 0.0f, tacc = 0.0f;
-    auto close = [&]() {
-        if (open) {
-            if (act) {
-                stream_store(acc, op + woff);
-                if (tot) add_total(nat(nxt), tacc);
-            }
-            woff += ostep;
-            ++nxt;
-            open = false;
-        }
+    double clast = 0.0;  // when open: mass below the open bin (unscaled)
+    Cum cum = 0;         // mass of the steps so far (unscaled)
+    float prev = 0.0f;   // ADD: the first pass's value of the open bin
+    // store the open bin with this pass's value v (unscaled); move to the next
+    auto emit = [&](float v) {
+        v *= scale;
+        if (act) stream_store(ADD ? prev + v : v, op + woff);
+        put_total(nxt, v);
+        woff += ostep;
+        ++nxt;
     };
-    auto bin = [&](int p, float fr, float dI) {
-        if (open && p == nxt) {
-            acc = madd(fr, dI, acc);
-            tacc = madd(fr, dI, tacc);
-        } else if (p > nxt || (p == nxt && !open)) {
-            close();
-            for (; nxt < p; ++nxt, woff += ostep)
-                if (!add_on && act) stream_store(0.0f, op + woff);
-            acc = madd(fr, dI, (add_on && act) ? op[woff] : 0.0f);
-            tacc = madd(fr, dI, 0.0f);
-            open = true;
-        } else if (act) {  // stored already: read, add, rewrite
-            const int b = nat(p);
-            float* o = op + (int64_t)b * plane;
-            *o = madd(fr, dI, *o);
-            if (tot) add_total(b, fr * dI);
-        }
-    };
-
-    // Lanes with `on` add v to the total of bin b.  Called with every lane of
-    // the wave active: when all those lanes close the same bin (neighbouring
-    // pixels of a row usually do), their sum is formed with DPP and added by
-    // one lane, instead of one LDS atomic per lane on a single address.
-    auto wave_add_total = [&](bool on, int b, float v) {
-        const unsigned long long m = __ballot(on);
-        if (m == 0) return;
-        const int b0 = __builtin_amdgcn_readlane(b, __builtin_ctzll(m));
-        if (__ballot(on && b != b0) == 0)
-            wave_sum_into(b0, on ? v : 0.0f);
-        else if (on)
-            add_total(b, v);
-    };
-    // Lanes with `on` close the open bin nxt and open nxt + 1 (the common
-    // step of the walk); the bin closed and the partial total it carries are
-    // returned in cb and cv for wave_add_totals.
-    auto advance = [&](bool on, int& cb, float& cv) {
-        cb = nat(nxt);
-        cv = tacc;
-        if (on && act) stream_store(acc, op + woff);
-        if (on) {
-            woff += ostep;
-            ++nxt;
-            acc = 0.0f;
-            tacc = 0.0f;
-            if (add_on && act) acc = op[woff];
-        }
-    };
-    // The partial totals of the (at most two) bins each lane closed in one
-    // step: one wave sum when every closed bin is the same bin (a lane that
-    // closes two bins never is), else one wave_add_total per kind of close.
-    auto wave_add_totals = [&](bool ca, int ba, float va, bool cb, int bb, float vb) {
-        const unsigned long long m = __ballot(ca || cb);
-        if (m == 0) return;
-        const int b0 = __builtin_amdgcn_readlane(ca ? ba : bb, __builtin_ctzll(m));
-        if (__ballot((ca && ba != b0) || (cb && bb != b0)) == 0) {
-            wave_sum_into(b0, (ca ? va : 0.0f) + (cb ? vb : 0.0f));
-        } else {
-            wave_add_total(ca, ba, va);
-            wave_add_total(cb, bb, vb);
-        }
-    };
-
-    // a floor as an int, clamped to [-2, B + 1] (both ends lie outside the grid)
-    auto ifloor = [&](double fl) {
-        return (int)__builtin_fmin(__builtin_fmax(fl, -2.0), (double)(B + 1));
-    };
-    double u_prev = u_first, fl_prev = __builtin_floor(u_first);
-    int ifl_prev = ifloor(fl_prev);
-    auto step = [&](int kk, int k, int s0, int s1) {
-        const double u_next =
-            position_at<TILT>(wyz[2 * kk], wyz[2 * kk + 1], py, pz, r, sr, c, e0, invw);
-        const double fl_next = __builtin_floor(u_next);
-        const int ifl_next = ifloor(fl_next);
-        const float dI = sample_diff<float, NORM>(s0, s1, a.wk, k) * scale;
-        // Fast form, taken when every lane of the wave qualifies: the interval
-        // lies inside the grid, covers one or two bins, and starts in the open
-        // bin or the one after it.  Same bins, fractions and order of
-        // accumulation as the general form below.
-        const double lo = __builtin_fmin(u_prev, u_next), hi = __builtin_fmax(u_prev, u_next);
-        const double len = hi - lo;
-        const double fh = __builtin_fmax(fl_prev, fl_next);
-        const int f = min(ifl_prev, ifl_next);
-        // last bin: floor(hi), or the one below when hi is exactly that integer
-        const int l = max(ifl_prev, ifl_next) - ((hi == fh && len > 0.0) ? 1 : 0);
-        const bool two = l > f;
-        const int p1 = dir > 0 ? f : B - 1 - l;  // first bin visited (direction frame)
-        const bool fast =
-            open && f >= 0 && l <= B - 1 && l <= f + 1 && (unsigned)(p1 - nxt) <= 1u;
-        if (__all(fast)) {
-            float fr1 = 1.0f, fr2 = 0.0f;
-            if (two) {  // bins f and f + 1, split at bd
-                const double bd = (double)(f + 1);
-                const float rl = __builtin_amdgcn_rcpf((float)len);
-                const float lower = (float)(bd - lo) * rl, upper = (float)(hi - bd) * rl;
-                fr1 = dir > 0 ? lower : upper;
-                fr2 = dir > 0 ? upper : lower;
-            }
-            const bool one = p1 != nxt;
-            int ba, bb;
-            float va, vb;
-            advance(one, ba, va);
-            acc = madd(fr1, dI, acc);
-            tacc = madd(fr1, dI, tacc);
-            advance(two, bb, vb);
-            if (two) {
-                acc = madd(fr2, dI, acc);
-                tacc = madd(fr2, dI, tacc);
-            }
-            if (tot) wave_add_totals(one && act, ba, va, two && act, bb, vb);
-        } else {
-            const PlanF e = plan_f32(u_prev, u_next, fl_prev, fl_next, B);
-            if (e.nb > 0) {
-                const int bh = e.bl + e.nb - 1;
-                const int p0 = dir > 0 ? e.bl : B - 1 - bh;
-                bin(p0, dir > 0 ? e.f0 : e.f1, dI);
-                if (e.nb > 1) {
-                    for (int q = 1; q + 1 < e.nb; ++q) bin(p0 + q, e.fm, dI);
-                    bin(p0 + e.nb - 1, dir > 0 ? e.f1 : e.f0, dI);
+    // general form of one step over [u_prev, u_next]; returns the open bin's value
+    auto general = [&](double u_prev, double u_next, float dI) {
+        float acc = open ? (float)((double)cum - clast) : 0.0f;
+        auto bin = [&](int p, float fr) {
+            if (open && p == nxt) {
+                acc = madd(fr, dI, acc);
+            } else if (p > nxt || (p == nxt && !open)) {
+                if (open) {
+                    emit(acc);
+                    open = false;
                 }
+                for (; nxt < p; ++nxt, woff += ostep)
+                    if (!ADD && act) stream_store(0.0f, op + woff);
+                if (ADD && act) prev = op[woff];
+                acc = fr * dI;
+                open = true;
+            } else if (act) {  // stored already: read, add, rewrite
+                const int b = nat(p);
+                float* o = op + (int64_t)b * plane;
+                const float v = (fr * dI) * scale;
+                *o = *o + v;
+                if (tot) atomic_total(b, v);
+            }
+        };
+        const PlanF e =
+            plan_f32(u_prev, u_next, __builtin_floor(u_prev), __builtin_floor(u_next), B);
+        if (e.nb > 0) {
+            const int bh = e.bl + e.nb - 1;
+            const int p0 = dir > 0 ? e.bl : B - 1 - bh;
+            bin(p0, dir > 0 ? e.f0 : e.f1);
+            if (e.nb > 1) {
+                for (int q = 1; q + 1 < e.nb; ++q) bin(p0 + q, e.fm);
+                bin(p0 + e.nb - 1, dir > 0 ? e.f1 : e.f0);
             }
         }
-        u_prev = u_next;
-        fl_prev = fl_next;
-        ifl_prev = ifl_next;
+        return acc;
     };
 
-    // ring of U samples: slot k % U holds step k; wire chunks are whole rings
-    constexpr int U = PF + 1;
-    constexpr int KCU = (kWireChunk / U) * U;
-    unsigned short ring[U];
-#pragma unroll
-    for (int d = 0; d < U; ++d) ring[d] = stream_load(ip + (int64_t)min(d, N - 1) * a.img_step);
-    for (int kc = 0; kc < nint; kc += KCU) {
-        const int nk = min(KCU, nint - kc);
-        __syncthreads();
-        for (int e = tid; e < 2 * nk; e += kPixelTile) wyz[e] = g.wire_yz[2 * (kc + 1) + e];
-        __syncthreads();
-        int kk = 0;
-        for (; kk + U <= nk; kk += U) {
-#pragma unroll
-            for (int d = 0; d < U; ++d) {
-                step(kk + d, kc + kk + d, (int)ring[d], (int)ring[(d + 1) % U]);
-                ring[d] = stream_load(ip + (int64_t)min(kc + kk + d + U, N - 1) * a.img_step);
+    double v_prev = sgn * u_first;
+    int p_prev = pbin(v_prev);
+    // the wire position of the coming step, loaded one step ahead
+    double wy = wire[2 * min(1, N - 1)], wz = wire[2 * min(1, N - 1) + 1];
+    auto step = [&](int k, int s0, int s1) {
+        const double cy = wy, cz = wz;
+        const int kn = min(k + 2, N - 1);
+        wy = wire[2 * kn];
+        wz = wire[2 * kn + 1];
+        const double v_next = position_at<TILT>(cy, cz, py, pz, r, sr, c, e0, sinvw);
+        const int p_next = pbin(v_next);
+        Cum dI;  // this step's intensity difference (unscaled)
+        if constexpr (NORM)
+            dI = (double)s0 * a.wk[k] - (double)s1 * a.wk[k + 1];
+        else
+            dI = s0 - s1;
+        const int d = p_next - nxt;
+        // chosen per lane from its own walk alone, so that a pixel's values do
+        // not depend on the pixels it shares a wave with (a zero-length step
+        // of a falling walk is a point mass, whose bin follows the floor of u,
+        // not of v: general form)
+        const bool fast = open && p_prev == nxt && (unsigned)d <= 1u && p_next <= B - 1 &&
+                          (dir > 0 || v_next != v_prev);
+        if (fast) {
+            if (d != 0) {  // the step crosses the open bin's upper boundary bd
+                const double bd = (double)(p_next - off);
+                const double rl = (double)__builtin_amdgcn_rcpf((float)(v_next - v_prev));
+                const double cb = __builtin_fma((bd - v_prev) * rl, (double)dI, (double)cum);
+                emit((float)(cb - clast));
+                if (ADD && act) prev = op[woff];
+                clast = cb;
             }
+        } else {
+            const float acc = general(sgn * v_prev, sgn * v_next, (float)dI);
+            if (open) clast = ((double)cum + (double)dI) - (double)acc;
         }
+        cum += dI;
+        v_prev = v_next;
+        p_prev = p_next;
+    };
+
+    // ring of U samples: slot k % U holds step k; blocks of U steps
+    constexpr int U = PF + 1;
+    unsigned short smp[U];
 #pragma unroll
-        for (int d = 0; d < U; ++d)
-            if (kk + d < nk) step(kk + d, kc + kk + d, (int)ring[d], (int)ring[(d + 1) % U]);
+    for (int dd = 0; dd < U; ++dd) smp[dd] = stream_load(ip + (int64_t)min(dd, N - 1) * a.img_step);
+    int k0 = 0;
+    for (; k0 + U <= nint; k0 += U) {
+        if (ring_on) flush(wave_min(act ? nxt : B));
+#pragma unroll
+        for (int dd = 0; dd < U; ++dd) {
+            step(k0 + dd, (int)smp[dd], (int)smp[(dd + 1) % U]);
+            smp[dd] = stream_load(ip + (int64_t)min(k0 + dd + U, N - 1) * a.img_step);
+        }
     }
-    close();
-    if (!add_on)
+    if (ring_on) flush(wave_min(act ? nxt : B));
+#pragma unroll
+    for (int dd = 0; dd < U; ++dd)
+        if (k0 + dd < nint) step(k0 + dd, (int)smp[dd], (int)smp[(dd + 1) % U]);
+    if (open) {
+        emit((float)((double)cum - clast));
+        open = false;
+    }
+    if (!ADD)
         for (; nxt < B; ++nxt, woff += ostep)
             if (act) stream_store(0.0f, op + woff);
     if (tot && in_lds) {
+        if (ring_on) flush(B);
         __syncthreads();
         for (int b = tid; b < B; b += kPixelTile)
-            gp[b] = (ltot[b] + ltot[B + b]) + (ltot[2 * B + b] + ltot[3 * B + b]);
+            gp[b] = ((trows[b] + trows[B + b]) + trows[2 * B + b]) + trows[3 * B + b];
     }
 }
 
@@ -509,8 +578,16 @@ static hipError_t launch_pixels(const ScanArgs& a, const GeomArgs& g, int side, 
 {
     const int64_t groups = l ? n_tiles : (int64_t)(a.row_end - a.row_begin) * a.tiles_per_row;
     if (groups <= 0) return hipSuccess;
-    const size_t need = (size_t)a.n_bins * sizeof(Acc) * (sizeof(Acc) == 4 ? kPixelTotalCopies : 1);
-    const size_t lds = (a.partials && need <= kPixelLdsBytes) ? need : 0;
+    size_t lds = 0;
+    if (a.partials) {
+        if (sizeof(Acc) == 4)
+            lds = pixel_totals_in_lds(a.n_bins)
+                      ? kRingBytes + (size_t)kPixelWaves * a.n_bins * sizeof(float)
+                      : 0;
+        else
+            lds = (size_t)a.n_bins * sizeof(Acc) <= kPixelLdsBytes ? (size_t)a.n_bins * sizeof(Acc)
+                                                                    : 0;
+    }
     const ListArgs none{};
     const ListArgs& la = l ? *l : none;
     const dim3 grid((unsigned)groups), block(kPixelTile);

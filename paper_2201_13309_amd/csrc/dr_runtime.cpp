@@ -306,6 +306,7 @@ dr_status dr_geometry_init(dr_ctx c, const dr_detector* det, const dr_wire* wire
     if (wire->n_steps < 2 || !wire->centers)
         return set_error(DR_E_INVAL, "wire needs n_steps >= 2 and centers");
     if (grid->n_bins < 1) return set_error(DR_E_INVAL, "depth grid needs n_bins >= 1");
+    if (grid->n_bins > (1 << 30)) return set_error(DR_E_INVAL, "depth grid needs n_bins <= 2^30");
     if (!(wire->radius > 0.0) || !std::isfinite(wire->radius))
         return set_error(DR_E_INVAL, "wire radius must be > 0");
     if (!(grid->width > 0.0) || !std::isfinite(grid->width) || !std::isfinite(grid->first_center))
@@ -420,6 +421,9 @@ dr_status dr_geometry_init(dr_ctx c, const dr_detector* det, const dr_wire* wire
         if (status & 2)
             return set_error(DR_E_INVAL,
                              "wire not strictly between the beam and the detector in y");
+        if (status & 4)
+            return set_error(DR_E_INVAL, "an edge position lies 2^30 bins or more from the "
+                                         "grid's first bin (depth grid too fine for the sweep)");
         for (int i = 0; i < 3; ++i) DR_HIP(hipEventCreate(&g->ev[i]));
         c->live_geoms++;
         *out = g.release();

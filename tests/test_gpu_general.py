@@ -99,6 +99,40 @@ def make_case(name):
         c = s.wire.centers
         idx = np.sort(np.concatenate([np.arange(c.shape[0]), [0, 5, 5, 11, c.shape[0] - 1]]))
         s.wire = synth.Wire(s.wire.radius, np.ascontiguousarray(c[idx]))
+    elif name == "tilted_decreasing_repeated":  # backwards, with zero-length steps
+        s = synth.tiny(128, 3, 33, 101, seed=212, n_src=8, dark=100.0, render_now=False)
+        _tilted_detector(s, [200.0, 0.0, -30.0])
+        c = s.wire.centers[::-1]
+        idx = np.sort(np.concatenate([np.arange(c.shape[0]), [0, 3, 3, 17, c.shape[0] - 1]]))
+        s.wire = synth.Wire(s.wire.radius, np.ascontiguousarray(c[idx]))
+    elif name == "pixel_table_mixed_directions":  # neighbouring shadows move opposite ways
+        # a pixel more than the detector distance downstream of the wire sees
+        # the wire's leading edge sweep the beam backwards: every other column
+        # sits 700 mm downstream, so every wave holds lanes walking both ways
+        s = synth.tiny(96, 3, 31, 181, seed=213, n_src=8, dark=100.0, render_now=False)
+        x, y, z = s.detector.pixel_xyz_arrays()
+        z = z + np.where(np.arange(96)[None, :] % 2 == 1, 700000.0, 0.0)
+        d = s.detector
+        s.detector = synth.Detector(d.nx, d.ny, d.origin, d.u, d.v,
+                                    pixel_xyz=np.stack([x, y, z], -1))
+        s.grid = synth.DepthGrid(181, -540.0 + 1.5, 3.0)
+        s.name = name
+        # the far pixels see no source occluded; counts drawn at random give
+        # every pixel intensity differences to spread
+        rng = np.random.default_rng(213)
+        s.images = rng.integers(0, 4000, (31, 3, 96)).astype(np.uint16)
+        return s
+    elif name == "pixel_table_spread":  # one direction, shadows of a wave tens of bins apart
+        s = synth.tiny(80, 3, 29, 121, seed=214, n_src=8, dark=100.0, render_now=False)
+        x, y, z = s.detector.pixel_xyz_arrays()
+        z = z + np.linspace(-100000.0, 100000.0, 80)[None, :]
+        d = s.detector
+        s.detector = synth.Detector(d.nx, d.ny, d.origin, d.u, d.v,
+                                    pixel_xyz=np.stack([x, y, z], -1))
+        s.grid = synth.DepthGrid(121, -100.0 + 0.5, 1.0)
+        s.name = name
+        synth.render(s)
+        return s
     elif name == "tilted_partial_grid":  # grid narrower than the sweeps: both ends leave it
         s = synth.tiny(100, 3, 31, 25, seed=211, n_src=6, dark=100.0, render_now=False)
         _tilted_detector(s, [200.0, -6.0, 22.0])
@@ -121,7 +155,8 @@ def make_case(name):
 
 CASES = ["tilted_detector", "axis_xz", "axis_xy", "axis_oblique", "pixel_table_jitter",
          "tilted_non_monotone", "tilted_coarse", "tilted_decreasing", "tilted_many_bins",
-         "tilted_repeated_steps", "tilted_partial_grid",
+         "tilted_repeated_steps", "tilted_partial_grid", "tilted_decreasing_repeated",
+         "pixel_table_mixed_directions", "pixel_table_spread",
          "trailing_tilted_detector",
          "trailing_axis_xz", "both_axis_xy", "both_tilted_non_monotone", "both_axis_oblique"]
 
@@ -221,3 +256,14 @@ def test_per_pixel_entry_points(dr, ctx):
         torch.cuda.synchronize()
     finally:
         dr.dr_geometry_free(g)
+
+
+def test_grid_too_fine_for_the_sweep_refused(dr, ctx):
+    """Per-pixel positions are bin indices in int32 arithmetic: a grid so fine
+    that an edge position lies 2^30 bins or more from its first bin is refused
+    when the geometry is built."""
+    s = make_case("tilted_detector")
+    fine = synth.DepthGrid(101, -5.0e-7, 1.0e-8)  # edge positions up to ~1.7e9 bins of 0.01 pm
+    with pytest.raises(dr.DRError) as e:
+        dr.dr_geometry_init(ctx, s.detector, s.wire, fine)
+    assert e.value.code == dr.DR_E_INVAL and "2^30" in str(e.value)
