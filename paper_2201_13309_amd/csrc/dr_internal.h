@@ -102,6 +102,18 @@ struct TileCfg {
     int ppl, waves, prefetch;
 };
 
+// Totals of one scan of a batch: partial rows [slots][n_bins] summed into
+// totals[n_bins] through the workspace work[kTotalsWorkRows][n_bins].
+struct TotalsJob {
+    const float* parts;
+    int64_t slots;  // partial rows of all passes
+    int32_t n_bins;
+    int32_t first1; // first block of this job in the stage-1 grid (64 bins per block)
+    int32_t first2; // first block of this job in the stage-2 grid (256 bins per block)
+    double* work;
+    float* totals;
+};
+
 // Launch wrappers (dr_kernels.hip).  All return the launch status.
 bool tile_supported(const TileCfg& t);
 int tile_width(const TileCfg& t);
@@ -134,6 +146,15 @@ hipError_t launch_totals_f32(const float* partials, int64_t slots, int n_bins, d
                              int work_rows, float* totals, hipStream_t s);
 hipError_t launch_totals_f64(const double* partials, int64_t slots, int n_bins, double* work,
                              int work_rows, double* totals, hipStream_t s);
+// the totals of n jobs of one batch in two launches (the same sums, in the
+// same order, as launch_totals_f32 per job); blocks1 / blocks2: the jobs'
+// stage-1 / stage-2 block counts summed
+hipError_t launch_totals_multi_f32(const TotalsJob* jobs, int n, int blocks1, int blocks2,
+                                   hipStream_t s);
+// totals[b] = sum over p of out[b][p] (out FP64 [n_bins][P]) in a fixed order;
+// work: work_rows * n_bins doubles
+hipError_t launch_plane_totals_f64(const double* out, int64_t P, int n_bins, double* work,
+                                  int work_rows, double* totals, hipStream_t s);
 hipError_t launch_debug_plan(const GeomArgs& g, const int64_t* pixels, int n, int side,
                              int32_t* bins, double* upos, hipStream_t s);
 // scans with per-step sample weights: launch shape (1, 4, 16) only

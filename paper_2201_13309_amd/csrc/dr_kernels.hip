@@ -126,6 +126,63 @@ __global__ __launch_bounds__(256) void totals_stage1(const T* part, int64_t slot
         work[(int64_t)blockIdx.y * B + b] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
 }
 
+// Totals of many scans at once: each block finds its job (jobs are few and
+// ordered by first block) and runs the single-scan stage on it.
+__device__ __forceinline__ int find_job(const TotalsJob* jobs, int n, int block, bool second)
+{
+    int j = 0;
+    while (j + 1 < n && (second ? jobs[j + 1].first2 : jobs[j + 1].first1) <= block) ++j;
+    return j;
+}
+
+__global__ __launch_bounds__(256) void totals_multi_stage1(const TotalsJob* jobs, int n)
+{
+    __shared__ double red[4][64];
+    const TotalsJob& jb = jobs[find_job(jobs, n, (int)blockIdx.x, false)];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int b = ((int)blockIdx.x - jb.first1) * 64 + lane;
+    const int B = jb.n_bins;
+    double s = 0.0;
+    if (b < B)
+        for (int64_t sl = (int64_t)blockIdx.y * 4 + w; sl < jb.slots; sl += (int64_t)gridDim.y * 4)
+            s += (double)jb.parts[sl * B + b];
+    red[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && b < B)
+        jb.work[(int64_t)blockIdx.y * B + b] =
+            ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+}
+
+__global__ __launch_bounds__(256) void totals_multi_stage2(const TotalsJob* jobs, int n, int rows)
+{
+    const TotalsJob& jb = jobs[find_job(jobs, n, (int)blockIdx.x, true)];
+    const int b = ((int)blockIdx.x - jb.first2) * 256 + threadIdx.x;
+    if (b >= jb.n_bins) return;
+    double s = 0.0;
+    for (int r = 0; r < rows; ++r) s += jb.work[(int64_t)r * jb.n_bins + b];
+    jb.totals[b] = (float)s;
+}
+
+// Column sums of an FP64 output [B][P] in a fixed order: block (b, chunk)
+// sums its chunk of plane b (256 strided partial sums, then a tree) into
+// work[chunk][b]; totals_stage2 adds the chunks in order.
+__global__ __launch_bounds__(256) void plane_sums_f64(const double* out, int64_t P, int B,
+                                                     double* work)
+{
+    __shared__ double red[256];
+    const int b = (int)blockIdx.x, ch = (int)blockIdx.y, nch = (int)gridDim.y;
+    const int64_t p0 = P * ch / nch, p1 = P * (ch + 1) / nch;
+    const double* plane = out + (int64_t)b * P;
+    double s = 0.0;
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += 256) s += plane[p];
+    red[threadIdx.x] = s;
+    for (int h = 128; h > 0; h >>= 1) {
+        __syncthreads();
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    }
+    if (threadIdx.x == 0) work[(int64_t)ch * B + b] = red[0];
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void totals_stage2(const double* work, int rows, int B, T* tot)
 {
@@ -332,6 +389,33 @@ hipError_t launch_totals_f64(const double* partials, int64_t slots, int n_bins, 
                              int work_rows, double* totals, hipStream_t s)
 {
     return launch_totals<double>(partials, slots, n_bins, work, work_rows, totals, s);
+}
+
+hipError_t launch_totals_multi_f32(const TotalsJob* jobs, int n, int blocks1, int blocks2,
+                                   hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(totals_multi_stage1, dim3((unsigned)blocks1, (unsigned)kTotalsWorkRows),
+                       dim3(256), 0, s, jobs, n);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(totals_multi_stage2, dim3((unsigned)blocks2), dim3(256), 0, s, jobs, n,
+                       kTotalsWorkRows);
+    return hipGetLastError();
+}
+
+hipError_t launch_plane_totals_f64(const double* out, int64_t P, int n_bins, double* work,
+                                  int work_rows, double* totals, hipStream_t s)
+{
+    if (P <= 0 || n_bins <= 0) return hipSuccess;
+    const int chunks = (int)std::max<int64_t>(1, std::min<int64_t>(work_rows, P / 65536));
+    hipLaunchKernelGGL(plane_sums_f64, dim3((unsigned)n_bins, (unsigned)chunks), dim3(256), 0, s,
+                       out, P, n_bins, work);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(totals_stage2<double>, dim3((unsigned)((n_bins + 255) / 256)), dim3(256),
+                       0, s, (const double*)work, chunks, n_bins, totals);
+    return hipGetLastError();
 }
 
 hipError_t launch_project_wire(const GeomArgs& g, double* wire_yz, int* d_status, hipStream_t s)

@@ -393,11 +393,16 @@ dr_status dr_reconstruct_list_f64(dr_list l, const uint16_t* images_dev, int32_t
     double* part = nullptr;
     const int32_t compact = layout == DR_LAYOUT_LIST;
     const int64_t slots = list_slots(l), groups = list_groups(l);
+    // totals: per-tile partial rows on the row path; on the per-pixel path the
+    // column sums of the finished output, in a fixed order
     if (totals) {
         std::lock_guard<std::mutex> lk(l->mu);
-        DR_HIP(l->part64.reserve(std::max<size_t>(8, (size_t)g->passes * slots * g->n_bins * 8)));
+        if (g->row_mode) {
+            DR_HIP(l->part64.reserve(
+                std::max<size_t>(8, (size_t)g->passes * slots * g->n_bins * 8)));
+            part = l->part64.as<double>();
+        }
         DR_HIP(l->work.reserve((size_t)kTotalsWorkRows * g->n_bins * sizeof(double)));
-        part = l->part64.as<double>();
     }
     const int64_t step = compact ? l->n : (int64_t)g->nx * g->ny;
     const ListArgs la = list_args(l, compact);
@@ -423,9 +428,12 @@ dr_status dr_reconstruct_list_f64(dr_list l, const uint16_t* images_dev, int32_t
     if (totals) {
         if (groups == 0) {
             DR_HIP(hipMemsetAsync(totals, 0, (size_t)g->n_bins * sizeof(double), s));
-        } else {
+        } else if (g->row_mode) {
             DR_HIP(launch_totals_f64(part, slots * g->passes, g->n_bins, l->work.as<double>(),
                                      kTotalsWorkRows, totals, s));
+        } else {
+            DR_HIP(launch_plane_totals_f64(out, l->n, g->n_bins, l->work.as<double>(),
+                                           kTotalsWorkRows, totals, s));
         }
     }
     set_error(DR_OK, "");

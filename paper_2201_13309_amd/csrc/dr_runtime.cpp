@@ -646,13 +646,17 @@ dr_status dr_reconstruct_f64(dr_geom g, const uint16_t* images, double* out, dou
     DR_HIP(hipSetDevice(g->ctx->device));
     hipStream_t s = (hipStream_t)stream;  // NULL is the null stream
     const TileCfg t{1, 4, 4};
+    // totals: per-wave partial rows on the row path; on the per-pixel path
+    // the column sums of the finished output, in a fixed order
     double* part = nullptr;
     if (totals) {
         std::lock_guard<std::mutex> lk(g->mu);
-        DR_HIP(g->part64.reserve((size_t)g->passes * partial_slots(g, t) * g->n_bins *
-                                 sizeof(double)));
+        if (g->row_mode) {
+            DR_HIP(g->part64.reserve((size_t)g->passes * partial_slots(g, t) * g->n_bins *
+                                     sizeof(double)));
+            part = g->part64.as<double>();
+        }
         DR_HIP(g->work.reserve((size_t)kTotalsWorkRows * g->n_bins * sizeof(double)));
-        part = g->part64.as<double>();
     }
     const int64_t slots = partial_slots(g, t);
     // two edges: each pass is a reconstruction of its own (halved fractions),
@@ -678,9 +682,12 @@ dr_status dr_reconstruct_f64(dr_geom g, const uint16_t* images, double* out, dou
         if (e == hipSuccess) e = ef;
     }
     DR_HIP(e);
-    if (totals)
+    if (totals && g->row_mode)
         DR_HIP(launch_totals_f64(part, slots * g->passes, g->n_bins, g->work.as<double>(),
                                  kTotalsWorkRows, totals, s));
+    else if (totals)
+        DR_HIP(launch_plane_totals_f64(out, (int64_t)g->nx * g->ny, g->n_bins,
+                                       g->work.as<double>(), kTotalsWorkRows, totals, s));
     return ok();
 }
 
@@ -874,6 +881,32 @@ static dr_status batch_build_args(dr_batch b, const TileCfg& t, int gpc)
                                                    (int64_t)g->nx * g->ny, 0, 0, g->ny,
                                                    b->items[i].out, part)});
     }
+    // the totals of every scan in two launches after the scans
+    std::vector<TotalsJob> jobs;
+    int blocks1 = 0, blocks2 = 0;
+    for (int i = 0; i < n; ++i) {
+        if (!b->items[i].totals) continue;
+        const dr_geom g = b->geoms[i];
+        TotalsJob j{};
+        j.parts = b->parts.as<float>() + b->part_off[i];
+        j.slots = b->slots[i] * g->passes;
+        j.n_bins = g->n_bins;
+        j.first1 = blocks1;
+        j.first2 = blocks2;
+        j.work = b->work.as<double>() + (size_t)i * kTotalsWorkRows * b->max_bins;
+        j.totals = b->items[i].totals;
+        blocks1 += (g->n_bins + 63) / 64;
+        blocks2 += (g->n_bins + 255) / 256;
+        jobs.push_back(j);
+    }
+    b->n_jobs = (int)jobs.size();
+    b->jblocks1 = blocks1;
+    b->jblocks2 = blocks2;
+    if (!jobs.empty()) {
+        DR_HIP(b->tjobs.reserve(sizeof(TotalsJob) * jobs.size()));
+        DR_HIP(hipMemcpy(b->tjobs.p, jobs.data(), sizeof(TotalsJob) * jobs.size(),
+                         hipMemcpyHostToDevice));
+    }
     std::vector<int64_t> starts(start1);
     starts.insert(starts.end(), start2.begin(), start2.end());
     DR_HIP(b->scans.reserve(sizeof(ScanArgs) * args.size()));
@@ -917,13 +950,8 @@ static dr_status batch_enqueue(dr_batch b, hipStream_t s)
         const dr_geom g = b->geoms[so.item];
         DR_HIP(launch_scan_f32(g, solo_tile(g), so.pass, so.args, s));
     }
-    for (size_t i = 0; i < b->items.size(); ++i) {
-        if (!b->items[i].totals) continue;
-        const dr_geom g = b->geoms[i];
-        double* work = b->work.as<double>() + i * (size_t)kTotalsWorkRows * b->max_bins;
-        DR_HIP(enqueue_totals(g, b->parts.as<float>() + b->part_off[i], b->slots[i], work,
-                              b->items[i].totals, s));
-    }
+    DR_HIP(launch_totals_multi_f32(b->tjobs.as<TotalsJob>(), b->n_jobs, b->jblocks1,
+                                   b->jblocks2, s));
     return DR_OK;
 }
 

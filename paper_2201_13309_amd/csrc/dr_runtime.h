@@ -118,6 +118,8 @@ struct dr_batch_s {
     int gpc = 0;
     int max_bins = 1;
     dr::DevBuf scans, starts, counter, parts, work;
+    dr::DevBuf tjobs;               // TotalsJob per scan with totals
+    int n_jobs = 0, jblocks1 = 0, jblocks2 = 0;
     int64_t total_tiles2 = 0;       // tiles of second passes (launched after the first)
     int n_args1 = 0, n_args2 = 0;   // ScanArgs entries of each launch
     std::vector<int64_t> part_off;  // per item offset into parts (floats)
