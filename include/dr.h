@@ -148,11 +148,14 @@ dr_status dr_ctx_destroy(dr_ctx ctx);
  * per-pixel geometry the paper's kernel reads for each pixel (Sec. III-C) -
  * and check it on the device.  Copies every input, so the caller may free its
  * arrays on return; the library owns *out until dr_geometry_free.
- * Errors: DR_E_INVAL for NULL pointers, nx/ny/n_bins < 1, n_steps < 2,
- * radius <= 0, width <= 0, an unknown edge, a zero or non-finite axis or one
- * along the beam, a pixel inside the wire, a wire position not strictly
- * between beam and pixel in eta (0 < eta_wire < eta_pixel), or any
- * non-finite depth on the wire edge(s) that wire->edge reconstructs;
+ * Errors: DR_E_INVAL for NULL pointers, nx/ny/n_bins < 1, nx * ny >= 2^32,
+ * n_bins > 2^30, n_steps < 2, radius <= 0, width <= 0, an unknown edge, a
+ * zero or non-finite axis or one along the beam, a pixel inside the wire, a
+ * wire position not strictly between beam and pixel in eta
+ * (0 < eta_wire < eta_pixel), or any non-finite depth on the wire edge(s)
+ * that wire->edge reconstructs; for geometries on the per-pixel path also a
+ * pixel within 2^-383 um of the wire surface (L2 - r^2 < 2^-767) or an edge
+ * position 2^30 bins or more from the grid's first bin;
  * DR_E_NOMEM / DR_E_DEVICE for allocation or HIP failures.
  * Synchronous. */
 dr_status dr_geometry_init(dr_ctx ctx, const dr_detector* det, const dr_wire* wire,

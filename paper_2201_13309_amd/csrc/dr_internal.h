@@ -69,7 +69,8 @@ struct GeomArgs {
     double radius, first_center, width;
     double axis[3];         // wire axis as given (normalised on the device)
     const double* wire_raw; // [n_steps][3] wire centres as given
-    const double* wire_yz;  // [n_steps][2] projected (eta, xi), built on the device
+    const double* wire_yz;  // [n_steps + 2][2] projected (eta, xi), built on the device;
+                            // entries n_steps and n_steps + 1 repeat the last
     const double* pix_xyz;  // [ny][nx][3] explicit pixel centres, or null (affine map)
     double origin[3], u[3], v[3];
 };

@@ -266,7 +266,7 @@ __global__ __launch_bounds__(256) void validate_pixels_kernel(GeomArgs g, int si
         for (int k = 0; k < g.n_steps; ++k) {
             const double u = edge_position(g, py, pz, k, sr, f.c, e0, invw);
             if (!__builtin_isfinite(u)) bad |= 1;
-            else if (!(__builtin_fabs(u) < 0x1p30)) bad |= 4;
+            else if (!(__builtin_fabs(u) < 0x1p30)) bad |= 8;
         }
     }
     for (int k = 0; k < g.n_steps; ++k) {

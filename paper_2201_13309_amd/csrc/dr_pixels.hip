@@ -352,13 +352,13 @@ __global__ __launch_bounds__(kPixelTile) void pixels_f32_kernel(ScanArgs a, Geom
 
     double v_prev = sgn * u_first;
     int p_prev = pbin(v_prev);
-    // the wire position of the coming step, loaded one step ahead
-    double wy = wire[2 * min(1, N - 1)], wz = wire[2 * min(1, N - 1) + 1];
+    // the wire position of the coming step, loaded one step ahead (the table
+    // repeats its last position twice: no clamp)
+    double wy = wire[2], wz = wire[3];
     auto step = [&](int k, int s0, int s1) {
         const double cy = wy, cz = wz;
-        const int kn = min(k + 2, N - 1);
-        wy = wire[2 * kn];
-        wz = wire[2 * kn + 1];
+        wy = wire[2 * (unsigned)(k + 2)];
+        wz = wire[2 * (unsigned)(k + 2) + 1];
         const double v_next = position_at<TILT>(cy, cz, py, pz, r, sr, c, e0, sinvw);
         const int p_next = pbin(v_next);
         Cum dI;  // this step's intensity difference (unscaled)
@@ -394,15 +394,21 @@ __global__ __launch_bounds__(kPixelTile) void pixels_f32_kernel(ScanArgs a, Geom
     // ring of U samples: slot k % U holds step k; blocks of U steps
     constexpr int U = PF + 1;
     unsigned short smp[U];
+    // sample k at ip + k * img_step: an unsigned 32 x 32 -> 64-bit product
+    // (k < 2^31, img_step <= ny * nx < 2^32)
+    const uint32_t istep = (uint32_t)a.img_step;
+    auto sample_at = [&](int k) {
+        return stream_load(ip + (uint64_t)(uint32_t)min(k, N - 1) * istep);
+    };
 #pragma unroll
-    for (int dd = 0; dd < U; ++dd) smp[dd] = stream_load(ip + (int64_t)min(dd, N - 1) * a.img_step);
+    for (int dd = 0; dd < U; ++dd) smp[dd] = sample_at(dd);
     int k0 = 0;
     for (; k0 + U <= nint; k0 += U) {
         if (ring_on) flush(wave_min(act ? nxt : B));
 #pragma unroll
         for (int dd = 0; dd < U; ++dd) {
             step(k0 + dd, (int)smp[dd], (int)smp[(dd + 1) % U]);
-            smp[dd] = stream_load(ip + (int64_t)min(k0 + dd + U, N - 1) * a.img_step);
+            smp[dd] = sample_at(k0 + dd + U);
         }
     }
     if (ring_on) flush(wave_min(act ? nxt : B));

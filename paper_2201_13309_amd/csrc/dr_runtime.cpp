@@ -303,6 +303,8 @@ dr_status dr_geometry_init(dr_ctx c, const dr_detector* det, const dr_wire* wire
         return set_error(DR_E_INVAL, "dr_geometry_init: NULL argument");
     *out = nullptr;
     if (det->nx < 1 || det->ny < 1) return set_error(DR_E_INVAL, "detector nx, ny must be >= 1");
+    if ((int64_t)det->nx * det->ny >= ((int64_t)1 << 32))
+        return set_error(DR_E_INVAL, "detector nx * ny must be below 2^32");
     if (wire->n_steps < 2 || !wire->centers)
         return set_error(DR_E_INVAL, "wire needs n_steps >= 2 and centers");
     if (grid->n_bins < 1) return set_error(DR_E_INVAL, "depth grid needs n_bins >= 1");
@@ -354,11 +356,13 @@ dr_status dr_geometry_init(dr_ctx c, const dr_detector* det, const dr_wire* wire
         }
     }
 
-    // wire: raw centres [N][3], then the projected (eta, xi) [N][2]; pixel
-    // centres [ny][nx][3] when given explicitly; one status word and one
-    // row-uniformity flag per row
+    // wire: raw centres [N][3], then the projected (eta, xi) [N + 2][2] (the
+    // last position repeated twice, so that kernels reading one or two steps
+    // ahead need no clamp); pixel centres [ny][nx][3] when given explicitly;
+    // one status word and one row-uniformity flag per row
     auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    const size_t w_raw = 0, w_yz = up((size_t)N * 3 * 8), w_st = w_yz + up((size_t)N * 2 * 8),
+    const size_t w_raw = 0, w_yz = up((size_t)N * 3 * 8),
+                 w_st = w_yz + up((size_t)(N + 2) * 2 * 8),
                  w_fl = w_st + 256, w_total = w_fl + up((size_t)ny * 4);
     DR_HIP(g->wire.reserve(w_total));
     char* wb = g->wire.as<char>();
@@ -394,6 +398,9 @@ dr_status dr_geometry_init(dr_ctx c, const dr_detector* det, const dr_wire* wire
     ga.wire_yz = d_wyz;
     ga.pix_xyz = det->pixel_xyz ? g->pix.as<double>() : nullptr;
     DR_HIP(launch_project_wire(ga, d_wyz, d_status, c->stream));
+    for (int k = N; k < N + 2; ++k)
+        DR_HIP(hipMemcpyAsync(d_wyz + 2 * k, d_wyz + 2 * (N - 1), 2 * sizeof(double),
+                              hipMemcpyDeviceToDevice, c->stream));
     DR_HIP(launch_row_uniform(ga, d_flags, c->stream));
     int status = 0;
     std::vector<int> flags(ny);
@@ -421,7 +428,7 @@ dr_status dr_geometry_init(dr_ctx c, const dr_detector* det, const dr_wire* wire
         if (status & 2)
             return set_error(DR_E_INVAL,
                              "wire not strictly between the beam and the detector in y");
-        if (status & 4)
+        if (status & 8)
             return set_error(DR_E_INVAL, "an edge position lies 2^30 bins or more from the "
                                          "grid's first bin (depth grid too fine for the sweep)");
         for (int i = 0; i < 3; ++i) DR_HIP(hipEventCreate(&g->ev[i]));
