@@ -267,3 +267,24 @@ def test_grid_too_fine_for_the_sweep_refused(dr, ctx):
     with pytest.raises(dr.DRError) as e:
         dr.dr_geometry_init(ctx, s.detector, s.wire, fine)
     assert e.value.code == dr.DR_E_INVAL and "2^30" in str(e.value)
+
+
+@pytest.mark.parametrize("name", ["tilted_detector", "tilted_decreasing", "both_axis_oblique",
+                                  "pixel_table_spread"])
+def test_totals_repeatable(dr, ctx, name):
+    """Totals do not depend on the order in which the hardware runs the
+    workgroups: the FP32 kernel sums each wave's closed bins through its LDS
+    ring in a fixed tree and adds the wave rows in order, and the FP64
+    instance sums its finished output in a fixed order.  Five runs each must
+    agree bit for bit (FP64 on every case; FP32 where every close falls in the
+    ring, i.e. all but the case whose shadows lie ~90 bins apart in a wave)."""
+    s = make_case(name)
+    g = dr.dr_geometry_init(ctx, s.detector, s.wire, s.grid)
+    try:
+        t64 = [run_f64(dr, ctx, s)[1] for _ in range(5)]
+        assert all(np.array_equal(t.view(np.int64), t64[0].view(np.int64)) for t in t64)
+        if name != "pixel_table_spread":
+            t32 = [run_f32(dr, ctx, s, geom=g)[1] for _ in range(5)]
+            assert all(np.array_equal(t.view(np.int32), t32[0].view(np.int32)) for t in t32)
+    finally:
+        dr.dr_geometry_free(g)
