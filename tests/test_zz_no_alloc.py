@@ -116,3 +116,34 @@ def test_noalloc_refuses_oversized_scratch(dr, ctx):
     finally:
         dr.dr_geometry_free(g)
         torch.cuda.empty_cache()
+
+
+def test_noalloc_full_frame(dr, ctx):
+    """The largest scan the fixed array serves: 2048^2 px, 1001 steps, 1001
+    bins with totals (125.6 MiB of partial rows at the autotuned (2, 4, 16)
+    shape), bitwise equal to dr_reconstruct, then a smaller scan again."""
+    import torch
+    s = synth.config3()
+    B, ny, nx = s.grid.n_bins, s.detector.ny, s.detector.nx
+    g = dr.dr_geometry_init(ctx, s.detector, s.wire, s.grid)
+    stream = torch.cuda.current_stream()
+    try:
+        img = dev_images(s.images)
+        s.images = None
+        dr.dr_set_tile(g, (2, 4, 16))
+        ref = torch.empty((B, ny, nx), device="cuda")
+        tref = torch.empty((B,), device="cuda")
+        dr.dr_reconstruct(g, img, True, ref, tref, stream)
+        out = torch.full((B, ny, nx), float("nan"), device="cuda")
+        tot = torch.full((B,), float("nan"), device="cuda")
+        dr.dr_reconstruct_noalloc(g, img, out, tot, stream)
+        torch.cuda.synchronize()
+        for r0 in range(0, ny, 64):
+            assert torch.equal(out[:, r0:r0 + 64].view(torch.int32),
+                               ref[:, r0:r0 + 64].view(torch.int32)), r0
+        assert torch.equal(tot.view(torch.int32), tref.view(torch.int32))
+        del img, ref, out
+    finally:
+        dr.dr_geometry_free(g)
+        torch.cuda.empty_cache()
+    both_ways(dr, ctx, synth.config1(), 300, 63)
