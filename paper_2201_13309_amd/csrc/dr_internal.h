@@ -73,6 +73,11 @@ struct GeomArgs {
                             // entries n_steps and n_steps + 1 repeat the last
     const double* pix_xyz;  // [ny][nx][3] explicit pixel centres, or null (affine map)
     double origin[3], u[3], v[3];
+    // per-pixel path: bound (bin units) on the difference between the fast
+    // and the exact FP64 edge position at any pixel and step; positions of
+    // the fast form within it of an integer are recomputed exactly (>= 1:
+    // every position exact)
+    double pos_margin = 1.0;
 };
 
 // A pixel list as seen by the list kernels: entries sorted by pixel index and
@@ -167,7 +172,10 @@ hipError_t launch_project_wire(const GeomArgs& g, double* wire_yz, int* d_status
 hipError_t launch_row_uniform(const GeomArgs& g, int* flags, hipStream_t s);
 // per-pixel geometry checks (status bits as in build_plans_kernel)
 // sides: bit 0 leading edge, bit 1 trailing edge (the sides the passes use)
-hipError_t launch_validate_pixels(const GeomArgs& g, int sides, int* d_status, hipStream_t s);
+// margin_bits: the largest fast-position error bound over every pixel and
+// step (bin units, as the bits of a non-negative double; 0 before the launch)
+hipError_t launch_validate_pixels(const GeomArgs& g, int sides, int* d_status,
+                                  unsigned long long* margin_bits, hipStream_t s);
 // per-pixel path: one lane per pixel, positions and bins computed in FP64 on
 // the fly.  side 0/1 = leading/trailing, scale as for the plan tables.
 hipError_t launch_pixels_f32(const ScanArgs& a, const GeomArgs& g, int side, double scale,

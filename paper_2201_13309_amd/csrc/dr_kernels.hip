@@ -249,7 +249,8 @@ __global__ __launch_bounds__(256) void row_uniform_kernel(GeomArgs g, int* flags
 // every (pixel, step) of a per-pixel geometry: finite positions on the edge
 // sides in `sides` (bit 0 leading, bit 1 trailing), wire between beam and
 // pixel (status bits 1 and 2 as in build_plans_kernel)
-__global__ __launch_bounds__(256) void validate_pixels_kernel(GeomArgs g, int sides, int* status)
+__global__ __launch_bounds__(256) void validate_pixels_kernel(GeomArgs g, int sides, int* status,
+                                                              unsigned long long* margin_bits)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= (int64_t)g.nx * g.ny) return;
@@ -263,11 +264,37 @@ __global__ __launch_bounds__(256) void validate_pixels_kernel(GeomArgs g, int si
         if (!(sides & (1 << side))) continue;
         const int s = side ? -leading_sign(g, py, pz) : leading_sign(g, py, pz);
         const double sr = (double)s * g.radius;
+        double bound = 0.0;
         for (int k = 0; k < g.n_steps; ++k) {
             const double u = edge_position(g, py, pz, k, sr, f.c, e0, invw);
             if (!__builtin_isfinite(u)) bad |= 1;
             else if (!(__builtin_fabs(u) < 0x1p30)) bad |= 8;
+            // How far the per-pixel kernel's fast position (one Newton step
+            // after the hardware reciprocal square root and reciprocal,
+            // relative errors below 2^-47, and 1/c for a tilted axis) can lie
+            // from this exact one: its square root moves t_xi, t_eta and so
+            // the quotient Q = num / t_eta by (|C_eta a_xi| + |Q a_eta|) kk /
+            // |t_eta| times its relative error, the division Q by |Q| times
+            // its error, and the roundings of every term are of the order of
+            // the terms; 2^-38, 2^9 above the errors, times the sum of the
+            // magnitudes, in bins.
+            const double cy = g.wire_yz[2 * k], cz = g.wire_yz[2 * k + 1];
+            const double ay = cy - py, az = cz - pz;
+            const double L2 = az * az + ay * ay;
+            const double kk = __builtin_sqrt(L2 - g.radius * g.radius);
+            const double ty = ay * kk + az * sr;
+            const double q = (cy * (az * kk - ay * sr) + sr * L2) / ty;
+            const double terms =
+                (__builtin_fabs(cy) * (__builtin_fabs(az) * kk + __builtin_fabs(ay) * g.radius) +
+                 g.radius * L2 +
+                 __builtin_fabs(q) * (__builtin_fabs(ay) * kk + __builtin_fabs(az) * g.radius)) /
+                __builtin_fabs(ty);
+            const double b = 0x1p-38 *
+                             (__builtin_fabs(cz) + __builtin_fabs(q) + __builtin_fabs(e0) + terms) /
+                             __builtin_fabs(f.c) * invw;
+            bound = __builtin_isfinite(b) ? __builtin_fmax(bound, b) : 1.0;
         }
+        atomicMax(margin_bits, (unsigned long long)__double_as_longlong(bound));
     }
     for (int k = 0; k < g.n_steps; ++k) {
         const double cy = g.wire_yz[2 * k];
@@ -433,11 +460,12 @@ hipError_t launch_row_uniform(const GeomArgs& g, int* flags, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_validate_pixels(const GeomArgs& g, int sides, int* d_status, hipStream_t s)
+hipError_t launch_validate_pixels(const GeomArgs& g, int sides, int* d_status,
+                                  unsigned long long* margin_bits, hipStream_t s)
 {
     const int64_t n = (int64_t)g.nx * g.ny;
     hipLaunchKernelGGL(validate_pixels_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                       g, sides, d_status);
+                       g, sides, d_status, margin_bits);
     return hipGetLastError();
 }
 

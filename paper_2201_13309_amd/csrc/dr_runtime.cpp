@@ -419,9 +419,18 @@ dr_status dr_geometry_init(dr_ctx c, const dr_detector* det, const dr_wire* wire
     if (!row_mode) {
         int sides = 0;  // only the edge sides the passes use
         for (int p = 0; p < g->passes; ++p) sides |= 1 << g->side[p];
-        DR_HIP(launch_validate_pixels(ga, sides, d_status, c->stream));
+        unsigned long long* d_margin = (unsigned long long*)(wb + w_st + 8);
+        unsigned long long margin_bits = 0;
+        DR_HIP(hipMemsetAsync(d_margin, 0, sizeof(unsigned long long), c->stream));
+        DR_HIP(launch_validate_pixels(ga, sides, d_status, d_margin, c->stream));
         DR_HIP(hipMemcpyAsync(&status, d_status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        DR_HIP(hipMemcpyAsync(&margin_bits, d_margin, sizeof(margin_bits), hipMemcpyDeviceToHost,
+                              c->stream));
         DR_HIP(hipStreamSynchronize(c->stream));
+        double margin = 1.0;
+        std::memcpy(&margin, &margin_bits, sizeof(margin));
+        // twice the largest bound; 1 (every position exact) when it is not small
+        ga.pos_margin = (std::isfinite(margin) && margin < 0x1p-12) ? 2.0 * margin : 1.0;
         if (status & 1)
             return set_error(DR_E_INVAL, "geometry gives a non-finite depth (pixel inside the "
                                          "wire or a ray parallel to the beam)");

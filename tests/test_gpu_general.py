@@ -288,3 +288,49 @@ def test_totals_repeatable(dr, ctx, name):
             assert all(np.array_equal(t.view(np.int32), t32[0].view(np.int32)) for t in t32)
     finally:
         dr.dr_geometry_free(g)
+
+
+def test_positions_on_bin_edges(dr, ctx):
+    """Edge positions that land exactly on bin edges.  With a 1 um grid whose
+    lower edge e0 is d - m for the exact depth d of one pixel at one step
+    (d - m is exact by Sterbenz's lemma for |d| >= 2 and m = floor(d)), that
+    position is exactly an integer in bin units.  The kernel's fast position
+    there lies within its error bound of the integer and must fall back to
+    the exact one: bins, FP64 output and FP32 output against the oracle as
+    everywhere."""
+    base = make_case("tilted_detector")
+    grid0 = synth.DepthGrid(base.grid.n_bins, 0.5, 1.0)  # e0 = 0: u = d exactly
+    probe = synth.Scan(base.name, base.detector, base.wire, grid0, base.sources, base.dark,
+                       base.noise, base.seed)
+    nx = base.detector.nx
+    pix = np.arange(nx, 2 * nx, 37, dtype=np.int64)
+    _, _, u = oracle.reconstruct_pixels(probe, pix, want_bins=False, want_u=True)
+    ok = np.argwhere(np.abs(u) >= 2.0)
+    assert ok.shape[0] > 0
+    i, k = ok[ok.shape[0] // 2]
+    d = float(u[i, k])
+    m = math.floor(d)
+    e0 = d - m
+    assert e0 + m == d and (e0 + 0.5) - 0.5 == e0
+    lo = math.floor(float(u.min())) - m - 4
+    B = int(math.ceil(float(u.max())) - m + 4 - lo)
+    # bin b of the new grid covers [e0 + (b + lo) um, ...): first centre e0 + lo + 0.5
+    s = synth.Scan("bin_edges", base.detector, base.wire,
+                   synth.DepthGrid(B, (e0 + lo) + 0.5, 1.0), base.sources, base.dark, base.noise,
+                   base.seed)
+    s.images = base.images
+    _, bins_ref, u_ref = oracle.reconstruct_pixels(s, pix, want_bins=True, want_u=True)
+    assert float(u_ref[i, k]) == float(m - lo)  # exactly on a bin edge
+    g = dr.dr_geometry_init(ctx, s.detector, s.wire, s.grid)
+    try:
+        bins, upos = dr.dr_debug_plan(g, pix, s.wire.n_steps)
+        assert np.array_equal(bins, bins_ref)
+        assert np.array_equal(upos.view(np.int64), u_ref.view(np.int64))
+    finally:
+        dr.dr_geometry_free(g)
+    out_ref, tot_ref, _ = oracle.reconstruct(s)
+    out64, _ = run_f64(dr, ctx, s)
+    assert np.array_equal(out64.view(np.int64), out_ref.view(np.int64))
+    out, tot = run_f32(dr, ctx, s)
+    assert_f32_close(out, out_ref, s.images)
+    assert_totals_close(tot, tot_ref, s.images)
