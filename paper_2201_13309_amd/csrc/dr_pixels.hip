@@ -168,33 +168,34 @@ __device__ __forceinline__ int wave_min(int v)
 }
 
 // FP32 per-pixel kernel: one lane per pixel of a row tile (or of a list tile,
-// as in the FP64 instance below).  The lane's FP64 positions u_k (bin units,
-// the fixed operation order of the tangent construction) are turned into its
-// walk direction by v = sgn*u, with sgn = +1 when its positions rise over the
-// scan and -1 otherwise (negation is exact); bin p = floor(v) + off (off = 0,
-// or B for sgn = -1) counts bins in the order the walk meets them (p = b, or
-// B - 1 - b).  Bins below the open bin `nxt` are stored; bin nxt accumulates.
+// as in the FP64 instance below).  The lane's FP64 positions u_k (bin units;
+// position_fast, or position_at where the fast form lies within the
+// geometry's margin of an integer, so that every floor is the exact
+// position's) are turned into its walk direction by v = sgn*u, with sgn = +1
+// when its positions rise over the scan and -1 otherwise (negation is
+// exact); bin p = floor(v) + off (off = 0, or B for sgn = -1) counts bins in
+// the order the walk meets them (p = b, or B - 1 - b).  Bins below the open
+// bin `nxt` are stored; bin nxt accumulates.
 //
 // Fast form: the step starts in the open bin and ends in it or in the next
-// one.  Let C(x) be the mass of
-// the intervals so far below x; a bin holds C(upper boundary) - C(lower
-// boundary).  In a walk of this kind every earlier interval lies below the
-// open bin's upper boundary bd, so C(bd) is the mass before the step (the sum
-// of the differences so far, kept exactly: an integer, or FP64 with step
-// weights) plus the step's part below bd, dI_k (bd - v_k) / (v_{k+1} - v_k).
-// A step that stays inside the open bin costs one integer add; one that
-// crosses bd costs one FP64 fma and stores the closed bin.  The values differ
-// from the per-step sums only by rounding: the fraction carries an FP32
-// reciprocal of the length (relative error 2^-23), each C one FP64 rounding,
-// the stored difference one FP32 rounding.
+// one.  Let C(x) be the mass of the intervals so far below x; a bin holds
+// C(upper boundary) - C(lower boundary).  In a walk of this kind every
+// earlier interval lies below the open bin's upper boundary bd, so C(bd) is
+// the mass before the step (the sum of the differences so far, kept exactly:
+// an integer, or FP64 with step weights) plus the step's part below bd,
+// dI_k (bd - v_k) / (v_{k+1} - v_k).  A step that stays inside the open bin
+// costs one integer add; one that crosses bd costs one FP64 fma and stores
+// the closed bin.  The values differ from the per-step sums only by rounding:
+// the fraction carries an FP32 reciprocal of the length (relative error
+// 2^-23), each C one FP64 rounding, the stored difference one FP32 rounding.
 //
 // General form, for any other step (entering or leaving the grid, more than
 // one boundary in a step, a walk that turns back): the interval's bins and
-// fractions (plan_f32) are visited one
-// by one, the open bin's value `acc` in FP32.  acc is taken from C as the mass
-// so far minus the mass below the open bin (`clast`), and given back the same
-// way; nothing lies above the open bin, so the two agree.  A bin behind nxt
-// that is visited again is read, added to and rewritten.
+// fractions (plan_f32) are visited one by one, the open bin's value `acc` in
+// FP32.  acc is taken from C as the mass so far minus the mass below the open
+// bin (`clast`), and given back the same way; nothing lies above the open
+// bin, so the two agree.  A bin behind nxt that is visited again is read,
+// added to and rewritten.
 //
 // Untouched bins are stored as zeros, except in the second pass of a
 // two-edge reconstruction (ADD), whose values are added onto the first
