@@ -248,25 +248,48 @@ __global__ __launch_bounds__(256) void row_uniform_kernel(GeomArgs g, int* flags
 
 // every (pixel, step) of a per-pixel geometry: finite positions on the edge
 // sides in `sides` (bit 0 leading, bit 1 trailing), wire between beam and
-// pixel (status bits 1 and 2 as in build_plans_kernel)
+// pixel (status bits 1 and 2 as in build_plans_kernel), |u| < 2^30 (bit 8),
+// and the margin within which the per-pixel kernel's fast positions must
+// stay away from an integer (*margin_bits: the largest bound of the pixels,
+// as the bits of a non-negative double, so that unsigned order is numeric
+// order)
 __global__ __launch_bounds__(256) void validate_pixels_kernel(GeomArgs g, int sides, int* status,
                                                               unsigned long long* margin_bits)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= (int64_t)g.nx * g.ny) return;
+    // lanes past the last pixel repeat it, so that every lane of the wave
+    // takes part in the wave's maximum below
+    const int64_t n = (int64_t)g.nx * g.ny;
     const Frame f = axis_frame(g);
     double py, pz;
-    pixel_key(g, f, p, py, pz);
+    pixel_key(g, f, p < n ? p : n - 1, py, pz);
     const double e0 = g.first_center - g.width / 2.0;
     const double invw = 1.0 / g.width;
+    const double r = g.radius;
     int bad = 0;
     for (int side = 0; side < 2; ++side) {
         if (!(sides & (1 << side))) continue;
         const int s = side ? -leading_sign(g, py, pz) : leading_sign(g, py, pz);
-        const double sr = (double)s * g.radius;
+        const double sr = (double)s * r;
         double bound = 0.0;
         for (int k = 0; k < g.n_steps; ++k) {
-            const double u = edge_position(g, py, pz, k, sr, f.c, e0, invw);
+            // the operations of tangent_depth and edge_position, in their
+            // order, keeping the parts the bound below needs
+            const double cy = g.wire_yz[2 * k], cz = g.wire_yz[2 * k + 1];
+            const double ay = cy - py, az = cz - pz;
+            const double L2 = az * az + ay * ay;
+            const double q = L2 - r * r;
+            double kk;
+            if (q >= 0x1p-767 && q < __builtin_inf())
+                kk = sqrt_newton(q);
+            else
+                kk = q > 0.0 ? __builtin_sqrt(q) : __builtin_nan("");
+            const double tz = az * kk - ay * sr;
+            const double ty = ay * kk + az * sr;
+            const double Q = (cy * tz + sr * L2) / ty;
+            const double t = cz - Q;
+            const double d = f.c == 1.0 ? t : t / f.c;
+            const double u = (d - e0) * invw;
             if (!__builtin_isfinite(u)) bad |= 1;
             else if (!(__builtin_fabs(u) < 0x1p30)) bad |= 8;
             // How far the per-pixel kernel's fast position (one Newton step
@@ -278,30 +301,29 @@ __global__ __launch_bounds__(256) void validate_pixels_kernel(GeomArgs g, int si
             // its error, and the roundings of every term are of the order of
             // the terms; 2^-38, 2^9 above the errors, times the sum of the
             // magnitudes, in bins.
-            const double cy = g.wire_yz[2 * k], cz = g.wire_yz[2 * k + 1];
-            const double ay = cy - py, az = cz - pz;
-            const double L2 = az * az + ay * ay;
-            const double kk = __builtin_sqrt(L2 - g.radius * g.radius);
-            const double ty = ay * kk + az * sr;
-            const double q = (cy * (az * kk - ay * sr) + sr * L2) / ty;
             const double terms =
-                (__builtin_fabs(cy) * (__builtin_fabs(az) * kk + __builtin_fabs(ay) * g.radius) +
-                 g.radius * L2 +
-                 __builtin_fabs(q) * (__builtin_fabs(ay) * kk + __builtin_fabs(az) * g.radius)) /
+                (__builtin_fabs(cy) * (__builtin_fabs(az) * kk + __builtin_fabs(ay) * r) + r * L2 +
+                 __builtin_fabs(Q) * (__builtin_fabs(ay) * kk + __builtin_fabs(az) * r)) /
                 __builtin_fabs(ty);
             const double b = 0x1p-38 *
-                             (__builtin_fabs(cz) + __builtin_fabs(q) + __builtin_fabs(e0) + terms) /
+                             (__builtin_fabs(cz) + __builtin_fabs(Q) + __builtin_fabs(e0) + terms) /
                              __builtin_fabs(f.c) * invw;
             bound = __builtin_isfinite(b) ? __builtin_fmax(bound, b) : 1.0;
         }
-        atomicMax(margin_bits, (unsigned long long)__double_as_longlong(bound));
+        // the wave's largest bound, then one atomic per wave
+        unsigned long long bits = (unsigned long long)__double_as_longlong(bound);
+        for (int off = 32; off >= 1; off >>= 1) {
+            const unsigned long long o = __shfl_xor(bits, off, 64);
+            bits = o > bits ? o : bits;
+        }
+        if ((threadIdx.x & 63) == 0) atomicMax(margin_bits, bits);
     }
     for (int k = 0; k < g.n_steps; ++k) {
         const double cy = g.wire_yz[2 * k];
         if (!(cy > 0.0 && cy < py)) bad |= 2;
         // the per-pixel kernels take the square root's Newton form unguarded
         const double ay = cy - py, az = g.wire_yz[2 * k + 1] - pz;
-        if (!((az * az + ay * ay) - g.radius * g.radius >= 0x1p-767)) bad |= 1;
+        if (!((az * az + ay * ay) - r * r >= 0x1p-767)) bad |= 1;
     }
     if (bad) atomicOr(status, bad);
 }
