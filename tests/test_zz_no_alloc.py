@@ -147,3 +147,78 @@ def test_noalloc_full_frame(dr, ctx):
         dr.dr_geometry_free(g)
         torch.cuda.empty_cache()
     both_ways(dr, ctx, synth.config1(), 300, 63)
+
+
+def _with_weights(s, seed):
+    w = np.random.default_rng(seed).uniform(0.5, 2.0, s.wire.n_steps)
+    s.wire = synth.Wire(s.wire.radius, s.wire.centers, axis=s.wire.axis, edge=s.wire.edge,
+                        weights=w)
+    return s
+
+
+def _tilted(s, u):
+    d = s.detector
+    s.detector = synth.Detector(d.nx, d.ny, d.origin, np.asarray(u, dtype=np.float64), d.v)
+    synth.render(s)
+    return s
+
+
+def _every_path_case(name):
+    if name == "rows_both_edges":
+        s = synth.tiny(160, 5, 33, 141, seed=701, n_src=10, dark=100.0)
+        s.grid = synth.DepthGrid(141, -71.5 + 0.35, 0.7)
+        s.wire.edge = synth.EDGE_BOTH
+    elif name == "rows_non_monotone":  # the generic (read-modify-write) row body
+        s = synth.tiny(96, 6, 31, 81, seed=702, n_src=8, dark=100.0)
+        c = s.wire.centers
+        s.wire = synth.Wire(s.wire.radius, np.ascontiguousarray(np.concatenate([c, c[::-1][1:]])))
+        synth.render(s)
+    elif name == "rows_weighted":
+        s = _with_weights(synth.tiny(300, 7, 37, 61, seed=703, n_src=12, dark=100.0), 704)
+    elif name == "pixels_both_edges":  # per-pixel kernel, two passes
+        s = _tilted(synth.tiny(300, 4, 31, 81, seed=705, n_src=10, dark=100.0,
+                               render_now=False), [200.0, 15.0, 35.0])
+        s.grid = synth.DepthGrid(81, -72.0 + 0.6, 1.2)
+        s.wire.edge = synth.EDGE_BOTH
+    elif name == "pixels_many_bins":  # partial totals beyond the kernel's LDS ring
+        s = _tilted(synth.tiny(40, 2, 21, 20000, seed=706, n_src=4, dark=100.0, width=0.002,
+                               render_now=False), [200.0, 0.0, 10.0])
+    elif name == "pixels_weighted":
+        s = _with_weights(_tilted(synth.tiny(300, 4, 31, 81, seed=707, n_src=10, dark=100.0,
+                                             render_now=False), [200.0, 15.0, 35.0]), 708)
+    else:
+        raise KeyError(name)
+    s.name = name
+    return s
+
+
+@pytest.mark.parametrize("name", ["rows_both_edges", "rows_non_monotone", "rows_weighted",
+                                  "pixels_both_edges", "pixels_many_bins", "pixels_weighted"])
+def test_noalloc_every_path(dr, ctx, name):
+    """Every kernel path that writes scratch (two-edge passes, the generic row
+    body, step weights, the per-pixel kernel, and its totals summed in place
+    when the bins outgrow its LDS): bitwise equal to dr_reconstruct, with and
+    without totals, twice in a row into the same buffers."""
+    import torch
+    s = _every_path_case(name)
+    B, ny, nx = s.grid.n_bins, s.detector.ny, s.detector.nx
+    g = dr.dr_geometry_init(ctx, s.detector, s.wire, s.grid)
+    stream = torch.cuda.current_stream()
+    try:
+        img = dev_images(s.images)
+        ref = torch.full((B, ny, nx), float("nan"), device="cuda")
+        tref = torch.full((B,), float("nan"), device="cuda")
+        dr.dr_reconstruct(g, img, True, ref, tref, stream)
+        out = torch.full((B, ny, nx), float("nan"), device="cuda")
+        tot = torch.full((B,), float("nan"), device="cuda")
+        for _ in range(2):
+            dr.dr_reconstruct_noalloc(g, img, out, tot, stream)
+        out_nt = torch.full((B, ny, nx), float("nan"), device="cuda")
+        dr.dr_reconstruct_noalloc(g, img, out_nt, None, stream)
+        torch.cuda.synchronize()
+        assert not bool(torch.isnan(ref).any()) and not bool(torch.isnan(tref).any())
+        assert torch.equal(out.view(torch.int32), ref.view(torch.int32)), name
+        assert torch.equal(out_nt.view(torch.int32), ref.view(torch.int32)), name
+        assert torch.equal(tot.view(torch.int32), tref.view(torch.int32)), name
+    finally:
+        dr.dr_geometry_free(g)
