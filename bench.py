@@ -343,6 +343,7 @@ def run_per_pixel(torch, synth, dr, ctx, s, dev, out, tot, stream, steps: int,
         g = dr.dr_geometry_init(ctx, det, wire, s.grid)
         try:
             assert dr.dr_geometry_path(g) == dr.DR_PATH_PIXELS
+            margin = dr.dr_geometry_position_margin(g)
             dr.dr_reconstruct(g, dev, True, out, tot, stream)
             torch.cuda.synchronize()
             ev0 = torch.cuda.Event(enable_timing=True)
@@ -358,7 +359,7 @@ def run_per_pixel(torch, synth, dr, ctx, s, dev, out, tot, stream, steps: int,
                 dr.dr_reconstruct(g, dev, True, out, tot, stream)
                 kl.append(dr.dr_last_timing(g)[0])
             dr.dr_enable_timing(g, False)
-            return ev0.elapsed_time(ev1) / steps, float(np.mean(kl))
+            return ev0.elapsed_time(ev1) / steps, float(np.mean(kl)), margin
         finally:
             dr.dr_geometry_free(g)
 
@@ -366,18 +367,19 @@ def run_per_pixel(torch, synth, dr, ctx, s, dev, out, tot, stream, steps: int,
     # one more FP64 division per step (the projected coordinate over cos)
     t3 = math.radians(3.0)
     w3 = synth.Wire(s.wire.radius, s.wire.centers, axis=np.array([math.cos(t3), 0.0, math.sin(t3)]))
-    ms_axis, kms_axis = timed(d, w3)
+    ms_axis, kms_axis, m_axis = timed(d, w3)
     log(f"per-pixel path, wire axis tilted 3 deg: {ms_axis:.2f} ms/step (kernel {kms_axis:.2f} ms)")
-    ms, kms = timed(det, s.wire)  # last, so that out and tot hold this geometry's result
+    ms, kms, m = timed(det, s.wire)  # last, so that out and tot hold this geometry's result
     work = d.nx * d.ny * s.wire.n_steps
     log(f"per-pixel path: {ms:.2f} ms/step (kernel {kms:.2f} ms)")
     res = {"value": work / (ms * 1e-3), "unit": UNIT, "ms_per_step": ms, "kernel_ms": kms,
            "kernel": "pixels_f32_kernel", "steps": steps,
            "geometry": "detector columns tilted 0.3 deg out of x (u = (200, 0, 1) um): "
                        "positions computed per pixel in FP64 on the fly",
+           "position_margin_bins": m,
            "tilted_axis": {"geometry": "flat detector, wire axis tilted 3 deg towards the beam",
                            "value": work / (ms_axis * 1e-3), "ms_per_step": ms_axis,
-                           "kernel_ms": kms_axis}}
+                           "kernel_ms": kms_axis, "position_margin_bins": m_axis}}
     if precision:
         ts = synth.Scan("tilted", det, s.wire, s.grid, None, 0.0, False, 0)
         ts.images = s.images

@@ -181,6 +181,16 @@ dr_status dr_geometry_set_step_weights(dr_geom geom, const double* weights);
 #define DR_PATH_PIXELS 1
 dr_status dr_geometry_path(dr_geom geom, int32_t* path);
 
+/* Per-pixel path diagnostic: the margin (bin units) within which a position
+ * of the shorter FP64 form (hardware reciprocal square root and reciprocal,
+ * each refined by one Newton step) must not come to an integer for its floor
+ * to be taken as the bin; closer positions are evaluated in the exact form,
+ * so bins always follow the exact positions.  *margin >= 1 means that every
+ * position is evaluated in the exact form (the geometry's bound is not small,
+ * or its shortest non-zero step is shorter than 2^18 margins); 0 for the
+ * per-row path.  Errors: DR_E_INVAL for NULL arguments. */
+dr_status dr_geometry_position_margin(dr_geom geom, double* margin);
+
 /* Free a geometry.  Waits for the device work already enqueued on it.
  * DR_E_BUSY while serving requests that use it are in flight, or while
  * pixel lists or batches built on it exist. */

@@ -76,7 +76,8 @@ struct GeomArgs {
     // per-pixel path: bound (bin units) on the difference between the fast
     // and the exact FP64 edge position at any pixel and step; positions of
     // the fast form within it of an integer are recomputed exactly (>= 1:
-    // every position exact)
+    // every position exact, as for geometries whose bound is not small or
+    // whose shortest step is too short for the fractions to stay exact)
     double pos_margin = 1.0;
 };
 
@@ -173,9 +174,12 @@ hipError_t launch_row_uniform(const GeomArgs& g, int* flags, hipStream_t s);
 // per-pixel geometry checks (status bits as in build_plans_kernel)
 // sides: bit 0 leading edge, bit 1 trailing edge (the sides the passes use)
 // margin_bits: the largest fast-position error bound over every pixel and
-// step (bin units, as the bits of a non-negative double; 0 before the launch)
+// step (bin units, as the bits of a non-negative double; 0 before the launch);
+// min_step_bits: the shortest non-zero step |u_{k+1} - u_k| over every pixel
+// (same form; at least every step before the launch)
 hipError_t launch_validate_pixels(const GeomArgs& g, int sides, int* d_status,
-                                  unsigned long long* margin_bits, hipStream_t s);
+                                  unsigned long long* margin_bits,
+                                  unsigned long long* min_step_bits, hipStream_t s);
 // per-pixel path: one lane per pixel, positions and bins computed in FP64 on
 // the fly.  side 0/1 = leading/trailing, scale as for the plan tables.
 hipError_t launch_pixels_f32(const ScanArgs& a, const GeomArgs& g, int side, double scale,

@@ -249,12 +249,14 @@ __global__ __launch_bounds__(256) void row_uniform_kernel(GeomArgs g, int* flags
 // every (pixel, step) of a per-pixel geometry: finite positions on the edge
 // sides in `sides` (bit 0 leading, bit 1 trailing), wire between beam and
 // pixel (status bits 1 and 2 as in build_plans_kernel), |u| < 2^30 (bit 8),
-// and the margin within which the per-pixel kernel's fast positions must
-// stay away from an integer (*margin_bits: the largest bound of the pixels,
-// as the bits of a non-negative double, so that unsigned order is numeric
-// order)
+// the margin within which the per-pixel kernel's fast positions must stay
+// away from an integer (*margin_bits: the largest bound of the pixels) and
+// the shortest step between two positions that differ (*min_step_bits: the
+// smallest |u_{k+1} - u_k| > 0 of the pixels); both as the bits of
+// non-negative doubles, so that unsigned order is numeric order
 __global__ __launch_bounds__(256) void validate_pixels_kernel(GeomArgs g, int sides, int* status,
-                                                              unsigned long long* margin_bits)
+                                                              unsigned long long* margin_bits,
+                                                              unsigned long long* min_step_bits)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     // lanes past the last pixel repeat it, so that every lane of the wave
@@ -271,7 +273,7 @@ __global__ __launch_bounds__(256) void validate_pixels_kernel(GeomArgs g, int si
         if (!(sides & (1 << side))) continue;
         const int s = side ? -leading_sign(g, py, pz) : leading_sign(g, py, pz);
         const double sr = (double)s * r;
-        double bound = 0.0;
+        double bound = 0.0, min_step = 0x1p1000, u_prev = 0.0;
         for (int k = 0; k < g.n_steps; ++k) {
             // the operations of tangent_depth and edge_position, in their
             // order, keeping the parts the bound below needs
@@ -292,6 +294,11 @@ __global__ __launch_bounds__(256) void validate_pixels_kernel(GeomArgs g, int si
             const double u = (d - e0) * invw;
             if (!__builtin_isfinite(u)) bad |= 1;
             else if (!(__builtin_fabs(u) < 0x1p30)) bad |= 8;
+            if (k > 0) {
+                const double len = __builtin_fabs(u - u_prev);
+                if (len > 0.0 && len < min_step) min_step = len;
+            }
+            u_prev = u;
             // How far the per-pixel kernel's fast position (one Newton step
             // after the hardware reciprocal square root and reciprocal,
             // relative errors below 2^-47, and 1/c for a tilted axis) can lie
@@ -310,13 +317,19 @@ __global__ __launch_bounds__(256) void validate_pixels_kernel(GeomArgs g, int si
                              __builtin_fabs(f.c) * invw;
             bound = __builtin_isfinite(b) ? __builtin_fmax(bound, b) : 1.0;
         }
-        // the wave's largest bound, then one atomic per wave
+        // the wave's largest bound and shortest step, then one atomic each
         unsigned long long bits = (unsigned long long)__double_as_longlong(bound);
+        unsigned long long sbits = (unsigned long long)__double_as_longlong(min_step);
         for (int off = 32; off >= 1; off >>= 1) {
             const unsigned long long o = __shfl_xor(bits, off, 64);
             bits = o > bits ? o : bits;
+            const unsigned long long so = __shfl_xor(sbits, off, 64);
+            sbits = so < sbits ? so : sbits;
         }
-        if ((threadIdx.x & 63) == 0) atomicMax(margin_bits, bits);
+        if ((threadIdx.x & 63) == 0) {
+            atomicMax(margin_bits, bits);
+            atomicMin(min_step_bits, sbits);
+        }
     }
     for (int k = 0; k < g.n_steps; ++k) {
         const double cy = g.wire_yz[2 * k];
@@ -483,11 +496,12 @@ hipError_t launch_row_uniform(const GeomArgs& g, int* flags, hipStream_t s)
 }
 
 hipError_t launch_validate_pixels(const GeomArgs& g, int sides, int* d_status,
-                                  unsigned long long* margin_bits, hipStream_t s)
+                                  unsigned long long* margin_bits,
+                                  unsigned long long* min_step_bits, hipStream_t s)
 {
     const int64_t n = (int64_t)g.nx * g.ny;
     hipLaunchKernelGGL(validate_pixels_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                       g, sides, d_status, margin_bits);
+                       g, sides, d_status, margin_bits, min_step_bits);
     return hipGetLastError();
 }
 

@@ -45,7 +45,9 @@ __device__ __forceinline__ double tangent_depth_checked(double py, double pz, do
 // division by c of a tilted axis a product with 1/c.  dr_geometry_init bounds
 // its distance from position_at at every pixel and step (GeomArgs::pos_margin);
 // the kernel takes its floor only where the bound keeps it away from an
-// integer, so bin indices are those of the exact positions.
+// integer, so bin indices are those of the exact positions.  The geometry
+// takes the fast form only when its shortest non-zero step is long against
+// the bound (2^18 times), so that fractions of a step move by less than 2^-26.
 template <bool TILT>
 __device__ __forceinline__ double position_fast(double cy, double cz, double py, double pz,
                                                 double r, double sr, double inv_c, double e0,

@@ -419,18 +419,32 @@ dr_status dr_geometry_init(dr_ctx c, const dr_detector* det, const dr_wire* wire
     if (!row_mode) {
         int sides = 0;  // only the edge sides the passes use
         for (int p = 0; p < g->passes; ++p) sides |= 1 << g->side[p];
-        unsigned long long* d_margin = (unsigned long long*)(wb + w_st + 8);
-        unsigned long long margin_bits = 0;
-        DR_HIP(hipMemsetAsync(d_margin, 0, sizeof(unsigned long long), c->stream));
-        DR_HIP(launch_validate_pixels(ga, sides, d_status, d_margin, c->stream));
+        // [0] the largest fast-position bound, [1] the shortest non-zero step
+        unsigned long long* d_bounds = (unsigned long long*)(wb + w_st + 8);
+        unsigned long long bounds[2] = {0, 0};
+        DR_HIP(hipMemsetAsync(d_bounds, 0, sizeof(unsigned long long), c->stream));
+        // 0x7f in every byte: 1.4e306, above every step
+        DR_HIP(hipMemsetAsync(d_bounds + 1, 0x7f, sizeof(unsigned long long), c->stream));
+        DR_HIP(launch_validate_pixels(ga, sides, d_status, d_bounds, d_bounds + 1, c->stream));
         DR_HIP(hipMemcpyAsync(&status, d_status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-        DR_HIP(hipMemcpyAsync(&margin_bits, d_margin, sizeof(margin_bits), hipMemcpyDeviceToHost,
+        DR_HIP(hipMemcpyAsync(bounds, d_bounds, sizeof(bounds), hipMemcpyDeviceToHost,
                               c->stream));
         DR_HIP(hipStreamSynchronize(c->stream));
-        double margin = 1.0;
-        std::memcpy(&margin, &margin_bits, sizeof(margin));
-        // twice the largest bound; 1 (every position exact) when it is not small
-        ga.pos_margin = (std::isfinite(margin) && margin < 0x1p-12) ? 2.0 * margin : 1.0;
+        double bound = 1.0, min_step = 0.0;
+        std::memcpy(&bound, &bounds[0], sizeof(bound));
+        std::memcpy(&min_step, &bounds[1], sizeof(min_step));
+        // The margin is twice the largest bound, which is 2^9 above the fast
+        // form's error e, so e <= margin * 2^-10.  A fraction (an overlap over
+        // the step's length len, both from fast positions) is then off by at
+        // most 4e / len = margin * 2^-8 / len; steps of at least margin * 2^18
+        // keep that below 2^-26, far under the FP32 accumulation's rounding.
+        // Otherwise (a large bound, or a step too short for it) every
+        // position is evaluated exactly (margin 1).
+        const double margin = 2.0 * bound;
+        ga.pos_margin = (std::isfinite(margin) && margin < 0x1p-12 &&
+                         min_step >= margin * 0x1p18)
+                            ? margin
+                            : 1.0;
         if (status & 1)
             return set_error(DR_E_INVAL, "geometry gives a non-finite depth (pixel inside the "
                                          "wire or a ray parallel to the beam)");
@@ -522,6 +536,13 @@ dr_status dr_geometry_path(dr_geom g, int32_t* path)
 {
     if (!g || !path) return set_error(DR_E_INVAL, "dr_geometry_path: NULL argument");
     *path = g->row_mode ? DR_PATH_ROWS : DR_PATH_PIXELS;
+    return ok();
+}
+
+dr_status dr_geometry_position_margin(dr_geom g, double* margin)
+{
+    if (!g || !margin) return set_error(DR_E_INVAL, "dr_geometry_position_margin: NULL argument");
+    *margin = g->row_mode ? 0.0 : g->g.pos_margin;
     return ok();
 }
 

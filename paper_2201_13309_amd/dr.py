@@ -30,7 +30,7 @@ DR_LAYOUT_FULL, DR_LAYOUT_LIST = 0, 1
 # names exported by libdr.so, as declared in include/dr.h
 ABI_SYMBOLS = (
     "dr_ctx_create", "dr_ctx_destroy", "dr_geometry_init", "dr_geometry_path",
-    "dr_geometry_set_step_weights",
+    "dr_geometry_position_margin", "dr_geometry_set_step_weights",
     "dr_geometry_free", "dr_set_tile",
     "dr_autotune", "dr_reconstruct", "dr_reconstruct_f64", "dr_debug_plan", "dr_enable_timing",
     "dr_last_timing", "dr_batch_create", "dr_batch_run", "dr_batch_tile", "dr_batch_free",
@@ -102,6 +102,7 @@ def load(path: Optional[str] = None):
         "dr_ctx_destroy": [vp],
         "dr_geometry_init": [vp, P(dr_detector), P(dr_wire), P(dr_depth_grid), P(vp)],
         "dr_geometry_path": [vp, P(i32)],
+        "dr_geometry_position_margin": [vp, P(ctypes.c_double)],
         "dr_geometry_set_step_weights": [vp, vp],
         "dr_geometry_free": [vp],
         "dr_set_tile": [vp, P(dr_tile_config)],
@@ -246,6 +247,14 @@ def dr_geometry_path(geom: int) -> int:
     """DR_PATH_ROWS or DR_PATH_PIXELS."""
     v = ctypes.c_int32()
     _check(load().dr_geometry_path(geom, ctypes.byref(v)))
+    return v.value
+
+
+def dr_geometry_position_margin(geom: int) -> float:
+    """Margin of the per-pixel path's fast positions (bin units; >= 1: every
+    position exact; 0: per-row path)."""
+    v = ctypes.c_double()
+    _check(load().dr_geometry_position_margin(geom, ctypes.byref(v)))
     return v.value
 
 

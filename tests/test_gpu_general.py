@@ -99,6 +99,18 @@ def make_case(name):
         c = s.wire.centers
         idx = np.sort(np.concatenate([np.arange(c.shape[0]), [0, 5, 5, 11, c.shape[0] - 1]]))
         s.wire = synth.Wire(s.wire.radius, np.ascontiguousarray(c[idx]))
+    elif name == "tilted_near_repeated":  # wire positions a hair apart: steps of ~1e-7 bins
+        s = synth.tiny(90, 3, 23, 61, seed=215, n_src=6, dark=100.0, render_now=False)
+        _tilted_detector(s, [200.0, 8.0, 28.0])
+        c = s.wire.centers
+        idx = np.sort(np.concatenate([np.arange(c.shape[0]), [2, 9, 9, 16]]))
+        c = c[idx].copy()
+        # each repeat moved 1e-7 um further along the scan (y and z by 1e-7/sqrt(2))
+        rep = np.concatenate([[False], idx[1:] == idx[:-1]])
+        bump = np.cumsum(rep) * rep * (1e-7 / math.sqrt(2.0))
+        c[:, 1] += bump
+        c[:, 2] += bump
+        s.wire = synth.Wire(s.wire.radius, np.ascontiguousarray(c))
     elif name == "tilted_decreasing_repeated":  # backwards, with zero-length steps
         s = synth.tiny(128, 3, 33, 101, seed=212, n_src=8, dark=100.0, render_now=False)
         _tilted_detector(s, [200.0, 0.0, -30.0])
@@ -155,7 +167,8 @@ def make_case(name):
 
 CASES = ["tilted_detector", "axis_xz", "axis_xy", "axis_oblique", "pixel_table_jitter",
          "tilted_non_monotone", "tilted_coarse", "tilted_decreasing", "tilted_many_bins",
-         "tilted_repeated_steps", "tilted_partial_grid", "tilted_decreasing_repeated",
+         "tilted_repeated_steps", "tilted_near_repeated", "tilted_partial_grid",
+         "tilted_decreasing_repeated",
          "pixel_table_mixed_directions", "pixel_table_spread",
          "trailing_tilted_detector",
          "trailing_axis_xz", "both_axis_xy", "both_tilted_non_monotone", "both_axis_oblique"]
@@ -222,6 +235,32 @@ def test_slab_streaming_matches_device(dr, ctx, monkeypatch, name):
         host, tot_h = run_f32(dr, ctx, s, on_device=False)
         assert np.array_equal(host, dev), rows
         assert np.allclose(tot_h, tot_d, rtol=0, atol=1e-5 * max(1.0, np.abs(tot_d).max()))
+
+
+@pytest.mark.parametrize("name", ["tilted_detector", "axis_oblique", "tilted_repeated_steps",
+                                  "tilted_near_repeated"])
+def test_fast_position_margin(dr, ctx, name):
+    """The per-pixel path takes the shorter FP64 form of the positions (with
+    exact bins) where the geometry's margin is small and every non-zero step
+    is at least 2^18 margins long; exact repeats of a wire position (zero
+    steps) keep it, positions a hair apart (steps of ~1e-7 bins) make every
+    position exact.  The other tests hold both forms to the oracle."""
+    s = make_case(name)
+    g = dr.dr_geometry_init(ctx, s.detector, s.wire, s.grid)
+    try:
+        m = dr.dr_geometry_position_margin(g)
+        if name == "tilted_near_repeated":
+            assert m >= 1.0, m
+        else:
+            assert 0.0 < m < 2.0 ** -12, m
+    finally:
+        dr.dr_geometry_free(g)
+    flat = synth.tiny(40, 6, 21, 51, seed=209, n_src=5, dark=100.0)
+    g = dr.dr_geometry_init(ctx, flat.detector, flat.wire, flat.grid)
+    try:
+        assert dr.dr_geometry_position_margin(g) == 0.0  # per-row path
+    finally:
+        dr.dr_geometry_free(g)
 
 
 def test_row_uniform_geometries_keep_row_path(dr, ctx):
