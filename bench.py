@@ -880,12 +880,14 @@ def main():
             result["roofline"]["stream_reference"] = {
                 "op": "hand-written kernel moving the same bytes in the reconstruction's order "
                       "(tiles of 512 pixels walking the 1001 step planes in and bin planes out; "
-                      "a uint16 read and a float written per element, non-temporal), no compute",
+                      "a uint16 read and a float written per element, non-temporal, 16 loads in "
+                      "flight per lane), no compute",
                 "ms": probe["planes"], "GBps": gbps["planes"], "bytes": ref_bytes,
                 "kernel_over_reference": achieved / gbps["planes"],
                 "linear": {"op": "the same bytes in address order (16-byte accesses, grid-stride)",
                            "ms": probe["linear"], "GBps": gbps["linear"]},
-                "read_only": {"op": "the reconstruction-order kernel's reads alone (the stack)",
+                "read_only": {"op": "the reconstruction-order kernel's reads alone (the stack, "
+                                    "16 loads in flight per lane)",
                               "ms": probe["read"], "bytes": dev.numel() * 2},
                 "write_only": {"op": "its writes alone (the output planes)",
                                "ms": probe["write"], "bytes": dev.numel() * 4},

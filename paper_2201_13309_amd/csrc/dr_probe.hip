@@ -31,18 +31,39 @@ __global__ __launch_bounds__(256) void stream_kernel(const u32x4* __restrict__ i
 }
 
 // Same bytes in the reconstruction's order: one workgroup per tile of 512
-// consecutive pixels, 2 per lane, walking all planes (steps in, bins out).
+// consecutive pixels, 2 per lane, walking all planes (steps in, bins out),
+// with kRing loads in flight per lane (a ring consumed in place, as the
+// reconstruction keeps its prefetch): a plain loop has one load in flight and
+// measures the latency, not the memory system.
+constexpr int kRing = 16;
+
 __global__ __launch_bounds__(256) void planes_kernel(const unsigned int* __restrict__ in,
                                                      f32x2* __restrict__ out, int64_t plane2,
                                                      int planes)
 {
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;  // pixel pair
     if (j >= plane2) return;
-    for (int k = 0; k < planes; ++k) {
-        const unsigned int v = __builtin_nontemporal_load(in + (int64_t)k * plane2 + j);
+    auto load = [&](int k) {
+        return __builtin_nontemporal_load(in + (int64_t)min(k, planes - 1) * plane2 + j);
+    };
+    auto store = [&](int k, unsigned int v) {
         const f32x2 o = {(float)(v & 0xffffu), (float)(v >> 16)};
         __builtin_nontemporal_store(o, out + (int64_t)k * plane2 + j);
+    };
+    unsigned int r[kRing];
+#pragma unroll
+    for (int d = 0; d < kRing; ++d) r[d] = load(d);
+    int k = 0;
+    for (; k + kRing <= planes; k += kRing) {
+#pragma unroll
+        for (int d = 0; d < kRing; ++d) {
+            store(k + d, r[d]);
+            r[d] = load(k + d + kRing);
+        }
     }
+#pragma unroll
+    for (int d = 0; d < kRing; ++d)
+        if (k + d < planes) store(k + d, r[d]);
 }
 
 // The two halves of that traffic on their own, same order and access width:
@@ -54,12 +75,28 @@ __global__ __launch_bounds__(256) void planes_read_kernel(const unsigned int* __
 {
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (j >= plane2) return;
+    auto load = [&](int k) {
+        return __builtin_nontemporal_load(in + (int64_t)min(k, planes - 1) * plane2 + j);
+    };
+    unsigned int r[kRing];
+#pragma unroll
+    for (int d = 0; d < kRing; ++d) r[d] = load(d);
     unsigned int a = 0u, b = 0u;
-    for (int k = 0; k < planes; ++k) {
-        const unsigned int v = __builtin_nontemporal_load(in + (int64_t)k * plane2 + j);
-        a += v & 0xffffu;
-        b += v >> 16;
+    int k = 0;
+    for (; k + kRing <= planes; k += kRing) {
+#pragma unroll
+        for (int d = 0; d < kRing; ++d) {
+            a += r[d] & 0xffffu;
+            b += r[d] >> 16;
+            r[d] = load(k + d + kRing);
+        }
     }
+#pragma unroll
+    for (int d = 0; d < kRing; ++d)
+        if (k + d < planes) {
+            a += r[d] & 0xffffu;
+            b += r[d] >> 16;
+        }
     const f32x2 o = {(float)a, (float)b};
     __builtin_nontemporal_store(o, out + j);
 }
