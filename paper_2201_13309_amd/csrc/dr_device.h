@@ -677,6 +677,20 @@ __device__ __forceinline__ void process_tile_mono(const ScanArgs& a, int row,
     // with step k + U.  Steps past the end re-read the last image (unused).
     constexpr int U = PF + 1;
     constexpr int KCU = (CH / U) * U;  // plan chunk, a whole number of rings
+    // Bins outside the row's touched range are zero.  Those on the side where
+    // the walk starts are stored before it, the others after it, so that the
+    // tile's stores run through the bin planes in one direction (0.6% faster
+    // than all after the walk on the 2048^2 x 1001 x 1001 scan).
+    const int blo = a.row_lo[row], bhi = a.row_hi[row];
+    Acc zero[PPL];
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) zero[q] = (Acc)0;
+    if (act && !ADD && blo <= bhi) {
+        if (dir > 0)
+            for (int b = 0; b < blo; ++b) store_bins<Acc, PPL>(outp(b), zero);
+        else
+            for (int b = B - 1; b > bhi; --b) store_bins<Acc, PPL>(outp(b), zero);
+    }
     V ring[U];
 #pragma unroll
     for (int d = 0; d < U; ++d) ring[d] = load(min(d, N - 1));
@@ -703,18 +717,14 @@ __device__ __forceinline__ void process_tile_mono(const ScanArgs& a, int row,
         }
     }
     if (cb >= 0) put();
-    // bins outside the row's touched range are zero; stored after the last load
-    const int blo = a.row_lo[row], bhi = a.row_hi[row];
+    // the other side's zero bins (every bin when the walk touches none)
     if (act && !ADD) {
-        Acc z[PPL];
-#pragma unroll
-        for (int q = 0; q < PPL; ++q) z[q] = (Acc)0;
-        if (blo > bhi) {
-            for (int b = 0; b < B; ++b) store_bins<Acc, PPL>(outp(b), z);
-        } else {
-            for (int b = 0; b < blo; ++b) store_bins<Acc, PPL>(outp(b), z);
-            for (int b = bhi + 1; b < B; ++b) store_bins<Acc, PPL>(outp(b), z);
-        }
+        if (blo > bhi)
+            for (int b = 0; b < B; ++b) store_bins<Acc, PPL>(outp(b), zero);
+        else if (dir > 0)
+            for (int b = bhi + 1; b < B; ++b) store_bins<Acc, PPL>(outp(b), zero);
+        else
+            for (int b = blo - 1; b >= 0; --b) store_bins<Acc, PPL>(outp(b), zero);
     }
     if (pwin.row) pwin.finish(lane);
 }
