@@ -42,31 +42,39 @@ __device__ __forceinline__ double tangent_depth_checked(double py, double pz, do
 // The same position in fewer instructions: the square root and the division
 // each one Newton step after the hardware reciprocal square root and
 // reciprocal (relative errors below 2^-47 instead of correctly rounded), the
-// division by c of a tilted axis a product with 1/c.  dr_geometry_init bounds
+// products and sums fused where one operand is a product (sr*L2 as
+// sr*q + sr*r^2, so that L2 itself is not formed), and the division by c of a
+// tilted axis, the offset and the bin width folded into one fused step.  Every
+// rounding stays of the order of the terms it rounds.  dr_geometry_init bounds
 // its distance from position_at at every pixel and step (GeomArgs::pos_margin);
 // the kernel takes its floor only where the bound keeps it away from an
 // integer, so bin indices are those of the exact positions.  The geometry
 // takes the fast form only when its shortest non-zero step is long against
 // the bound (2^18 times), so that fractions of a step move by less than 2^-26.
-template <bool TILT>
-__device__ __forceinline__ double position_fast(double cy, double cz, double py, double pz,
-                                                double r, double sr, double inv_c, double e0,
-                                                double sinvw)
+struct FastPos {
+    double py, pz;  // the pixel's projected position
+    double sr;      // signed wire radius of the edge
+    double mrr;     // -r^2
+    double srrr;    // sr * r^2
+    double scale;   // sgn / (c * width): bin units, walk direction
+    double offs;    // -e0 * sgn / width
+};
+
+__device__ __forceinline__ double position_fast(double cy, double cz, const FastPos& P)
 {
-    const double ay = cy - py;
-    const double az = cz - pz;
-    const double L2 = az * az + ay * ay;
-    const double q = L2 - r * r;
+    const double ay = cy - P.py;
+    const double az = cz - P.pz;
+    const double q = __builtin_fma(az, az, __builtin_fma(ay, ay, P.mrr));  // L2 - r^2
     const double y = __builtin_amdgcn_rsq(q);
     const double g = q * y, h = y * 0.5;
     const double kk = __builtin_fma(g, __builtin_fma(-h, g, 0.5), g);
-    const double tz = az * kk - ay * sr;
-    const double ty = ay * kk + az * sr;
+    const double tz = __builtin_fma(az, kk, -(ay * P.sr));
+    const double ty = __builtin_fma(ay, kk, az * P.sr);
     const double y0 = __builtin_amdgcn_rcp(ty);
     const double y1 = __builtin_fma(y0, __builtin_fma(-ty, y0, 1.0), y0);
-    const double t = cz - (cy * tz + sr * L2) * y1;
-    const double d = TILT ? t * inv_c : t;
-    return (d - e0) * sinvw;
+    const double num = __builtin_fma(cy, tz, __builtin_fma(P.sr, q, P.srrr));
+    const double t = __builtin_fma(-num, y1, cz);
+    return __builtin_fma(t, P.scale, P.offs);
 }
 
 // Edge position in bin units times `sinvw` = (+-1) / width: the position u,
@@ -271,7 +279,15 @@ __global__ __launch_bounds__(kPixelTile) void pixels_f32_kernel(ScanArgs a, Geom
                                             py, pz, r, sr, c, e0, invw);
     const int dir = (u_last >= u_first) ? 1 : -1;
     const double sgn = (double)dir, sinvw = sgn * invw;
-    const double inv_c = 1.0 / c, margin = g.pos_margin;
+    const double margin = g.pos_margin, half_in = 0.5 - margin;
+    FastPos fp;
+    fp.py = py;
+    fp.pz = pz;
+    fp.sr = sr;
+    fp.mrr = -(r * r);
+    fp.srrr = sr * (r * r);
+    fp.scale = TILT ? sinvw / c : sinvw;
+    fp.offs = -e0 * sinvw;
     const int off = dir > 0 ? 0 : B;
     // |u| < 2^30 and B <= 2^30 (checked when the geometry is built): exact in int
     auto pbin = [&](double v) { return (int)__builtin_floor(v) + off; };
@@ -391,10 +407,11 @@ __global__ __launch_bounds__(kPixelTile) void pixels_f32_kernel(ScanArgs a, Geom
         const double cy = wy, cz = wz;
         wy = wire[2 * (unsigned)(k + 2)];
         wz = wire[2 * (unsigned)(k + 2) + 1];
-        double v_next = position_fast<TILT>(cy, cz, py, pz, r, sr, inv_c, e0, sinvw);
+        double v_next = position_fast(cy, cz, fp);
         double fl = __builtin_floor(v_next);
         const double fr = v_next - fl;  // exact: |v| < 2^30
-        if (!(fr > margin && fr < 1.0 - margin)) {  // near an integer: the exact position
+        // fr within the margin of 0 or 1: the exact position
+        if (!(__builtin_fabs(fr - 0.5) < half_in)) {
             v_next = position_at<TILT>(cy, cz, py, pz, r, sr, c, e0, sinvw);
             fl = __builtin_floor(v_next);
         }
