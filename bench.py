@@ -343,7 +343,7 @@ def run_per_pixel(torch, synth, dr, ctx, s, dev, out, tot, stream, steps: int,
         g = dr.dr_geometry_init(ctx, det, wire, s.grid)
         try:
             assert dr.dr_geometry_path(g) == dr.DR_PATH_PIXELS
-            margin = dr.dr_geometry_position_margin(g)
+            margin, max_err = dr.dr_geometry_position_margin(g)
             dr.dr_reconstruct(g, dev, True, out, tot, stream)
             torch.cuda.synchronize()
             ev0 = torch.cuda.Event(enable_timing=True)
@@ -359,7 +359,7 @@ def run_per_pixel(torch, synth, dr, ctx, s, dev, out, tot, stream, steps: int,
                 dr.dr_reconstruct(g, dev, True, out, tot, stream)
                 kl.append(dr.dr_last_timing(g)[0])
             dr.dr_enable_timing(g, False)
-            return ev0.elapsed_time(ev1) / steps, float(np.mean(kl)), margin
+            return ev0.elapsed_time(ev1) / steps, float(np.mean(kl)), (margin, max_err)
         finally:
             dr.dr_geometry_free(g)
 
@@ -376,10 +376,11 @@ def run_per_pixel(torch, synth, dr, ctx, s, dev, out, tot, stream, steps: int,
            "kernel": "pixels_f32_kernel", "steps": steps,
            "geometry": "detector columns tilted 0.3 deg out of x (u = (200, 0, 1) um): "
                        "positions computed per pixel in FP64 on the fly",
-           "position_margin_bins": m,
+           "position_margin_bins": m[0], "position_max_error_bins": m[1],
            "tilted_axis": {"geometry": "flat detector, wire axis tilted 3 deg towards the beam",
                            "value": work / (ms_axis * 1e-3), "ms_per_step": ms_axis,
-                           "kernel_ms": kms_axis, "position_margin_bins": m_axis}}
+                           "kernel_ms": kms_axis, "position_margin_bins": m_axis[0],
+                           "position_max_error_bins": m_axis[1]}}
     if precision:
         ts = synth.Scan("tilted", det, s.wire, s.grid, None, 0.0, False, 0)
         ts.images = s.images

@@ -188,8 +188,12 @@ dr_status dr_geometry_path(dr_geom geom, int32_t* path);
  * so bins always follow the exact positions.  *margin >= 1 means that every
  * position is evaluated in the exact form (the geometry's bound is not small,
  * or its shortest non-zero step is shorter than 2^18 margins); 0 for the
- * per-row path.  Errors: DR_E_INVAL for NULL arguments. */
-dr_status dr_geometry_position_margin(dr_geom geom, double* margin);
+ * per-row path.  max_error (may be NULL) receives the largest distance
+ * between the two forms that the geometry check found, evaluating both at
+ * every pixel and step it checks (bin units; 0 for the per-row path): the
+ * margin is sound for this geometry while that distance stays below it.
+ * Errors: DR_E_INVAL for NULL geom or margin. */
+dr_status dr_geometry_position_margin(dr_geom geom, double* margin, double* max_error);
 
 /* Free a geometry.  Waits for the device work already enqueued on it.
  * DR_E_BUSY while serving requests that use it are in flight, or while

@@ -173,13 +173,12 @@ hipError_t launch_project_wire(const GeomArgs& g, double* wire_yz, int* d_status
 hipError_t launch_row_uniform(const GeomArgs& g, int* flags, hipStream_t s);
 // per-pixel geometry checks (status bits as in build_plans_kernel)
 // sides: bit 0 leading edge, bit 1 trailing edge (the sides the passes use)
-// margin_bits: the largest fast-position error bound over every pixel and
-// step (bin units, as the bits of a non-negative double; 0 before the launch);
-// min_step_bits: the shortest non-zero step |u_{k+1} - u_k| over every pixel
-// (same form; at least every step before the launch)
+// bounds[3], bin units as the bits of non-negative doubles, over every pixel
+// and step: [0] the largest bound on the fast positions' error (0 before the
+// launch), [1] the shortest non-zero step |u_{k+1} - u_k| (at least every
+// step before the launch), [2] the largest error found (0 before the launch)
 hipError_t launch_validate_pixels(const GeomArgs& g, int sides, int* d_status,
-                                  unsigned long long* margin_bits,
-                                  unsigned long long* min_step_bits, hipStream_t s);
+                                  unsigned long long* bounds, hipStream_t s);
 // per-pixel path: one lane per pixel, positions and bins computed in FP64 on
 // the fly.  side 0/1 = leading/trailing, scale as for the plan tables.
 hipError_t launch_pixels_f32(const ScanArgs& a, const GeomArgs& g, int side, double scale,

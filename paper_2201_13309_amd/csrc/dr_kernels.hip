@@ -2,6 +2,7 @@
 // tables, totals, debug and general-geometry kernels, and the launch wrappers
 // (the row-tile and batch instantiations are in dr_tiles_*.hip).
 #include "dr_device.h"
+#include "dr_fastpos.h"
 
 #include <algorithm>
 
@@ -249,14 +250,13 @@ __global__ __launch_bounds__(256) void row_uniform_kernel(GeomArgs g, int* flags
 // every (pixel, step) of a per-pixel geometry: finite positions on the edge
 // sides in `sides` (bit 0 leading, bit 1 trailing), wire between beam and
 // pixel (status bits 1 and 2 as in build_plans_kernel), |u| < 2^30 (bit 8),
-// the margin within which the per-pixel kernel's fast positions must stay
-// away from an integer (*margin_bits: the largest bound of the pixels) and
-// the shortest step between two positions that differ (*min_step_bits: the
-// smallest |u_{k+1} - u_k| > 0 of the pixels); both as the bits of
-// non-negative doubles, so that unsigned order is numeric order
+// and, as the bits of non-negative doubles (unsigned order is then numeric
+// order): bounds[0] the largest bound on the distance between the per-pixel
+// kernel's fast positions and the exact ones, bounds[1] the shortest step
+// between two positions that differ (the smallest |u_{k+1} - u_k| > 0), and
+// bounds[2] the largest distance actually found between the two forms
 __global__ __launch_bounds__(256) void validate_pixels_kernel(GeomArgs g, int sides, int* status,
-                                                              unsigned long long* margin_bits,
-                                                              unsigned long long* min_step_bits)
+                                                              unsigned long long* bounds)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     // lanes past the last pixel repeat it, so that every lane of the wave
@@ -268,12 +268,23 @@ __global__ __launch_bounds__(256) void validate_pixels_kernel(GeomArgs g, int si
     const double e0 = g.first_center - g.width / 2.0;
     const double invw = 1.0 / g.width;
     const double r = g.radius;
+    // the fast form as the kernel evaluates it, walking upwards (a walk the
+    // other way negates every value, exactly)
+    const bool tilt = g.axis[2] != 0.0;
+    FastPos fp;
+    fp.py = py;
+    fp.pz = pz;
+    fp.mrr = -(r * r);
+    fp.scale = tilt ? invw / f.c : invw;
+    fp.offs = -e0 * invw;
     int bad = 0;
     for (int side = 0; side < 2; ++side) {
         if (!(sides & (1 << side))) continue;
         const int s = side ? -leading_sign(g, py, pz) : leading_sign(g, py, pz);
         const double sr = (double)s * r;
-        double bound = 0.0, min_step = 0x1p1000, u_prev = 0.0;
+        double bound = 0.0, min_step = 0x1p1000, u_prev = 0.0, err = 0.0;
+        fp.sr = sr;
+        fp.srrr = sr * (r * r);
         for (int k = 0; k < g.n_steps; ++k) {
             // the operations of tangent_depth and edge_position, in their
             // order, keeping the parts the bound below needs
@@ -299,6 +310,8 @@ __global__ __launch_bounds__(256) void validate_pixels_kernel(GeomArgs g, int si
                 if (len > 0.0 && len < min_step) min_step = len;
             }
             u_prev = u;
+            const double e = __builtin_fabs(position_fast(cy, cz, fp) - u);
+            if (e > err) err = e;  // NaN (a bad pixel, flagged above) is skipped
             // How far the per-pixel kernel's fast position (one Newton step
             // after the hardware reciprocal square root and reciprocal,
             // relative errors below 2^-47, and 1/c for a tilted axis) can lie
@@ -317,18 +330,23 @@ __global__ __launch_bounds__(256) void validate_pixels_kernel(GeomArgs g, int si
                              __builtin_fabs(f.c) * invw;
             bound = __builtin_isfinite(b) ? __builtin_fmax(bound, b) : 1.0;
         }
-        // the wave's largest bound and shortest step, then one atomic each
+        // the wave's largest bound and error and shortest step, then one
+        // atomic each
         unsigned long long bits = (unsigned long long)__double_as_longlong(bound);
         unsigned long long sbits = (unsigned long long)__double_as_longlong(min_step);
+        unsigned long long ebits = (unsigned long long)__double_as_longlong(err);
         for (int off = 32; off >= 1; off >>= 1) {
             const unsigned long long o = __shfl_xor(bits, off, 64);
             bits = o > bits ? o : bits;
             const unsigned long long so = __shfl_xor(sbits, off, 64);
             sbits = so < sbits ? so : sbits;
+            const unsigned long long eo = __shfl_xor(ebits, off, 64);
+            ebits = eo > ebits ? eo : ebits;
         }
         if ((threadIdx.x & 63) == 0) {
-            atomicMax(margin_bits, bits);
-            atomicMin(min_step_bits, sbits);
+            atomicMax(bounds, bits);
+            atomicMin(bounds + 1, sbits);
+            atomicMax(bounds + 2, ebits);
         }
     }
     for (int k = 0; k < g.n_steps; ++k) {
@@ -496,12 +514,11 @@ hipError_t launch_row_uniform(const GeomArgs& g, int* flags, hipStream_t s)
 }
 
 hipError_t launch_validate_pixels(const GeomArgs& g, int sides, int* d_status,
-                                  unsigned long long* margin_bits,
-                                  unsigned long long* min_step_bits, hipStream_t s)
+                                  unsigned long long* bounds, hipStream_t s)
 {
     const int64_t n = (int64_t)g.nx * g.ny;
     hipLaunchKernelGGL(validate_pixels_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                       g, sides, d_status, margin_bits, min_step_bits);
+                       g, sides, d_status, bounds);
     return hipGetLastError();
 }
 

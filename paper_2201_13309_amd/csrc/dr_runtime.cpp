@@ -419,13 +419,14 @@ dr_status dr_geometry_init(dr_ctx c, const dr_detector* det, const dr_wire* wire
     if (!row_mode) {
         int sides = 0;  // only the edge sides the passes use
         for (int p = 0; p < g->passes; ++p) sides |= 1 << g->side[p];
-        // [0] the largest fast-position bound, [1] the shortest non-zero step
+        // [0] the largest fast-position bound, [1] the shortest non-zero step,
+        // [2] the largest fast-position error found
         unsigned long long* d_bounds = (unsigned long long*)(wb + w_st + 8);
-        unsigned long long bounds[2] = {0, 0};
-        DR_HIP(hipMemsetAsync(d_bounds, 0, sizeof(unsigned long long), c->stream));
+        unsigned long long bounds[3] = {0, 0, 0};
+        DR_HIP(hipMemsetAsync(d_bounds, 0, 3 * sizeof(unsigned long long), c->stream));
         // 0x7f in every byte: 1.4e306, above every step
         DR_HIP(hipMemsetAsync(d_bounds + 1, 0x7f, sizeof(unsigned long long), c->stream));
-        DR_HIP(launch_validate_pixels(ga, sides, d_status, d_bounds, d_bounds + 1, c->stream));
+        DR_HIP(launch_validate_pixels(ga, sides, d_status, d_bounds, c->stream));
         DR_HIP(hipMemcpyAsync(&status, d_status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
         DR_HIP(hipMemcpyAsync(bounds, d_bounds, sizeof(bounds), hipMemcpyDeviceToHost,
                               c->stream));
@@ -433,6 +434,7 @@ dr_status dr_geometry_init(dr_ctx c, const dr_detector* det, const dr_wire* wire
         double bound = 1.0, min_step = 0.0;
         std::memcpy(&bound, &bounds[0], sizeof(bound));
         std::memcpy(&min_step, &bounds[1], sizeof(min_step));
+        std::memcpy(&g->pos_max_error, &bounds[2], sizeof(double));
         // The margin is twice the largest bound, which is 2^9 above the fast
         // form's error e, so e <= margin * 2^-10.  A fraction (an overlap over
         // the step's length len, both from fast positions) is then off by at
@@ -539,10 +541,11 @@ dr_status dr_geometry_path(dr_geom g, int32_t* path)
     return ok();
 }
 
-dr_status dr_geometry_position_margin(dr_geom g, double* margin)
+dr_status dr_geometry_position_margin(dr_geom g, double* margin, double* max_error)
 {
     if (!g || !margin) return set_error(DR_E_INVAL, "dr_geometry_position_margin: NULL argument");
     *margin = g->row_mode ? 0.0 : g->g.pos_margin;
+    if (max_error) *max_error = g->row_mode ? 0.0 : g->pos_max_error;
     return ok();
 }
 

@@ -83,6 +83,9 @@ struct dr_geom_s {
     int side[2] = {0, 0};         // per pass: 0 leading side s_p, 1 trailing side -s_p
     double scale[2] = {1.0, 1.0};  // per pass: factor on every fraction
     dr::GeomArgs g{};
+    // per-pixel path: the largest distance between fast and exact positions
+    // found at init, over every pixel and step of the passes' sides (bins)
+    double pos_max_error = 0.0;
     dr::PlanTables t[2]{};
     // wire: raw and projected centres, status and row flags; pix: explicit
     // pixel centres; plan[p]: all plan tables of pass p in one allocation

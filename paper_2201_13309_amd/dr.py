@@ -102,7 +102,7 @@ def load(path: Optional[str] = None):
         "dr_ctx_destroy": [vp],
         "dr_geometry_init": [vp, P(dr_detector), P(dr_wire), P(dr_depth_grid), P(vp)],
         "dr_geometry_path": [vp, P(i32)],
-        "dr_geometry_position_margin": [vp, P(ctypes.c_double)],
+        "dr_geometry_position_margin": [vp, P(ctypes.c_double), P(ctypes.c_double)],
         "dr_geometry_set_step_weights": [vp, vp],
         "dr_geometry_free": [vp],
         "dr_set_tile": [vp, P(dr_tile_config)],
@@ -250,12 +250,13 @@ def dr_geometry_path(geom: int) -> int:
     return v.value
 
 
-def dr_geometry_position_margin(geom: int) -> float:
-    """Margin of the per-pixel path's fast positions (bin units; >= 1: every
-    position exact; 0: per-row path)."""
-    v = ctypes.c_double()
-    _check(load().dr_geometry_position_margin(geom, ctypes.byref(v)))
-    return v.value
+def dr_geometry_position_margin(geom: int) -> tuple:
+    """(margin, max_error): the margin of the per-pixel path's fast positions
+    (bin units; >= 1: every position exact; 0: per-row path) and the largest
+    distance between fast and exact positions found at init."""
+    v, e = ctypes.c_double(), ctypes.c_double()
+    _check(load().dr_geometry_position_margin(geom, ctypes.byref(v), ctypes.byref(e)))
+    return v.value, e.value
 
 
 def dr_geometry_free(geom: int) -> None:

@@ -56,7 +56,7 @@ def test_null_arguments_rejected_without_device(lib):
     assert lib.dr_reconstruct_list(None, None, 0, 1, None, None, None) == dr.DR_E_INVAL
     assert lib.dr_reconstruct_list_f64(None, None, 0, None, None, None) == dr.DR_E_INVAL
     assert lib.dr_geometry_path(None, None) == dr.DR_E_INVAL
-    assert lib.dr_geometry_position_margin(None, None) == dr.DR_E_INVAL
+    assert lib.dr_geometry_position_margin(None, None, None) == dr.DR_E_INVAL
     assert lib.dr_geometry_set_step_weights(None, None) == dr.DR_E_INVAL
 
 

@@ -168,7 +168,8 @@ def test_config3_sampled_and_invariants(dr, ctx):
 def test_config3_per_pixel_path_sampled(dr, ctx):
     """2048^2 px x 1001 steps x 1001 bins with the detector's columns tilted
     out of the x axis: the per-pixel path, sampled pixels against the oracle
-    (FP32 tolerance, bit-exact positions, bit-exact FP64 instance)."""
+    (FP32 tolerance, bit-exact positions, bit-exact FP64 instance), and the
+    fast positions' largest error, found at init, against their margin."""
     import torch
     s = synth.config3(render_now=False)
     d = s.detector
@@ -180,6 +181,10 @@ def test_config3_per_pixel_path_sampled(dr, ctx):
     g, dev, out, tot = _run_like_bench(dr, ctx, s, host)
     try:
         assert dr.dr_geometry_path(g) == dr.DR_PATH_PIXELS
+        # fast positions in use, and their largest error over all 4.2e9
+        # evaluations well inside the margin that certifies their floors
+        m, err = dr.dr_geometry_position_margin(g)
+        assert 0.0 < m < 2.0 ** -12 and err <= m / 64.0, (m, err)
         assert not torch.isnan(out).any().item(), "unwritten output elements"
         pix = _sample_pixels(nx, ny, 2000, 34)
         ref, bins_ref, u_ref = oracle.reconstruct_pixels(s, pix, want_bins=True, want_u=True)

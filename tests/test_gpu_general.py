@@ -248,17 +248,20 @@ def test_fast_position_margin(dr, ctx, name):
     s = make_case(name)
     g = dr.dr_geometry_init(ctx, s.detector, s.wire, s.grid)
     try:
-        m = dr.dr_geometry_position_margin(g)
+        m, err = dr.dr_geometry_position_margin(g)
         if name == "tilted_near_repeated":
             assert m >= 1.0, m
         else:
             assert 0.0 < m < 2.0 ** -12, m
+        # the two forms evaluated at every pixel and step: the bound holds
+        # with room (it is taken 2^9 above the errors it models)
+        assert 0.0 <= err <= m / 64.0, (err, m)
     finally:
         dr.dr_geometry_free(g)
     flat = synth.tiny(40, 6, 21, 51, seed=209, n_src=5, dark=100.0)
     g = dr.dr_geometry_init(ctx, flat.detector, flat.wire, flat.grid)
     try:
-        assert dr.dr_geometry_position_margin(g) == 0.0  # per-row path
+        assert dr.dr_geometry_position_margin(g) == (0.0, 0.0)  # per-row path
     finally:
         dr.dr_geometry_free(g)
 
