@@ -362,7 +362,9 @@ __global__ __launch_bounds__(kPixelTile) void pixels_f32_kernel(ScanArgs a, Geom
     };
 
     double v_prev = sgn * u_first;
-    int p_prev = pbin(v_prev);
+    // open, and the last position lies in the open bin: true after every
+    // step of the fast form (it keeps the bin open and moves nxt with it)
+    bool ok = false;
     // the wire position of the coming step, loaded one step ahead (the table
     // repeats its last position twice: no clamp)
     double wy = wire[2], wz = wire[3];
@@ -389,7 +391,7 @@ __global__ __launch_bounds__(kPixelTile) void pixels_f32_kernel(ScanArgs a, Geom
         // not depend on the pixels it shares a wave with (a zero-length step
         // of a falling walk is a point mass, whose bin follows the floor of u,
         // not of v: general form)
-        const bool fast = open && p_prev == nxt && (unsigned)d <= 1u && p_next <= B - 1 &&
+        const bool fast = ok && (unsigned)d <= 1u && p_next <= B - 1 &&
                           (dir > 0 || v_next != v_prev);
         if (fast) {
             if (d != 0) {  // the step crosses the open bin's upper boundary bd
@@ -403,10 +405,10 @@ __global__ __launch_bounds__(kPixelTile) void pixels_f32_kernel(ScanArgs a, Geom
         } else {
             const float acc = general(sgn * v_prev, sgn * v_next, (float)dI);
             if (open) clast = ((double)cum + (double)dI) - (double)acc;
+            ok = open && p_next == nxt;
         }
         cum += dI;
         v_prev = v_next;
-        p_prev = p_next;
     };
 
     // ring of U samples: slot k % U holds step k; blocks of U steps
