@@ -323,8 +323,14 @@ __global__ __launch_bounds__(kPixelTile) void pixels_f32_kernel(ScanArgs a, Geom
         woff += ostep;
         ++nxt;
     };
-    // general form of one step over [u_prev, u_next]; returns the open bin's value
-    auto general = [&](double u_prev, double u_next, float dI) {
+    // general form of one step from walk position vp to vn; returns the open
+    // bin's value
+    auto general = [&](double vp, double vn, float dI) {
+        // The natural positions and their floors are formed here only: the
+        // empty statement keeps the compiler from computing them ahead of the
+        // branch on every step, where the fast form has no use for them.
+        asm volatile("" : "+v"(vp), "+v"(vn));
+        const double u_prev = sgn * vp, u_next = sgn * vn;
         float acc = open ? (float)((double)cum - clast) : 0.0f;
         auto bin = [&](int p, float fr) {
             if (open && p == nxt) {
@@ -376,9 +382,14 @@ __global__ __launch_bounds__(kPixelTile) void pixels_f32_kernel(ScanArgs a, Geom
         double fl = __builtin_floor(v_next);
         const double fr = v_next - fl;  // exact: |v| < 2^30
         // fr within the margin of 0 or 1: the exact position
+        bool zero_int = false;
         if (!(__builtin_fabs(fr - 0.5) < half_in)) {
             v_next = position_at<TILT>(cy, cz, py, pz, r, sr, c, e0, sinvw);
             fl = __builtin_floor(v_next);
+            // a zero-length step of a falling walk is a point mass in bin
+            // floor(u), which is floor(v)'s bin unless u is an integer (then
+            // the general form): such a position is always evaluated here
+            zero_int = dir < 0 && v_next == v_prev;
         }
         const int p_next = (int)fl + off;
         Cum dI;  // this step's intensity difference (unscaled)
@@ -388,11 +399,8 @@ __global__ __launch_bounds__(kPixelTile) void pixels_f32_kernel(ScanArgs a, Geom
             dI = s0 - s1;
         const int d = p_next - nxt;
         // chosen per lane from its own walk alone, so that a pixel's values do
-        // not depend on the pixels it shares a wave with (a zero-length step
-        // of a falling walk is a point mass, whose bin follows the floor of u,
-        // not of v: general form)
-        const bool fast = ok && (unsigned)d <= 1u && p_next <= B - 1 &&
-                          (dir > 0 || v_next != v_prev);
+        // not depend on the pixels it shares a wave with
+        const bool fast = ok && (unsigned)d <= 1u && p_next <= B - 1 && !zero_int;
         if (fast) {
             if (d != 0) {  // the step crosses the open bin's upper boundary bd
                 const double bd = (double)(p_next - off);
@@ -403,7 +411,7 @@ __global__ __launch_bounds__(kPixelTile) void pixels_f32_kernel(ScanArgs a, Geom
                 clast = cb;
             }
         } else {
-            const float acc = general(sgn * v_prev, sgn * v_next, (float)dI);
+            const float acc = general(v_prev, v_next, (float)dI);
             if (open) clast = ((double)cum + (double)dI) - (double)acc;
             ok = open && p_next == nxt;
         }
