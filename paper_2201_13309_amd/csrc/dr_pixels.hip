@@ -159,8 +159,9 @@ __device__ __forceinline__ int wave_min(int v)
 // dI_k (bd - v_k) / (v_{k+1} - v_k).  A step that stays inside the open bin
 // costs one integer add; one that crosses bd costs one FP64 fma and stores
 // the closed bin.  The values differ from the per-step sums only by rounding:
-// the fraction carries an FP32 reciprocal of the length (relative error
-// 2^-23), each C one FP64 rounding, the stored difference one FP32 rounding.
+// the fraction carries the hardware FP64 reciprocal of the length (relative
+// error about 2^-24), each C one FP64 rounding, the stored difference one
+// FP32 rounding.
 //
 // General form, for any other step (entering or leaving the grid, more than
 // one boundary in a step, a walk that turns back): the interval's bins and
@@ -402,9 +403,9 @@ __global__ __launch_bounds__(kPixelTile) void pixels_f32_kernel(ScanArgs a, Geom
         // not depend on the pixels it shares a wave with
         const bool fast = ok && (unsigned)d <= 1u && p_next <= B - 1 && !zero_int;
         if (fast) {
-            if (d != 0) {  // the step crosses the open bin's upper boundary bd
-                const double bd = (double)(p_next - off);
-                const double rl = (double)__builtin_amdgcn_rcpf((float)(v_next - v_prev));
+            if (d != 0) {  // the step crosses the open bin's upper boundary bd = fl
+                const double rl = __builtin_amdgcn_rcp(v_next - v_prev);  // ~2^-24 relative
+                const double bd = fl;
                 const double cb = __builtin_fma((bd - v_prev) * rl, (double)dI, (double)cum);
                 emit((float)(cb - clast));
                 if (ADD && act) prev = op[woff];
