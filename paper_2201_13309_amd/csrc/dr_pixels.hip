@@ -217,6 +217,7 @@ __global__ __launch_bounds__(kPixelTile) void pixels_f32_kernel(ScanArgs a, Geom
     float* const gp = tot ? (float*)a.partials + slot * B : nullptr;
     const bool in_lds = pixel_totals_in_lds(B);
     float* const ring = reinterpret_cast<float*>(dyn_lds) + wave * (kRingBins * 64);
+    float* const ring_lane = ring + lane;  // this lane's slot of ring bin 0
     float* const trows = reinterpret_cast<float*>(dyn_lds + kRingBytes);
     float* const wrow = trows + wave * B;
     if (tot) {
@@ -272,7 +273,7 @@ __global__ __launch_bounds__(kPixelTile) void pixels_f32_kernel(ScanArgs a, Geom
     auto put_total = [&](int p, float v) {  // this lane closed bin p with value v
         if (!tot || !act) return;
         if (ring_on && (unsigned)(p - F) < (unsigned)kRingBins)
-            ring[(p & (kRingBins - 1)) * 64 + lane] = v;
+            ring_lane[(p & (kRingBins - 1)) * 64] = v;
         else
             atomic_total(nat(p), v);
     };
@@ -311,7 +312,7 @@ __global__ __launch_bounds__(kPixelTile) void pixels_f32_kernel(ScanArgs a, Geom
     }
 
     int nxt = 0;  // first bin (walk order) not stored
-    int64_t woff = dir > 0 ? 0 : (int64_t)(B - 1) * plane;  // element offset of bin nxt
+    float* on = op + (dir > 0 ? 0 : (int64_t)(B - 1) * plane);  // the lane's element of bin nxt
     bool open = false;
     double clast = 0.0;  // when open: mass below the open bin (unscaled)
     Cum cum = 0;         // mass of the steps so far (unscaled)
@@ -319,9 +320,9 @@ __global__ __launch_bounds__(kPixelTile) void pixels_f32_kernel(ScanArgs a, Geom
     // store the open bin with this pass's value v (unscaled); move to the next
     auto emit = [&](float v) {
         v *= scale;
-        if (act) stream_store(ADD ? prev + v : v, op + woff);
+        if (act) stream_store(ADD ? prev + v : v, on);
         put_total(nxt, v);
-        woff += ostep;
+        on += ostep;
         ++nxt;
     };
     // general form of one step from walk position vp to vn; returns the open
@@ -341,9 +342,9 @@ __global__ __launch_bounds__(kPixelTile) void pixels_f32_kernel(ScanArgs a, Geom
                     emit(acc);
                     open = false;
                 }
-                for (; nxt < p; ++nxt, woff += ostep)
-                    if (!ADD && act) stream_store(0.0f, op + woff);
-                if (ADD && act) prev = op[woff];
+                for (; nxt < p; ++nxt, on += ostep)
+                    if (!ADD && act) stream_store(0.0f, on);
+                if (ADD && act) prev = *on;
                 acc = fr * dI;
                 open = true;
             } else if (act) {  // stored already: read, add, rewrite
@@ -408,7 +409,7 @@ __global__ __launch_bounds__(kPixelTile) void pixels_f32_kernel(ScanArgs a, Geom
                 const double bd = fl;
                 const double cb = __builtin_fma((bd - v_prev) * rl, (double)dI, (double)cum);
                 emit((float)(cb - clast));
-                if (ADD && act) prev = op[woff];
+                if (ADD && act) prev = *on;
                 clast = cb;
             }
         } else {
@@ -449,8 +450,8 @@ __global__ __launch_bounds__(kPixelTile) void pixels_f32_kernel(ScanArgs a, Geom
         open = false;
     }
     if (!ADD)
-        for (; nxt < B; ++nxt, woff += ostep)
-            if (act) stream_store(0.0f, op + woff);
+        for (; nxt < B; ++nxt, on += ostep)
+            if (act) stream_store(0.0f, on);
     if (tot && in_lds) {
         if (ring_on) flush(B);
         __syncthreads();
