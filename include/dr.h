@@ -185,14 +185,14 @@ dr_status dr_geometry_path(dr_geom geom, int32_t* path);
  * of the shorter FP64 form (hardware reciprocal square root and reciprocal,
  * each refined by one Newton step) must not come to an integer for its floor
  * to be taken as the bin; closer positions are evaluated in the exact form,
- * so bins always follow the exact positions.  *margin >= 1 means that every
- * position is evaluated in the exact form (the geometry's bound is not small,
- * or its shortest non-zero step is shorter than 2^18 margins); 0 for the
- * per-row path.  max_error (may be NULL) receives the largest distance
- * between the two forms that the geometry check found, evaluating both at
- * every pixel and step it checks (bin units; 0 for the per-row path): the
- * margin is sound for this geometry while that distance stays below it.
- * Errors: DR_E_INVAL for NULL geom or margin. */
+ * so bins always follow the exact positions.  max_error (may be NULL)
+ * receives the largest distance between the two forms, which the geometry
+ * check finds by evaluating both at every pixel and step the kernel
+ * evaluates (bin units; 0 for the per-row path).  The shorter form is used
+ * only while that distance is below half the margin and every non-zero step
+ * is at least 2^28 times it long; otherwise, or when the geometry's bound is
+ * not small, *margin >= 1 and every position is evaluated in the exact form.
+ * 0 for the per-row path.  Errors: DR_E_INVAL for NULL geom or margin. */
 dr_status dr_geometry_position_margin(dr_geom geom, double* margin, double* max_error);
 
 /* Free a geometry.  Waits for the device work already enqueued on it.

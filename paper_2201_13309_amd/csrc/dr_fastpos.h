@@ -13,11 +13,12 @@ namespace dr {
 // sr*q + sr*r^2, so that L2 itself is not formed), and the division by c of a
 // tilted axis, the offset and the bin width folded into one fused step.  Every
 // rounding stays of the order of the terms it rounds.  dr_geometry_init bounds
-// its distance from position_at at every pixel and step (GeomArgs::pos_margin);
-// the kernel takes its floor only where the bound keeps it away from an
-// integer, so bin indices are those of the exact positions.  The geometry
-// takes the fast form only when its shortest non-zero step is long against
-// the bound (2^18 times), so that fractions of a step move by less than 2^-26.
+// its distance from position_at at every pixel and step (GeomArgs::pos_margin)
+// and also evaluates it there, finding its largest actual distance e; the
+// kernel takes its floor only where the margin keeps it away from an integer,
+// and the geometry takes the fast form only when e is below half the margin,
+// so bin indices are those of the exact positions, and when its shortest
+// non-zero step is at least 2^28 e, so that fractions move by less than 2^-26.
 struct FastPos {
     double py, pz;  // the pixel's projected position
     double sr;      // signed wire radius of the edge

@@ -435,16 +435,21 @@ dr_status dr_geometry_init(dr_ctx c, const dr_detector* det, const dr_wire* wire
         std::memcpy(&bound, &bounds[0], sizeof(bound));
         std::memcpy(&min_step, &bounds[1], sizeof(min_step));
         std::memcpy(&g->pos_max_error, &bounds[2], sizeof(double));
-        // The margin is twice the largest bound, which is 2^9 above the fast
-        // form's error e, so e <= margin * 2^-10.  A fraction (an overlap over
-        // the step's length len, both from fast positions) is then off by at
-        // most 4e / len = margin * 2^-8 / len; steps of at least margin * 2^18
-        // keep that below 2^-26, far under the FP32 accumulation's rounding.
-        // Otherwise (a large bound, or a step too short for it) every
+        // The margin is twice the largest bound (taken 2^9 above the errors
+        // it models).  The check has also evaluated the fast form itself at
+        // every pixel and step the kernel will evaluate, with the same
+        // operations on the same inputs, so its largest error e is exact for
+        // this geometry, not an estimate: e < margin / 2 makes every floor the
+        // kernel takes from a fast position (one at least a margin away from
+        // an integer) the exact position's floor.  A fraction (an overlap over
+        // the step's length len, both ends within e) moves by at most
+        // 4e / len; steps of at least 2^28 e keep that below 2^-26, far under
+        // the FP32 accumulation's rounding.  Otherwise (a large bound, an
+        // error not well inside it, or a step too short for it) every
         // position is evaluated exactly (margin 1).
-        const double margin = 2.0 * bound;
-        ga.pos_margin = (std::isfinite(margin) && margin < 0x1p-12 &&
-                         min_step >= margin * 0x1p18)
+        const double margin = 2.0 * bound, e = g->pos_max_error;
+        ga.pos_margin = (std::isfinite(margin) && margin < 0x1p-12 && e < 0.5 * margin &&
+                         min_step >= e * 0x1p28)
                             ? margin
                             : 1.0;
         if (status & 1)

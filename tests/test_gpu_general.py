@@ -241,10 +241,12 @@ def test_slab_streaming_matches_device(dr, ctx, monkeypatch, name):
                                   "tilted_near_repeated"])
 def test_fast_position_margin(dr, ctx, name):
     """The per-pixel path takes the shorter FP64 form of the positions (with
-    exact bins) where the geometry's margin is small and every non-zero step
-    is at least 2^18 margins long; exact repeats of a wire position (zero
-    steps) keep it, positions a hair apart (steps of ~1e-7 bins) make every
-    position exact.  The other tests hold both forms to the oracle."""
+    exact bins) where the geometry's margin is small, the form's largest
+    error (found at init over every pixel and step) is below half of it and
+    every non-zero step is at least 2^28 times that error long; exact repeats
+    of a wire position (zero steps) keep it, positions a hair apart (steps of
+    ~1e-7 bins) make every position exact.  The other tests hold both forms
+    to the oracle."""
     s = make_case(name)
     g = dr.dr_geometry_init(ctx, s.detector, s.wire, s.grid)
     try:
