@@ -8,11 +8,13 @@
 // (Sec. III-C: each pixel's differences are added into depth arrays).
 //
 //   pixels_f32_kernel  FP32 accumulation.  ALU-bound: per (pixel, step) one
-//                      FP64 square root and one FP64 division; a step inside
-//                      one bin costs an integer add, a step across a bin
-//                      boundary one FP32 reciprocal and one FP64 fma; wire
-//                      positions come through scalar loads; totals are summed
-//                      in a fixed order through per-wave LDS rings.
+//                      FP64 square root and one FP64 division, in a shorter
+//                      form (dr_fastpos.h) whose floors are certified at
+//                      init, exact where they are not; a step inside one bin
+//                      costs an integer add, a step across a bin boundary one
+//                      FP64 reciprocal and one FP64 fma; wire positions come
+//                      through scalar loads; totals are summed in a fixed
+//                      order through per-wave LDS rings.
 //   pixels_kernel      FP64 instance (validation): each overlap divided by the
 //                      length in FP64, the oracle's order of accumulation.
 #include <type_traits>
