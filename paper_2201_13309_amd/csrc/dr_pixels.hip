@@ -314,7 +314,9 @@ __global__ __launch_bounds__(kPixelTile) void pixels_f32_kernel(ScanArgs a, Geom
     }
 
     int nxt = 0;  // first bin (walk order) not stored
-    float* on = op + (dir > 0 ? 0 : (int64_t)(B - 1) * plane);  // the lane's element of bin nxt
+    // the lane's element of bin nxt; after the last bin it is moved once more
+    // and never used again (an integer address instead measured 6% slower)
+    float* on = op + (dir > 0 ? 0 : (int64_t)(B - 1) * plane);
     bool open = false;
     double clast = 0.0;  // when open: mass below the open bin (unscaled)
     Cum cum = 0;         // mass of the steps so far (unscaled)
