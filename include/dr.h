@@ -252,6 +252,10 @@ dr_status dr_reconstruct_f64(dr_geom geom, const uint16_t* images_dev, double* o
  * one GPU shares that GPU's array, so calls whose work overlaps in time on one
  * GPU (other streams, other host threads) race and must be serialized by the
  * caller; each call writes every scratch element it reads before reading it.
+ * The array holds the totals scratch of a 2048 x 2048 scan with 1001 bins
+ * and one edge on the per-row path; per-pixel geometries need five rows of
+ * n_bins floats per 256 pixels, so a per-pixel 2048 x 2048 scan with totals
+ * does not fit.
  * Errors: DR_E_INVAL for NULL or misaligned pointers, and for a scan whose
  * totals need more scratch than the array holds (the message gives both
  * sizes; pass totals = NULL, which needs none, or use dr_reconstruct);

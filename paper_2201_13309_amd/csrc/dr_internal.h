@@ -186,8 +186,12 @@ hipError_t launch_pixels_f32(const ScanArgs& a, const GeomArgs& g, int side, dou
 hipError_t launch_pixels_f64(const ScanArgs& a, const GeomArgs& g, int side, double scale,
                              hipStream_t s);
 constexpr int kPixelTile = 256;  // pixels per workgroup of the per-pixel path
-// largest partial-total row the per-pixel path sums in LDS (larger rows are
-// summed with device atomics in the partials buffer itself)
+// partial-total rows per workgroup of the per-pixel FP32 path: one per wave
+// (its ring sums, each bin written once) and one for the closes that fall
+// outside a ring (device atomics)
+constexpr int kPixelPartialRows = kPixelTile / 64 + 1;
+// largest partial-total row the FP64 per-pixel instance sums in LDS (larger
+// rows are summed with device atomics in the partials buffer itself)
 constexpr size_t kPixelLdsBytes = 64 * 1024;
 
 // Top-k selection state, kept on the device between the radix passes:

@@ -110,6 +110,25 @@ __global__ void reset_counter_kernel(unsigned long long* c) { *c = 0ull; }
 
 // ------------------------------------------------------------------ totals
 
+// Rows sl, sl + step, ... (below slots) of column b, added in that order;
+// eight loads are issued before their adds, so a thread does not wait for
+// each row in turn (the sum is the same, in the same order).
+template <typename T>
+__device__ __forceinline__ double column_sum(const T* part, int64_t sl, int64_t slots,
+                                             int64_t step, int B, int b)
+{
+    double s = 0.0;
+    for (; sl + 7 * step < slots; sl += 8 * step) {
+        T v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = part[(sl + i * step) * B + b];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) s += (double)v[i];
+    }
+    for (; sl < slots; sl += step) s += (double)part[sl * B + b];
+    return s;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void totals_stage1(const T* part, int64_t slots, int B,
                                                      double* work)
@@ -117,10 +136,9 @@ __global__ __launch_bounds__(256) void totals_stage1(const T* part, int64_t slot
     __shared__ double red[4][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int b = blockIdx.x * 64 + lane;
-    double s = 0.0;
-    if (b < B)
-        for (int64_t sl = (int64_t)blockIdx.y * 4 + w; sl < slots; sl += (int64_t)gridDim.y * 4)
-            s += (double)part[sl * B + b];
+    const double s =
+        b < B ? column_sum(part, (int64_t)blockIdx.y * 4 + w, slots, (int64_t)gridDim.y * 4, B, b)
+              : 0.0;
     red[w][lane] = s;
     __syncthreads();
     if (w == 0 && b < B)
@@ -143,10 +161,9 @@ __global__ __launch_bounds__(256) void totals_multi_stage1(const TotalsJob* jobs
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int b = ((int)blockIdx.x - jb.first1) * 64 + lane;
     const int B = jb.n_bins;
-    double s = 0.0;
-    if (b < B)
-        for (int64_t sl = (int64_t)blockIdx.y * 4 + w; sl < jb.slots; sl += (int64_t)gridDim.y * 4)
-            s += (double)jb.parts[sl * B + b];
+    const double s = b < B ? column_sum(jb.parts, (int64_t)blockIdx.y * 4 + w, jb.slots,
+                                        (int64_t)gridDim.y * 4, B, b)
+                           : 0.0;
     red[w][lane] = s;
     __syncthreads();
     if (w == 0 && b < B)

@@ -104,7 +104,12 @@ static ListArgs list_args(const dr_list l, int32_t compact)
 
 // workgroups of one pass, and partial-total rows of one pass
 static int64_t list_groups(const dr_list l) { return l->n_tiles; }
-static int64_t list_slots(const dr_list l) { return l->n_tiles; }  // one row per (wave) tile
+// partial-total rows of one pass: one per wave tile on the row path,
+// kPixelPartialRows per tile on the per-pixel path
+static int64_t list_slots(const dr_list l)
+{
+    return l->n_tiles * (l->g->row_mode ? 1 : kPixelPartialRows);
+}
 
 // Scan arguments of pass p over a list: images img (full frames: step stride
 // nx*ny; compact: step stride `img_step` entries), output [n_bins][n].

@@ -102,25 +102,23 @@ __device__ __forceinline__ PlanF plan_f32(double u0, double u1, double fl0, doub
 }
 
 constexpr int kPixelWaves = kPixelTile / 64;
-static_assert(kPixelWaves == 4, "the per-workgroup totals add four wave rows");
+static_assert(kPixelPartialRows == kPixelWaves + 1, "a partial row per wave, one for atomics");
 
 // Totals of the FP32 kernel, summed in a fixed order.  Each wave owns a ring
 // of kRingBins bins x 64 lanes in LDS: the lane that closes bin p (counted in
 // its walk direction) writes its value into slot (p mod kRingBins, lane)
 // while p lies in the ring's window [F, F + kRingBins).  At the start of each
 // block of steps the bins below the wave's lowest open bin are complete; each
-// is summed over the 64 lanes in a fixed tree into the wave's own totals row,
-// and the window moves up.  At the end the workgroup adds its four rows in
-// wave order.  A close outside the window (a walk that turns back, lanes of
-// one wave far apart, lanes walking opposite ways) adds into the wave's row
-// with an LDS atomic instead.
+// is summed over the 64 lanes in a fixed tree and stored into the wave's own
+// partial row in device memory (every bin of that row is written once: a sum,
+// or zero for a bin the window never held), and the window moves up.  A
+// close outside the window (a walk that turns back, lanes of one wave far
+// apart, lanes walking opposite ways) adds into the workgroup's fifth row
+// with a device atomic instead; only those closes are order-dependent.  The
+// rows live in device memory rather than LDS so that the LDS of a workgroup
+// is its four rings alone, and six waves fit on a SIMD.
 constexpr int kRingBins = 16;
 constexpr size_t kRingBytes = (size_t)kPixelWaves * kRingBins * 64 * sizeof(float);
-
-__host__ __device__ constexpr bool pixel_totals_in_lds(int B)
-{
-    return kRingBytes + (size_t)kPixelWaves * (size_t)B * sizeof(float) <= kPixelLdsBytes;
-}
 
 // v from the DPP source lane; lanes without one (or in rows outside ROW_MASK)
 // keep their own v
@@ -177,7 +175,9 @@ __device__ __forceinline__ int wave_min(int v)
 // two-edge reconstruction (ADD), whose values are added onto the first
 // pass's.  Values are scaled (by +-1 or +-1/2, exactly) as they are stored.
 template <int PF, bool NORM, bool TILT, bool ADD>
-__global__ __launch_bounds__(kPixelTile) void pixels_f32_kernel(ScanArgs a, GeomArgs g, int side,
+// Six waves per SIMD (at most 80 VGPRs; the compiler spills one register of
+// the main instance): 7% faster than five.
+__global__ __launch_bounds__(kPixelTile, 6) void pixels_f32_kernel(ScanArgs a, GeomArgs g, int side,
                                                                 float scale, ListArgs l)
 {
     using Cum = typename std::conditional<NORM, double, int>::type;
@@ -214,22 +214,18 @@ __global__ __launch_bounds__(kPixelTile) void pixels_f32_kernel(ScanArgs a, Geom
         op = (float*)a.out + (int64_t)row * a.nx + col;
         slot = (int64_t)row * a.tiles_per_row + tile;
     }
-    // totals: the rings and the four wave rows in LDS, or, for rows too long
-    // for LDS, device atomics into the workgroup's row of the partials buffer
-    float* const gp = tot ? (float*)a.partials + slot * B : nullptr;
-    const bool in_lds = pixel_totals_in_lds(B);
+    // totals: the wave's ring in LDS, its partial row and the workgroup's
+    // atomics row in the partials buffer (kPixelPartialRows per workgroup)
+    float* const gbase = tot ? (float*)a.partials + slot * kPixelPartialRows * B : nullptr;
+    const int uwave = __builtin_amdgcn_readfirstlane(wave);  // uniform: a scalar row base
+    float* const gw = tot ? gbase + (int64_t)uwave * B : nullptr;
+    float* const gp = tot ? gbase + (int64_t)kPixelWaves * B : nullptr;
     float* const ring = reinterpret_cast<float*>(dyn_lds) + wave * (kRingBins * 64);
     float* const ring_lane = ring + lane;  // this lane's slot of ring bin 0
-    float* const trows = reinterpret_cast<float*>(dyn_lds + kRingBytes);
-    float* const wrow = trows + wave * B;
     if (tot) {
-        if (in_lds) {  // each wave clears its own ring and row
-            for (int i = lane; i < kRingBins * 64; i += 64) ring[i] = 0.0f;
-            for (int b = lane; b < B; b += 64) wrow[b] = 0.0f;
-        } else {
-            for (int b = tid; b < B; b += kPixelTile) gp[b] = 0.0f;
-            __syncthreads();  // cleared before any wave adds
-        }
+        for (int i = lane; i < kRingBins * 64; i += 64) ring[i] = 0.0f;
+        for (int b = tid; b < B; b += kPixelTile) gp[b] = 0.0f;
+        __syncthreads();  // cleared before any wave adds
     }
 
     const Frame f = axis_frame(g);
@@ -260,17 +256,14 @@ __global__ __launch_bounds__(kPixelTile) void pixels_f32_kernel(ScanArgs a, Geom
     auto pbin = [&](double v) { return (int)__builtin_floor(v) + off; };
     const bool up_w = __all(dir > 0), down_w = __all(dir < 0);  // wave-uniform
     const bool uni = up_w || down_w;
-    const bool ring_on = tot && in_lds && uni;
+    const bool ring_on = tot && uni;
     const int64_t plane = a.out_plane;
     const int64_t ostep = dir > 0 ? plane : -plane;
     auto nat = [&](int p) { return dir > 0 ? p : B - 1 - p; };
 
     int F = 0;  // the ring's window [F, F + kRingBins) (wave-uniform)
     auto atomic_total = [&](int b, float v) {  // b: natural bin
-        if (in_lds)
-            __hip_atomic_fetch_add(&wrow[b], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        else
-            __hip_atomic_fetch_add(&gp[b], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&gp[b], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     };
     auto put_total = [&](int p, float v) {  // this lane closed bin p with value v
         if (!tot || !act) return;
@@ -281,7 +274,8 @@ __global__ __launch_bounds__(kPixelTile) void pixels_f32_kernel(ScanArgs a, Geom
     };
     // bins [F, upto) are complete for every lane of the wave: sum their ring
     // slots over the lanes (16 lanes per quarter in order, then the quarters
-    // pairwise) into the wave's row, clear them, and move the window
+    // pairwise) into the wave's row, clear them, and move the window; bins of
+    // [F, upto) beyond the window were never held: zero in the row
     auto flush = [&](int upto) {
         const int n = min(upto, F + kRingBins) - F;
         if (n > 0) {
@@ -303,15 +297,17 @@ __global__ __launch_bounds__(kPixelTile) void pixels_f32_kernel(ScanArgs a, Geom
             v += __shfl_xor(v, 32, 64);
             if (q == 0 && si < n) {
                 const int p = F + si;
-                wrow[up_w ? p : B - 1 - p] += v;
+                gw[up_w ? p : B - 1 - p] = v;
             }
         }
+        for (int p = F + kRingBins + lane; p < upto; p += 64) gw[up_w ? p : B - 1 - p] = 0.0f;
         F = max(F, upto);
     };
     if (ring_on) {  // start the window just below the lowest first bin of the wave
         const int p0 = min(max(pbin(sgn * u_first), 0), B);
         F = max(0, wave_min(act ? p0 : B) - 1);
     }
+    const int F0 = F;  // bins below it (walk order) are never held: zero in the row
 
     int nxt = 0;  // first bin (walk order) not stored
     // the lane's element of bin nxt; after the last bin it is moved once more
@@ -456,11 +452,13 @@ __global__ __launch_bounds__(kPixelTile) void pixels_f32_kernel(ScanArgs a, Geom
     if (!ADD)
         for (; nxt < B; ++nxt, on += ostep)
             if (act) stream_store(0.0f, on);
-    if (tot && in_lds) {
-        if (ring_on) flush(B);
-        __syncthreads();
-        for (int b = tid; b < B; b += kPixelTile)
-            gp[b] = ((trows[b] + trows[B + b]) + trows[2 * B + b]) + trows[3 * B + b];
+    if (tot) {  // complete the wave's row: every bin written once
+        if (ring_on) {
+            flush(B);
+            for (int p = lane; p < F0; p += 64) gw[up_w ? p : B - 1 - p] = 0.0f;
+        } else {
+            for (int b = lane; b < B; b += 64) gw[b] = 0.0f;
+        }
     }
 }
 
@@ -621,9 +619,7 @@ static hipError_t launch_pixels(const ScanArgs& a, const GeomArgs& g, int side, 
     size_t lds = 0;
     if (a.partials) {
         if (sizeof(Acc) == 4)
-            lds = pixel_totals_in_lds(a.n_bins)
-                      ? kRingBytes + (size_t)kPixelWaves * a.n_bins * sizeof(float)
-                      : 0;
+            lds = kRingBytes;
         else
             lds = (size_t)a.n_bins * sizeof(Acc) <= kPixelLdsBytes ? (size_t)a.n_bins * sizeof(Acc)
                                                                     : 0;

@@ -67,8 +67,10 @@ static int tiles_per_row(const dr_geom g, const TileCfg& t)
 
 int64_t partial_slots(const dr_geom g, const TileCfg& t)
 {
-    // per-pixel path: one partial row per workgroup
-    return (int64_t)g->ny * tiles_per_row(g, t) * (g->row_mode ? t.waves : 1);
+    // row path: one partial row per wave; per-pixel path: kPixelPartialRows
+    // per workgroup of the FP32 kernel (the FP64 instance takes its totals
+    // from its finished output)
+    return (int64_t)g->ny * tiles_per_row(g, t) * (g->row_mode ? t.waves : kPixelPartialRows);
 }
 
 ScanArgs scan_args(const dr_geom g, const TileCfg& t, int pass, const uint16_t* img,
