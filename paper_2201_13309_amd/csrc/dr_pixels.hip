@@ -29,14 +29,15 @@ namespace dr {
 // tangent_depth for the per-pixel kernels: the square root always in its
 // Newton form.  dr_geometry_init checks for these geometries that
 // L2 - r^2 >= 2^-767 at every pixel and wire step, where the Newton form and
-// the guarded one in tangent_depth give the same bits.
+// the guarded one in tangent_depth give the same bits.  rr is the product
+// r * r.
 __device__ __forceinline__ double tangent_depth_checked(double py, double pz, double cy,
-                                                       double cz, double r, double sr)
+                                                       double cz, double rr, double sr)
 {
     const double ay = cy - py;
     const double az = cz - pz;
     const double L2 = az * az + ay * ay;
-    const double kk = sqrt_newton(L2 - r * r);
+    const double kk = sqrt_newton(L2 - rr);
     const double tz = az * kk - ay * sr;
     const double ty = ay * kk + az * sr;
     return cz - (cy * tz + sr * L2) / ty;
@@ -45,13 +46,14 @@ __device__ __forceinline__ double tangent_depth_checked(double py, double pz, do
 // Edge position in bin units times `sinvw` = (+-1) / width: the position u,
 // or -u for a walk that runs the other way (exact: a sign); TILT: the wire
 // axis has a z component, so the tangent point's xi is divided by c = e1.z;
-// otherwise c is exactly 1 and the division (t / 1 == t) is left out.
+// otherwise c is exactly 1 and the division (t / 1 == t) is left out.  rr is
+// the product r * r.
 template <bool TILT>
 __device__ __forceinline__ double position_at(double cy, double cz, double py, double pz,
-                                              double r, double sr, double c, double e0,
+                                              double rr, double sr, double c, double e0,
                                               double sinvw)
 {
-    const double t = tangent_depth_checked(py, pz, cy, cz, r, sr);
+    const double t = tangent_depth_checked(py, pz, cy, cz, rr, sr);
     const double d = TILT ? t / c : t;
     return (d - e0) * sinvw;
 }
@@ -77,7 +79,7 @@ __device__ __forceinline__ PlanF plan_f32(double u0, double u1, double fl0, doub
     const double lo = __builtin_fmin(u0, u1), hi = __builtin_fmax(u0, u1);
     const double flo = __builtin_fmin(fl0, fl1), fhi = __builtin_fmax(fl0, fl1);
     const double len = hi - lo;
-    const double top = (double)(B - 1);
+    const double top = uni((double)(B - 1));
     if (len > 0.0) {
         const double f = __builtin_fmax(flo, 0.0);
         double l = __builtin_fmin(fhi, top);
@@ -232,23 +234,25 @@ __global__ __launch_bounds__(kPixelTile, 6) void pixels_f32_kernel(ScanArgs a, G
     double py, pz;
     pixel_key(g, f, pixel, py, pz);
     const int s = side ? -leading_sign(g, py, pz) : leading_sign(g, py, pz);
-    const double r = g.radius, sr = (double)s * g.radius;
-    const double e0 = g.first_center - g.width / 2.0;
+    // wave-uniform values through readfirstlane, so that they are held in
+    // scalar registers (the vector registers bound the kernel's occupancy)
+    const double r = uni(g.radius), sr = (double)s * g.radius, rr = uni(r * r);
+    const double e0 = uni(g.first_center - g.width / 2.0);
     const double invw = 1.0 / g.width;
-    const double c = f.c;
+    const double c = uni(f.c);
     const double u_first =
-        position_at<TILT>(g.wire_yz[0], g.wire_yz[1], py, pz, r, sr, c, e0, invw);
+        position_at<TILT>(g.wire_yz[0], g.wire_yz[1], py, pz, rr, sr, c, e0, invw);
     const double u_last = position_at<TILT>(g.wire_yz[2 * (N - 1)], g.wire_yz[2 * (N - 1) + 1],
-                                            py, pz, r, sr, c, e0, invw);
+                                            py, pz, rr, sr, c, e0, invw);
     const int dir = (u_last >= u_first) ? 1 : -1;
     const double sgn = (double)dir, sinvw = sgn * invw;
-    const double margin = g.pos_margin, half_in = 0.5 - margin;
+    const double margin = g.pos_margin, half_in = uni(0.5 - margin);
     FastPos fp;
     fp.py = py;
     fp.pz = pz;
     fp.sr = sr;
-    fp.mrr = -(r * r);
-    fp.srrr = sr * (r * r);
+    fp.mrr = uni(-rr);
+    fp.srrr = sr * rr;
     fp.scale = TILT ? sinvw / c : sinvw;
     fp.offs = -e0 * sinvw;
     const int off = dir > 0 ? 0 : B;
@@ -386,7 +390,7 @@ __global__ __launch_bounds__(kPixelTile, 6) void pixels_f32_kernel(ScanArgs a, G
         // fr within the margin of 0 or 1: the exact position
         bool zero_int = false;
         if (!(__builtin_fabs(fr - 0.5) < half_in)) {
-            v_next = position_at<TILT>(cy, cz, py, pz, r, sr, c, e0, sinvw);
+            v_next = position_at<TILT>(cy, cz, py, pz, rr, sr, c, e0, sinvw);
             fl = __builtin_floor(v_next);
             // a zero-length step of a falling walk is a point mass in bin
             // floor(u), which is floor(v)'s bin unless u is an integer (then
