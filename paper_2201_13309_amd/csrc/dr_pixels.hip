@@ -177,8 +177,9 @@ __device__ __forceinline__ int wave_min(int v)
 // two-edge reconstruction (ADD), whose values are added onto the first
 // pass's.  Values are scaled (by +-1 or +-1/2, exactly) as they are stored.
 template <int PF, bool NORM, bool TILT, bool ADD>
-// Six waves per SIMD (at most 80 VGPRs; the compiler spills one register of
-// the main instance): 7% faster than five.
+// Six waves per SIMD (at most 80 VGPRs; the main instance needs 77, with the
+// wave-uniform values in scalar registers): 7% faster than five; seven (72)
+// spill inside the step loop and are slower.
 __global__ __launch_bounds__(kPixelTile, 6) void pixels_f32_kernel(ScanArgs a, GeomArgs g, int side,
                                                                 float scale, ListArgs l)
 {
