@@ -122,6 +122,16 @@ static_assert(kPixelPartialRows == kPixelWaves + 1, "a partial row per wave, one
 constexpr int kRingBins = 16;
 constexpr size_t kRingBytes = (size_t)kPixelWaves * kRingBins * 64 * sizeof(float);
 
+// Prefetch depth PF of the FP32 per-pixel kernel; a block of steps between
+// two flushes of the ring is PF + 1 steps, within which a lane's fast steps
+// move it by at most PF + 1 bins.  Twelve-step blocks where the registers
+// allow it (the instances without step weights and axis tilt: 1.6% faster
+// than nine); nine where the weights or the tilted axis's division need the
+// registers (twelve spill there and are slower).
+constexpr int pixel_pf(bool norm, bool tilt) { return (norm || tilt) ? 8 : 11; }
+static_assert(pixel_pf(false, false) + 1 < kRingBins && pixel_pf(true, true) + 1 < kRingBins,
+              "a block of steps fits the ring's window");
+
 // v from the DPP source lane; lanes without one (or in rows outside ROW_MASK)
 // keep their own v
 template <int CTRL, int ROW_MASK>
@@ -177,9 +187,9 @@ __device__ __forceinline__ int wave_min(int v)
 // two-edge reconstruction (ADD), whose values are added onto the first
 // pass's.  Values are scaled (by +-1 or +-1/2, exactly) as they are stored.
 template <int PF, bool NORM, bool TILT, bool ADD>
-// Six waves per SIMD (at most 80 VGPRs; the main instance needs 77, with the
-// wave-uniform values in scalar registers): 7% faster than five; seven (72)
-// spill inside the step loop and are slower.
+// Six waves per SIMD (at most 80 VGPRs, all of them used by the main
+// instance, with the wave-uniform values in scalar registers): 7% faster than
+// five; seven (72) spill inside the step loop and are slower.
 __global__ __launch_bounds__(kPixelTile, 6) void pixels_f32_kernel(ScanArgs a, GeomArgs g, int side,
                                                                 float scale, ListArgs l)
 {
@@ -640,8 +650,8 @@ static hipError_t launch_pixels(const ScanArgs& a, const GeomArgs& g, int side, 
         switch (v) {
 #define DR_PIX(V, NORM, TILT, ADD)                                                              \
     case V:                                                                                     \
-        hipLaunchKernelGGL((pixels_f32_kernel<8, NORM, TILT, ADD>), grid, block, lds, s, a, g,  \
-                           side, sc, la);                                                       \
+        hipLaunchKernelGGL((pixels_f32_kernel<pixel_pf(NORM, TILT), NORM, TILT, ADD>), grid,    \
+                           block, lds, s, a, g, side, sc, la);                                  \
         break;
             DR_PIX(0, false, false, false)
             DR_PIX(1, true, false, false)
