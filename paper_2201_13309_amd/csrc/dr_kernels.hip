@@ -129,6 +129,25 @@ __device__ __forceinline__ double column_sum(const T* part, int64_t sl, int64_t 
     return s;
 }
 
+// Sum of column b of work[rows][B], rows added in order 0, 1, ...; sixteen
+// rows' loads are issued before their adds (a loop of one load and one add
+// waits out a full memory latency per row: these kernels run on a handful of
+// workgroups).
+__device__ __forceinline__ double rows_in_order(const double* work, int rows, int B, int b)
+{
+    double s = 0.0;
+    int r = 0;
+    for (; r + 16 <= rows; r += 16) {
+        double v[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = work[(int64_t)(r + i) * B + b];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) s += v[i];
+    }
+    for (; r < rows; ++r) s += work[(int64_t)r * B + b];
+    return s;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void totals_stage1(const T* part, int64_t slots, int B,
                                                      double* work)
@@ -176,9 +195,7 @@ __global__ __launch_bounds__(256) void totals_multi_stage2(const TotalsJob* jobs
     const TotalsJob& jb = jobs[find_job(jobs, n, (int)blockIdx.x, true)];
     const int b = ((int)blockIdx.x - jb.first2) * 256 + threadIdx.x;
     if (b >= jb.n_bins) return;
-    double s = 0.0;
-    for (int r = 0; r < rows; ++r) s += jb.work[(int64_t)r * jb.n_bins + b];
-    jb.totals[b] = (float)s;
+    jb.totals[b] = (float)rows_in_order(jb.work, rows, jb.n_bins, b);
 }
 
 // Column sums of an FP64 output [B][P] in a fixed order: block (b, chunk)
@@ -206,9 +223,7 @@ __global__ __launch_bounds__(256) void totals_stage2(const double* work, int row
 {
     const int b = blockIdx.x * 256 + threadIdx.x;
     if (b >= B) return;
-    double s = 0.0;
-    for (int r = 0; r < rows; ++r) s += work[(int64_t)r * B + b];
-    tot[b] = (T)s;
+    tot[b] = (T)rows_in_order(work, rows, B, b);
 }
 
 // ------------------------------------------------------------------- debug
