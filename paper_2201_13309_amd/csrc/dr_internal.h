@@ -200,6 +200,7 @@ constexpr size_t kPixelLdsBytes = 64 * 1024;
 struct SelectState {
     uint64_t prefix, mask;
     int64_t need, above;
+    unsigned long long bits;  // OR of all keys: digits above its top bit are 0 in every key
     unsigned long long hist[256];
 };
 constexpr int64_t kSelectBlock = 4096;  // keys per workgroup of the selection scan

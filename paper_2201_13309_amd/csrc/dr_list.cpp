@@ -207,14 +207,15 @@ dr_status dr_select_top(dr_geom g, const uint64_t* activity_dev, int64_t k, dr_l
     if (st != DR_OK) return st;
     std::unique_ptr<dr_list_s> own(l);
     {
-        // selection state and block sums in one buffer; build_tiles reads the
-        // list back on the same stream (and waits), so the kernels are done
-        // before the buffer is freed
-        DevBuf scratch;
+        // selection state and block sums in the geometry's buffer (kept
+        // between calls), held under its lock; build_tiles reads the list
+        // back on the same stream and waits, so the kernels are done before
+        // the lock is released
+        std::lock_guard<std::mutex> lk(g->mu);
         if (k > 0) {
             const size_t nb = (size_t)((npix + kSelectBlock - 1) / kSelectBlock);
-            DR_HIP(scratch.reserve(up256(sizeof(SelectState)) + nb * sizeof(uint64_t)));
-            char* base = scratch.as<char>();
+            DR_HIP(g->sel.reserve(up256(sizeof(SelectState)) + nb * sizeof(uint64_t)));
+            char* base = g->sel.as<char>();
             DR_HIP(launch_select_top(activity_dev, npix, k, (SelectState*)base,
                                      (uint64_t*)(base + up256(sizeof(SelectState))),
                                      l->pixels.as<int64_t>(), s));

@@ -91,6 +91,7 @@ struct dr_geom_s {
     // pixel centres; plan[p]: all plan tables of pass p in one allocation
     dr::DevBuf wire, pix, plan[2];
     dr::DevBuf part32, part64, work;
+    dr::DevBuf sel;  // dr_select_top's state and block sums, kept between calls
     std::mutex mu;
     bool forced = false, tuned = false;
     dr::TileCfg tile{0, 0, 0};

@@ -9,7 +9,9 @@
 //   activity_kernel    one pass over the stack, 8 pixels per lane (16-byte
 //                      loads) when aligned; HBM-bound.
 //   select_hist/pick   radix select of the k-th largest activity, 8 bits per
-//                      pass from the top, with the state kept on the device.
+//                      pass from the top, with the state kept on the device;
+//                      digits above the top bit of the OR of all keys
+//                      (select_or) are 0 in every key and are skipped.
 //   select_reduce /    two-level scan of the packed counts (greater, equal)
 //   scan / scatter     and a scatter of the selected indices in index order.
 #include "dr_device.h"
@@ -50,7 +52,33 @@ __global__ void select_init_kernel(SelectState* st, int64_t k)
         st->mask = 0;
         st->need = k;
         st->above = 0;
+        st->bits = 0;
     }
+}
+
+// OR of all keys into st->bits
+__global__ __launch_bounds__(256) void select_or_kernel(const uint64_t* act, int64_t npix,
+                                                        SelectState* st)
+{
+    __shared__ unsigned long long red;
+    if (threadIdx.x == 0) red = 0;
+    __syncthreads();
+    unsigned long long v = 0;
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < npix;
+         p += (int64_t)gridDim.x * 256)
+        v |= act[p];
+    if (v) atomicOr(&red, v);
+    __syncthreads();
+    if (threadIdx.x == 0 && red) atomicOr(&st->bits, red);
+}
+
+// Digit `shift` is 0 in every key when no key has a bit at or above it: its
+// pass would find every remaining key in bucket 0 and leave the state as it
+// is (the prefix keeps a 0 there, the count above and the need do not move),
+// so it is skipped.
+__device__ __forceinline__ bool digit_empty(const SelectState* st, int shift)
+{
+    return (st->bits >> shift) == 0;
 }
 
 // histogram of digit `shift` over the keys that match the selected prefix
@@ -58,6 +86,7 @@ __global__ __launch_bounds__(256) void select_hist_kernel(const uint64_t* act, i
                                                           int shift, SelectState* st)
 {
     __shared__ unsigned int h[256];
+    if (digit_empty(st, shift)) return;  // the same for every thread
     h[threadIdx.x] = 0;
     __syncthreads();
     const uint64_t prefix = st->prefix, mask = st->mask;
@@ -70,26 +99,33 @@ __global__ __launch_bounds__(256) void select_hist_kernel(const uint64_t* act, i
     if (h[threadIdx.x]) atomicAdd(&st->hist[threadIdx.x], (unsigned long long)h[threadIdx.x]);
 }
 
-// the digit bucket, from the top, that holds the need-th largest key
-__global__ void select_pick_kernel(int shift, SelectState* st)
+// The digit bucket, from the top, that holds the need-th largest key: thread
+// t holds bucket 255 - t, and an inclusive scan over t counts the keys in the
+// buckets from the top down to it; the one thread whose bucket takes the
+// count from below need to need or more (exactly one: the keys that match the
+// prefix number need or more) records the bucket and the keys above it.
+__global__ __launch_bounds__(256) void select_pick_kernel(int shift, SelectState* st)
 {
     __shared__ unsigned long long h[256];
-    const int t = threadIdx.x;
-    h[t] = st->hist[t];
+    if (digit_empty(st, shift)) return;  // the same for every thread
+    const int t = threadIdx.x, b = 255 - t;
+    const unsigned long long c = st->hist[b];
+    const unsigned long long need = (unsigned long long)st->need;
+    h[t] = c;
     __syncthreads();
-    st->hist[t] = 0;
-    if (t == 0) {
-        unsigned long long cum = 0;
-        for (int b = 255; b >= 0; --b) {
-            if (cum + h[b] >= (unsigned long long)st->need) {
-                st->prefix |= (uint64_t)b << shift;
-                st->mask |= (uint64_t)255 << shift;
-                st->above += (int64_t)cum;
-                st->need -= (int64_t)cum;
-                break;
-            }
-            cum += h[b];
-        }
+    for (int w = 1; w < 256; w <<= 1) {  // inclusive Hillis-Steele scan
+        const unsigned long long x = t >= w ? h[t - w] : 0;
+        __syncthreads();
+        h[t] += x;
+        __syncthreads();
+    }
+    const unsigned long long incl = h[t], excl = incl - c;
+    st->hist[b] = 0;
+    if (excl < need && incl >= need) {
+        st->prefix |= (uint64_t)b << shift;
+        st->mask |= (uint64_t)255 << shift;
+        st->above += (int64_t)excl;
+        st->need -= (int64_t)excl;
     }
 }
 
@@ -240,6 +276,7 @@ hipError_t launch_select_top(const uint64_t* act, int64_t npix, int64_t k, Selec
 {
     hipLaunchKernelGGL(select_init_kernel, dim3(1), dim3(256), 0, s, st, k);
     const unsigned hist_groups = (unsigned)std::min<int64_t>(1024, (npix + 255) / 256);
+    hipLaunchKernelGGL(select_or_kernel, dim3(hist_groups), dim3(256), 0, s, act, npix, st);
     for (int shift = 56; shift >= 0; shift -= 8) {
         hipLaunchKernelGGL(select_hist_kernel, dim3(hist_groups), dim3(256), 0, s, act, npix,
                            shift, st);

@@ -111,7 +111,10 @@ def test_select_top_matches_rule(dr, ctx):
         acts = [rng.integers(0, 4, npix).astype(np.uint64),           # heavy ties
                 rng.integers(0, 1 << 62, npix).astype(np.uint64),     # every radix digit
                 np.zeros(npix, dtype=np.uint64),                      # all equal
-                (rng.integers(0, 3, npix).astype(np.uint64) << np.uint64(40)) + np.uint64(7)]
+                (rng.integers(0, 3, npix).astype(np.uint64) << np.uint64(40)) + np.uint64(7),
+                # the top bit (keys compare unsigned; no digit is 0 in every key)
+                (rng.integers(0, 2, npix).astype(np.uint64) << np.uint64(63))
+                | rng.integers(0, 8, npix).astype(np.uint64)]
         for act in acts:
             for k in (0, 1, 2, 100, 341, 512, npix - 1, npix):
                 got = _select(dr, g, act, k)
