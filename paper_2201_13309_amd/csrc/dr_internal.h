@@ -205,10 +205,10 @@ struct SelectState {
 };
 constexpr int64_t kSelectBlock = 4096;  // keys per workgroup of the selection scan
 
-// pixel activity sum_k |I_k - I_{k+1}| of a full stack [N][npix]; vec8: 16-byte
-// loads (img 16-byte aligned and npix % 8 == 0)
+// pixel activity sum_k |I_k - I_{k+1}| of a full stack [N][npix]; vec4: 8-byte
+// loads of 4 pixels (img 8-byte aligned and npix % 4 == 0)
 hipError_t launch_activity(const uint16_t* img, int64_t npix, int n_steps, uint64_t* act,
-                           bool vec8, hipStream_t s);
+                           bool vec4, hipStream_t s);
 // the k (1 <= k <= npix) largest activities, ties to the lower index, as an
 // increasing index list; bsum holds ceil(npix / kSelectBlock) entries
 hipError_t launch_select_top(const uint64_t* act, int64_t npix, int64_t k, SelectState* st,

@@ -187,8 +187,8 @@ dr_status dr_pixel_activity(dr_geom g, const uint16_t* images_dev, uint64_t* act
         return set_error(DR_E_INVAL, "dr_pixel_activity: misaligned buffer");
     DR_HIP(hipSetDevice(g->ctx->device));
     const int64_t npix = (int64_t)g->nx * g->ny;
-    const bool vec8 = aligned_to(images_dev, 16) && npix % 8 == 0;
-    DR_HIP(launch_activity(images_dev, npix, g->n_steps, activity_dev, vec8, (hipStream_t)stream));
+    const bool vec4 = aligned_to(images_dev, 8) && npix % 4 == 0;
+    DR_HIP(launch_activity(images_dev, npix, g->n_steps, activity_dev, vec4, (hipStream_t)stream));
     set_error(DR_OK, "");
     return DR_OK;
 }

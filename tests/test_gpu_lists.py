@@ -57,6 +57,8 @@ def make_case(name):
         s.detector = synth.Detector(d.nx, d.ny, d.origin, np.array([200.0, 15.0, 35.0]), d.v)
         synth.render(s)
         return s
+    if name == "short_scan":    # fewer steps than the activity kernel's ring of loads
+        return synth.tiny(64, 5, 9, 21, seed=308, n_src=4, dark=100.0)
     if name == "both_tilted":
         s = make_case("tilted")
         s.grid = synth.DepthGrid(81, -72.0 + 0.6, 1.2)
@@ -79,13 +81,14 @@ def _activity(dr, g, images, offset=0):
     return act.cpu().numpy().view(np.uint64)
 
 
-@pytest.mark.parametrize("name", ["rows", "rows_noise_free", "tilted"])
+@pytest.mark.parametrize("name", ["rows", "rows_noise_free", "tilted", "short_scan"])
 def test_activity_exact(dr, ctx, name):
     s = make_case(name)
     ref = oracle.activity(s.images)
     g = dr.dr_geometry_init(ctx, s.detector, s.wire, s.grid)
     try:
-        for off in (0, 1, 8):  # 16-byte aligned (vector loads when nx*ny % 8 == 0) or not
+        # 8-byte aligned (vector loads when nx*ny % 4 == 0: offsets 0, 4, 8) or not (1)
+        for off in (0, 1, 4, 8):
             assert np.array_equal(_activity(dr, g, s.images, off), ref), off
     finally:
         dr.dr_geometry_free(g)
